@@ -1,0 +1,389 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics
+(not against the oracle itself).
+
+P1  compressed per-row form (Sec. V) reproduces the literal check rule
+P2  single-scan (Sec. IV) equals two-scan (Sec. III) message for message
+P3  the 1-bit form (Sec. V) equals single-scan
+P4  on cycle-free graphs plain min-sum gives the brute-force max-log LLR
+P5  noiseless inputs are fixed points (hand-derived sequence in fixed point)
+P6  single parity-check code: closed form after one iteration, stationary
+P7  scale invariance of plain/normalised min-sum (Sec. II remark on Z^(0)=y)
+P8  codeword symmetry
+P9  the syndrome flag matches H x^T = 0 computed independently
+plus the hand-computed golden example under tests/golden/.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_cs_0609090_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _tiny_code():
+    g = json.load(open(os.path.join(GOLDEN, "tiny3x6.json")))
+    return g, W.ParityCheck.from_rows(len(g["H_rows"]), g["N"], g["H_rows"], "tiny3x6")
+
+
+# --------------------------------------------------------------------------
+# golden hand-computed example
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("algo", ["two_scan", "single_scan", "one_bit"])
+def test_golden_tiny_int(orc, algo):
+    g, code = _tiny_code()
+    for case in g["cases"]:
+        if case["arith"] != "int":
+            continue
+        llr = np.array([case["llr_steps"]], dtype=np.int8)
+        r = orc.decode(code, llr, algo=algo, arith="int", max_iter=2, alpha=case["alpha"],
+                       beta=case["beta"], early_stop=False, step=case["step"], trace=True)
+        assert r["L"][0, 0].tolist() == case["iter1_L_csr"], case["name"]
+        assert r["Z"][0, 0].tolist() == case["iter1_Z_steps"], case["name"]
+        assert r["L"][0, 1].tolist() == case["iter2_L_csr"], case["name"]
+        assert r["Z"][0, 1].tolist() == case["iter2_Z_steps"], case["name"]
+        np.testing.assert_array_equal(r["post"][0], np.array(case["iter2_Z_steps"]) * case["step"])
+        if "iter2_hard" in case:
+            assert r["hard"][0].tolist() == case["iter2_hard"]
+            assert int(r["ok"][0]) == case["iter2_syndrome_ok"]
+            assert int(r["iters"][0]) == 2
+            r2 = orc.decode(code, llr, algo=algo, arith="int", max_iter=2, alpha=case["alpha"],
+                            beta=case["beta"], early_stop=True, step=case["step"])
+            assert int(r2["iters"][0]) == case["early_stop_iters"]
+            assert int(r2["ok"][0]) == 1
+            np.testing.assert_array_equal(r2["post"][0], np.array(case["iter1_Z_steps"]) * case["step"])
+
+
+@pytest.mark.parametrize("algo", ["two_scan", "single_scan", "one_bit"])
+@pytest.mark.parametrize("arith", ["f32", "f64"])
+def test_golden_tiny_float(orc, algo, arith):
+    g, code = _tiny_code()
+    case = [c for c in g["cases"] if c["arith"] == "f64"][0]
+    llr = np.array([case["llr"]], dtype=np.float32)
+    r = orc.decode(code, llr, algo=algo, arith=arith, max_iter=2, alpha=case["alpha"],
+                   beta=case["beta"], early_stop=False, trace=True)
+    assert r["L"][0, 0].tolist() == case["iter1_L_csr"]
+    assert r["Z"][0, 0].tolist() == case["iter1_Z"]
+    assert r["L"][0, 1].tolist() == case["iter2_L_csr"]
+    assert r["Z"][0, 1].tolist() == case["iter2_Z"]
+
+
+def test_max_iter_zero_returns_channel_decisions(orc):
+    _, code = _tiny_code()
+    llr = np.array([[5, -3, 8, 0, -1, 7]], dtype=np.int8)
+    for algo in orc.ALGOS:
+        r = orc.decode(code, llr, algo=algo, arith="int", max_iter=0)
+        assert r["iters"].tolist() == [0]
+        assert r["hard"][0].tolist() == [0, 1, 0, 1, 1, 0]  # Z=0 decides 1
+        np.testing.assert_array_equal(r["post"][0], llr[0] * 0.5)
+        assert r["ok"][0] == (code.syndrome(r["hard"][0]).sum() == 0)
+
+
+# --------------------------------------------------------------------------
+# P1: per-row compression (Sec. V observation) against the literal rule
+# --------------------------------------------------------------------------
+def test_p1_row_compression_roundtrip(orc):
+    rng = np.random.default_rng(1)
+    for trial in range(3000):
+        d = int(rng.integers(2, 24))
+        t = rng.integers(-31, 32, size=d)
+        if trial % 3 == 0:  # many ties
+            t = rng.choice([-31, -4, 0, 4, 31], size=d)
+        alpha = [1.0, 0.8, 0.75, 0.5][trial % 4]
+        beta = [0.0, 0.5, 1.0][trial % 3]
+        L = orc.row_update_int(t, alpha, beta)
+        # all |L| equal except at most one position (the argmin of |t|)
+        mags = np.abs(L)
+        assert len(set(mags.tolist())) <= 2
+        A, B, idx, s = orc.compress_row_int(L)
+        np.testing.assert_array_equal(orc.expand_row_int(d, A, B, idx, s), L)
+        # sign of every non-zero message times own sign = product of all signs
+        total = np.prod(np.where(t < 0, -1, 1))
+        own = np.where(t < 0, -1, 1)
+        nz = L != 0
+        np.testing.assert_array_equal(np.sign(L[nz]) * own[nz], np.full(nz.sum(), total))
+        # plain min-sum magnitudes are order statistics of |t|
+        if alpha == 1.0 and beta == 0.0:
+            srt = np.sort(np.abs(t))
+            assert mags.min() == srt[0] and mags.max() == srt[1]
+            assert mags[int(np.argmin(np.abs(t)))] == srt[1]
+
+
+# --------------------------------------------------------------------------
+# P2 / P3: single-scan == two-scan == 1-bit, message for message
+# --------------------------------------------------------------------------
+def _rand_codes(n, seed):
+    rng = np.random.default_rng(seed)
+    for i in range(n):
+        M = int(rng.integers(3, 12))
+        N = int(rng.integers(M + 2, 2 * M + 6))
+        yield W.random_small_code(M, N, (2, min(7, N)), seed=seed * 1000 + i)
+
+
+@pytest.mark.parametrize("alpha,beta", [(1.0, 0.0), (0.8, 0.0), (0.8, 0.5), (1.0, 1.0), (0.625, 0.5)])
+def test_p2_p3_int_message_for_message(orc, alpha, beta):
+    rng = np.random.default_rng(int(alpha * 100 + beta * 10))
+    for code in _rand_codes(25, int(alpha * 1000 + beta * 100)):
+        llr = rng.integers(-31, 32, size=(3, code.N)).astype(np.int8)
+        kw = dict(arith="int", max_iter=8, alpha=alpha, beta=beta, early_stop=False, trace=True)
+        ts = orc.decode(code, llr, algo="two_scan", **kw)
+        ss = orc.decode(code, llr, algo="single_scan", **kw)
+        ob = orc.decode(code, llr, algo="one_bit", **kw)
+        np.testing.assert_array_equal(ts["L"], ss["L"])
+        np.testing.assert_array_equal(ts["Z"], ss["Z"])
+        np.testing.assert_array_equal(ob["L"], ss["L"])
+        np.testing.assert_array_equal(ob["Z"], ss["Z"])
+        # two-scan Z_mn equals the single-scan extrinsic sat(Z_n - L_mn)
+        zn_e = ss["Z"][:, :, code.col_idx]
+        np.testing.assert_array_equal(ts["Zmn"], np.clip(zn_e - ss["L"], -31, 31))
+        for k in ("post", "hard", "iters", "ok"):
+            np.testing.assert_array_equal(ts[k], ss[k])
+            np.testing.assert_array_equal(ob[k], ss[k])
+
+
+@pytest.mark.parametrize("alpha", [1.0, 0.75, 0.5])
+def test_p2_f64_dyadic_exact(orc, alpha):
+    """With dyadic inputs and dyadic alpha every quantity is exact in binary64,
+    so two-scan and single-scan agree bit for bit."""
+    rng = np.random.default_rng(7)
+    for code in _rand_codes(20, 77):
+        llr = (rng.integers(-64, 65, size=(2, code.N)) / 8.0).astype(np.float32)
+        kw = dict(arith="f64", max_iter=10, alpha=alpha, beta=0.0, early_stop=False, trace=True)
+        ts = orc.decode(code, llr, algo="two_scan", **kw)
+        ss = orc.decode(code, llr, algo="single_scan", **kw)
+        np.testing.assert_array_equal(ts["L"], ss["L"])
+        np.testing.assert_array_equal(ts["Z"], ss["Z"])
+        np.testing.assert_array_equal(ts["Zmn"], ss["Z"][:, :, code.col_idx] - ss["L"])
+
+
+@pytest.mark.parametrize("arith", ["f32", "f64"])
+def test_p3_float_one_bit_equals_single_scan(orc, arith):
+    rng = np.random.default_rng(11)
+    for code in _rand_codes(20, 5):
+        llr = rng.normal(1.0, 2.0, size=(3, code.N)).astype(np.float32)
+        kw = dict(arith=arith, max_iter=12, alpha=0.8, beta=0.15, early_stop=False, trace=True)
+        ss = orc.decode(code, llr, algo="single_scan", **kw)
+        ob = orc.decode(code, llr, algo="one_bit", **kw)
+        np.testing.assert_array_equal(ob["L"], ss["L"])
+        np.testing.assert_array_equal(ob["Z"], ss["Z"])
+
+
+def test_p2_f32_close_to_two_scan(orc):
+    """In binary32 Z_n - L_mn and the exclusion sum round differently; the two
+    forms must still agree to a few ulps of the summed magnitudes."""
+    rng = np.random.default_rng(3)
+    for code in _rand_codes(15, 9):
+        llr = rng.normal(1.0, 2.0, size=(2, code.N)).astype(np.float32)
+        kw = dict(arith="f32", max_iter=3, alpha=0.8, beta=0.0, early_stop=False, trace=True)
+        ts = orc.decode(code, llr, algo="two_scan", **kw)
+        ss = orc.decode(code, llr, algo="single_scan", **kw)
+        scale = np.abs(llr).max() * 40
+        np.testing.assert_allclose(ts["Z"], ss["Z"], rtol=0, atol=scale * 1e-6)
+
+
+def test_p2_int_on_peg1008_sample(orc):
+    code = W.code_c0_peg1008()
+    llr = W.quantize_llr(W.awgn_llr(code.N, 4, 2.0, code.design_rate, key=(1, 2)))
+    kw = dict(arith="int", max_iter=20, alpha=0.8, beta=0.0, early_stop=False, trace=True)
+    ts = orc.decode(code, llr, algo="two_scan", **kw)
+    ss = orc.decode(code, llr, algo="single_scan", **kw)
+    ob = orc.decode(code, llr, algo="one_bit", **kw)
+    np.testing.assert_array_equal(ts["L"], ss["L"])
+    np.testing.assert_array_equal(ob["L"], ss["L"])
+    np.testing.assert_array_equal(ts["Z"], ss["Z"])
+
+
+# --------------------------------------------------------------------------
+# P4: trees -- min-sum = max-log brute force over all codewords
+# --------------------------------------------------------------------------
+def _maxlog_bruteforce(code, lam):
+    H = code.dense()
+    N = code.N
+    words = np.array(list(itertools.product([0, 1], repeat=N)), dtype=np.uint8)
+    cws = words[(H @ words.T % 2).sum(axis=0) == 0]
+    score = ((1 - 2 * cws.astype(np.float64)) * lam).sum(axis=1)
+    out = np.zeros(N)
+    for n in range(N):
+        out[n] = 0.5 * (score[cws[:, n] == 0].max() - score[cws[:, n] == 1].max())
+    return out
+
+
+@pytest.mark.parametrize("algo", ["two_scan", "single_scan", "one_bit"])
+def test_p4_tree_maxlog(orc, algo):
+    rng = np.random.default_rng(21)
+    checked = 0
+    for seed in range(60):
+        code = W.tree_code(int(rng.integers(1, 5)), 4, seed)
+        if code.N > 11:
+            continue
+        lam = rng.normal(0.5, 2.0, size=code.N).astype(np.float32)
+        r = orc.decode(code, lam[None, :], algo=algo, arith="f64", max_iter=2 * code.M + 2,
+                       alpha=1.0, beta=0.0, early_stop=False)
+        ref = _maxlog_bruteforce(code, lam.astype(np.float64))
+        np.testing.assert_allclose(r["post"][0], ref, rtol=0, atol=1e-9)
+        checked += 1
+    assert checked >= 30
+
+
+# --------------------------------------------------------------------------
+# P5: noiseless fixed point
+# --------------------------------------------------------------------------
+def test_p5_regular_fixed_point_sequence(orc):
+    """(3,6)-regular code, all-zero word, Z0 = 6 steps, alpha = 0.8: by hand,
+    L = 5, 13, 25, 25, ... so Z = 6+3L = 21, 45, 81, 81, ..."""
+    code = W.code_c0_peg1008()
+    llr = np.full((1, code.N), 6, dtype=np.int8)
+    for algo in ("two_scan", "single_scan", "one_bit"):
+        r = orc.decode(code, llr, algo=algo, arith="int", max_iter=6, alpha=0.8,
+                       early_stop=False, trace=True)
+        seq = r["Z"][0, :, 0].tolist()
+        assert seq == [21, 45, 81, 81, 81, 81], algo
+        assert np.all(r["Z"][0] == r["Z"][0, :, :1])
+        assert r["hard"].sum() == 0 and r["ok"][0] == 1
+        r2 = orc.decode(code, llr, algo=algo, arith="int", max_iter=6, alpha=0.8, early_stop=True)
+        assert r2["iters"][0] == 1 and r2["ok"][0] == 1
+
+
+@pytest.mark.parametrize("arith", ["int", "f32", "f64"])
+def test_p5_codeword_is_fixed_point(orc, arith):
+    rng = np.random.default_rng(5)
+    for code in _rand_codes(10, 31):
+        basis = W.gf2_nullspace_basis(code.dense())
+        if basis.shape[0] == 0:
+            continue
+        c = (rng.integers(0, 2, size=basis.shape[0]) @ basis) % 2
+        a = 9
+        llr = (a * (1 - 2 * c.astype(np.int64)))[None, :]
+        llr = llr.astype(np.int8 if arith == "int" else np.float32)
+        for algo in orc.ALGOS:
+            r = orc.decode(code, llr, algo=algo, arith=arith, max_iter=7, alpha=0.8,
+                           beta=0.0, early_stop=False, trace=True)
+            for k in range(7):
+                np.testing.assert_array_equal((r["Z"][0, k] <= 0).astype(np.uint8), c)
+            assert r["ok"][0] == 1
+            r2 = orc.decode(code, llr, algo=algo, arith=arith, max_iter=7, alpha=0.8,
+                            early_stop=True)
+            assert r2["iters"][0] == 1
+
+
+# --------------------------------------------------------------------------
+# P6: single parity-check code
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("arith", ["int", "f64"])
+def test_p6_single_parity_check(orc, arith):
+    rng = np.random.default_rng(6)
+    for d in range(2, 12):
+        code = W.ParityCheck.from_rows(1, d, [list(range(d))])
+        if arith == "int":
+            z0 = rng.integers(-31, 32, size=d)
+            llr = z0.astype(np.int8)[None, :]
+            alpha, beta = 0.8, 0.5
+            a8, b = 205, 1
+
+            def norm(m):
+                return max(((m * a8 + 128) >> 8) - b, 0)
+        else:
+            z0 = rng.normal(0, 3, size=d).astype(np.float32).astype(np.float64)
+            llr = z0.astype(np.float32)[None, :]
+            alpha, beta = 0.75, 0.25
+
+            def norm(m):
+                return max(alpha * m - beta, 0.0)
+        expect = np.zeros(d)
+        for n in range(d):
+            others = np.delete(z0, n)
+            sgn = np.prod(np.where(others < 0, -1, 1))
+            expect[n] = z0[n] + sgn * norm(np.abs(others).min())
+        for algo in orc.ALGOS:
+            r = orc.decode(code, llr, algo=algo, arith=arith, max_iter=4, alpha=alpha,
+                           beta=beta, early_stop=False, trace=True)
+            for k in range(4):
+                np.testing.assert_array_equal(r["Z"][0, k], expect)
+
+
+# --------------------------------------------------------------------------
+# P7: scale invariance; P8: codeword symmetry; P9: syndrome flag
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("arith", ["f32", "f64"])
+def test_p7_scale_invariance(orc, arith):
+    rng = np.random.default_rng(8)
+    for code in _rand_codes(12, 41):
+        llr = rng.normal(1.0, 2.0, size=(2, code.N)).astype(np.float32)
+        for s in (-3, 1, 5):
+            for algo in orc.ALGOS:
+                a = orc.decode(code, llr, algo=algo, arith=arith, max_iter=9, alpha=0.8,
+                               early_stop=False)
+                b = orc.decode(code, (llr * 2.0 ** s).astype(np.float32), algo=algo,
+                               arith=arith, max_iter=9, alpha=0.8, early_stop=False)
+                np.testing.assert_array_equal(b["post"], a["post"] * 2.0 ** s)
+
+
+@pytest.mark.parametrize("arith", ["int", "f64"])
+def test_p8_codeword_symmetry(orc, arith):
+    rng = np.random.default_rng(9)
+    for code in _rand_codes(12, 51):
+        basis = W.gf2_nullspace_basis(code.dense())
+        if basis.shape[0] == 0:
+            continue
+        c = (rng.integers(0, 2, size=basis.shape[0]) @ basis) % 2
+        flip = 1 - 2 * c.astype(np.int64)
+        if arith == "int":
+            llr = rng.integers(-31, 32, size=(2, code.N))
+            l2 = (llr * flip).astype(np.int8)
+            llr = llr.astype(np.int8)
+        else:
+            llr = rng.normal(0.5, 2.0, size=(2, code.N)).astype(np.float32)
+            l2 = (llr * flip).astype(np.float32)
+        for algo in orc.ALGOS:
+            a = orc.decode(code, llr, algo=algo, arith=arith, max_iter=8, alpha=0.8,
+                           beta=0.5 if arith == "int" else 0.0, early_stop=False)
+            b = orc.decode(code, l2, algo=algo, arith=arith, max_iter=8, alpha=0.8,
+                           beta=0.5 if arith == "int" else 0.0, early_stop=False)
+            np.testing.assert_array_equal(b["post"], a["post"] * flip)
+            nz = a["post"] != 0
+            np.testing.assert_array_equal(b["hard"][nz], (a["hard"] ^ c)[nz])
+
+
+def test_p9_syndrome_flag(orc):
+    code = W.code_c0_peg1008()
+    llr = W.quantize_llr(W.awgn_llr(code.N, 24, 1.0, code.design_rate, key=(3, 4)))
+    for algo in orc.ALGOS:
+        for es in (False, True):
+            r = orc.decode(code, llr, algo=algo, arith="int", max_iter=15, alpha=0.8,
+                           early_stop=es)
+            ok = (code.syndrome(r["hard"]).sum(axis=1) == 0).astype(np.uint8)
+            np.testing.assert_array_equal(r["ok"], ok)
+            assert 0 < ok.sum() < 24  # a mix of decoded and failed frames at 1 dB
+            if es:
+                assert np.all(r["iters"][ok == 0] == 15)
+
+
+def test_one_bit_state_consistent(orc):
+    code = W.code_c0_peg1008()
+    llr = W.quantize_llr(W.awgn_llr(code.N, 2, 2.0, code.design_rate, key=(5, 6)))
+    r = orc.decode(code, llr, algo="one_bit", arith="int", max_iter=5, alpha=0.8,
+                   early_stop=False, trace=True, state=True)
+    A, B, idx = r["state"][..., 0], r["state"][..., 1], r["state"][..., 2]
+    assert np.all(A <= B) and np.all(A >= 0) and np.all(B <= 31)
+    L = r["L"][:, -1]
+    np.testing.assert_array_equal(r["signs"], (L < 0).astype(np.uint8))
+    for f in range(2):
+        for m in range(code.M):
+            lo, hi = code.row_ptr[m], code.row_ptr[m + 1]
+            mags = np.abs(L[f, lo:hi])
+            assert mags.min() == A[f, m] and mags.max() == B[f, m]
+            assert mags[idx[f, m]] == B[f, m]
+
+
+def test_oracle_rejects_bad_input(orc):
+    _, code = _tiny_code()
+    with pytest.raises(ValueError):
+        orc.decode(code, np.full((1, 6), 40, dtype=np.int8), arith="int")
+    with pytest.raises(ValueError):
+        orc.decode(code, np.zeros((1, 6), dtype=np.int8), arith="int", alpha=1.5)
+    bad = W.ParityCheck(1, 3, np.array([0, 1], dtype=np.int32), np.array([0], dtype=np.int32))
+    with pytest.raises(ValueError):
+        orc.decode(bad, np.zeros((1, 3), dtype=np.int8), arith="int")
