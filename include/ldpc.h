@@ -1,0 +1,169 @@
+/*
+ * ldpc.h -- C ABI of the single-scan min-sum LDPC decoder for AMD Instinct
+ * MI355X (gfx950).
+ *
+ * Method: X. Huang, "Single-Scan Min-Sum Algorithms for Fast Decoding of LDPC
+ * Codes", ITW 2006.  The library decodes binary LDPC codes with normalised /
+ * offset min-sum (Sec. III) in the single-scan form of Sec. IV (Eq. 3): each
+ * iteration is one pass over the check-to-variable addressing that rebuilds
+ * the variable-to-check message as Z_{n'} - L_{mn'} and accumulates the new
+ * posteriors Z_n in the same pass.  Messages can be 6-bit fixed point (int8),
+ * the compressed "1-bit" form of Sec. V (a sign bit per edge plus A_m, B_m and
+ * the position n~_m per check), or binary32.  The standard two-scan schedule
+ * (Sec. III, Eqs. 1-2) is available as a baseline.
+ *
+ * Conventions
+ *  - All functions are plain C, thread-safe for distinct handles, and return
+ *    an ldpc_status; on failure ldpc_last_error() gives a message (per thread).
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are GPU memory
+ *    on the device the code was created for (e.g. from hipMalloc or a torch
+ *    tensor).  The library never takes ownership of caller buffers.
+ *  - Layouts are row-major; [F][N] means frame-major, N contiguous values per
+ *    frame.
+ */
+#ifndef LDPC_H
+#define LDPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ldpc_code ldpc_code; /* opaque, owned by the library */
+
+typedef enum {
+    LDPC_OK = 0,
+    LDPC_EINVAL = 1,        /* bad argument (null pointer, range, size) */
+    LDPC_EBADCODE = 2,      /* parity-check matrix rejected */
+    LDPC_ENOMEM = 3,        /* device or host allocation failed */
+    LDPC_EDEVICE = 4,       /* HIP runtime error (launch, copy, device) */
+    LDPC_EUNSUPPORTED = 5   /* valid request with no kernel for it */
+} ldpc_status;
+
+/* Message representation (Sec. V uses b = 6..8 bit fixed point). */
+typedef enum {
+    LDPC_MSG_FP32 = 0, /* binary32 messages and posteriors */
+    LDPC_MSG_INT8 = 1, /* 6-bit fixed point held in int8, extrinsics saturated to +-31 */
+    LDPC_MSG_1BIT = 2  /* Sec. V: per-edge sign bit + per-check (A, B, n~), 6-bit values */
+} ldpc_msg;
+
+typedef enum {
+    LDPC_SINGLE_SCAN = 0, /* Sec. IV, Eq. (3) (and Sec. V for LDPC_MSG_1BIT) */
+    LDPC_TWO_SCAN = 1     /* Sec. III, Eqs. (1)-(2): baseline; FP32 and INT8 only */
+} ldpc_sched;
+
+/* flags */
+#define LDPC_F_CHECK_INPUT 0x1u /* validate llr_in on the device first (synchronises the stream) */
+#define LDPC_F_LAYOUT_SHIFT 8   /* bits 8..11: force a layout (LDPC_LAYOUT_*), 0 = automatic */
+#define LDPC_LAYOUT_AUTO 0
+#define LDPC_LAYOUT_LDS 1       /* messages in LDS (must fit) */
+#define LDPC_LAYOUT_HBM 2       /* messages in the caller's workspace (device memory) */
+
+/*
+ * Decoding parameters (Sec. III: normalisation lambda_k = alpha, offset
+ * beta_k = beta, both constant over iterations; iteration cap max_iter).
+ *  alpha      in (0, 1]; |L| = max(alpha * m - beta, 0) where m is the
+ *             check-node minimum (alpha = 1, beta = 0: plain min-sum).
+ *  beta       >= 0, in LLR units.
+ *  llr_step   LLR value of one fixed-point unit for INT8 / 1BIT (0.5 for the
+ *             6-bit range +-15.5).  Fixed point uses a8 = round(256 alpha),
+ *             b = round(beta / llr_step) (half away from zero) and
+ *             |L| = max(((m*a8 + 128) >> 8) - b, 0).
+ *  early_stop nonzero: stop a frame after the first iteration k >= 1 whose
+ *             hard decision satisfies H x^T = 0 (Sec. III decoding step).
+ */
+typedef struct {
+    int32_t max_iter;
+    float alpha;
+    float beta;
+    int32_t early_stop;
+    int32_t msg;   /* ldpc_msg */
+    int32_t sched; /* ldpc_sched */
+    float llr_step;
+    uint32_t flags;
+} ldpc_decode_params;
+
+/* Facts about a code handle and its planned device layouts. */
+typedef struct {
+    int32_t M, N;
+    int64_t E;                  /* nonzeros of H (edges of the Tanner graph) */
+    int32_t min_row_deg, max_row_deg, max_col_deg;
+    int32_t slots_per_row;      /* padded row width used on the device */
+    int32_t rows_padded;        /* rows rounded up to a multiple of 64 */
+    int32_t device;
+    int64_t addr_bytes_single;  /* check-to-variable addressing (all single-scan kernels) */
+    int64_t addr_bytes_two;     /* plus the variable-to-check index (two-scan, FP32 sum) */
+    int64_t msg_bits_int8;      /* b * E with b = 8 (int8 message store, Sec. V) */
+    int64_t msg_bits_1bit;      /* E sign bits + M * (5 + 5 + ceil(log2 d_c)) state bits */
+    int32_t lds_bytes_per_cu;   /* LDS available to one workgroup on this device */
+} ldpc_code_info;
+
+/*
+ * Create a code handle from a sparse parity-check matrix H (M x N over GF(2),
+ * Sec. II) in CSR form.
+ *  row_ptr  host, M+1 entries, row_ptr[0] = 0, nondecreasing, row_ptr[M] = nnz.
+ *  col_idx  host, nnz entries; row m lists N(m) in the order messages are
+ *           indexed inside the check (ties of the 1-bit argmax go to the first).
+ *  device   HIP device ordinal; the handle keeps its own device copies.  A
+ *           negative ordinal makes a host-only handle (no device memory, LDS
+ *           budget of one gfx950 CU) for queries and workspace sizing; decoding
+ *           with it returns LDPC_EINVAL.
+ * Rejected with LDPC_EBADCODE: a row of degree < 2 (the minimum over N(m)\n
+ * would be empty), a repeated column inside a row, an index outside [0, N).
+ * LDPC_EUNSUPPORTED: a row degree above 64.
+ */
+ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *row_ptr,
+                             const int32_t *col_idx, int32_t device, ldpc_code **out);
+
+/* Free a handle and its device memory.  NULL is accepted. */
+ldpc_status ldpc_code_destroy(ldpc_code *code);
+
+/* Fill *out with the facts above.  Host only. */
+ldpc_status ldpc_code_query(const ldpc_code *code, ldpc_code_info *out);
+
+/*
+ * Bytes of device workspace ldpc_decode_batch needs for n_frames frames with
+ * these parameters (0 when every per-frame state fits in LDS).
+ */
+ldpc_status ldpc_decode_workspace_size(const ldpc_code *code, int32_t n_frames,
+                                       const ldpc_decode_params *p, size_t *bytes);
+
+/*
+ * Decode n_frames frames (one parity-check matrix, Sec. III-V).
+ *  llr_in      device [F][N]: float32 channel LLRs Z^(0) for LDPC_MSG_FP32;
+ *              int8 fixed-point LLRs in [-31, 31] (units of llr_step) for INT8
+ *              and 1BIT (values outside are saturated).
+ *  hard_out    device [F][N] uint8: x_n = 0 if Z_n > 0 else 1.
+ *  llr_out     device [F][N] float32 posterior Z_n (fixed point: Z * llr_step,
+ *              exact); may be NULL.
+ *  iters_out   device [F] int32: iterations run (first k >= 1 whose decision is a
+ *              codeword when early_stop, else max_iter; 0 if max_iter == 0).
+ *  syndrome_ok device [F] uint8: 1 iff H x^T = 0 for the returned hard_out.
+ *  workspace   device, at least ldpc_decode_workspace_size() bytes, 256-byte
+ *              aligned; may be NULL when that size is 0.
+ *  stream      hipStream_t (NULL = default stream).
+ * The call is asynchronous on `stream`, allocates nothing and never
+ * synchronises (except with LDPC_F_CHECK_INPUT).  Each frame's result depends
+ * only on its own input.  max_iter = 0 returns the channel decisions.
+ * Errors: LDPC_EINVAL for n_frames < 0, max_iter < 0, alpha outside (0, 1],
+ * beta < 0, llr_step <= 0, a required NULL pointer or a small workspace;
+ * LDPC_EUNSUPPORTED for LDPC_TWO_SCAN with LDPC_MSG_1BIT or a forced layout
+ * that does not fit; LDPC_EDEVICE for a failed launch.
+ */
+ldpc_status ldpc_decode_batch(const ldpc_code *code, int32_t n_frames, const void *llr_in,
+                              const ldpc_decode_params *p, uint8_t *hard_out, float *llr_out,
+                              int32_t *iters_out, uint8_t *syndrome_ok, void *workspace,
+                              size_t workspace_bytes, void *stream);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *ldpc_last_error(void);
+
+/* Library version string. */
+const char *ldpc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LDPC_H */

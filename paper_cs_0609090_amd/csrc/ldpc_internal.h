@@ -1,0 +1,76 @@
+// Library-private declarations shared by the runtime and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace ldpc {
+
+constexpr int kWave = 64;     // CDNA wavefront width
+constexpr int kQmax = 31;     // 6-bit message range: extrinsics saturate to +-31
+constexpr int kZoldMax = 62;  // stored Z_{n} saturates to +-62 (see ss_int.hip)
+
+enum Msg : int { MSG_FP32 = 0, MSG_INT8 = 1, MSG_1BIT = 2 };
+
+// Device copy of a parity-check matrix in padded slot-major (ELL) form.
+// Slot j of row m lives at index j * Mp + m, so the 64 rows of a wavefront
+// touch 64 consecutive entries of every per-slot array.
+struct DevCode {
+    int32_t M, N;
+    int32_t Mp;          // rows rounded up to a multiple of 64
+    int32_t D;           // slots per row (max row degree)
+    int32_t dummy;       // variable index of padding slots: multiple of 6, >= N
+    const uint32_t *ell; // [D][Mp] variable index of each slot (dummy for padding)
+    const int32_t *vc_ptr;   // [N+1] edges of variable n: vc_slot[vc_ptr[n] .. vc_ptr[n+1])
+    const uint32_t *vc_slot; // [E] slot index (j*Mp + m) of each edge, ascending m
+};
+
+// Everything a decode kernel needs; passed by value in the kernel arguments.
+struct DecodeArgs {
+    DevCode c;
+    int32_t n_frames;
+    int32_t max_iter;
+    int32_t early_stop;
+    const void *llr_in;      // [F][N] int8 or float
+    int32_t a8, b_int;       // fixed-point normalisation: max(((m*a8+128)>>8) - b, 0)
+    float alpha, beta;       // binary32 normalisation: max(alpha*m - beta, 0)
+    double step;             // LLR value of one fixed-point unit
+    uint8_t *hard_out;
+    float *llr_out;          // nullable
+    int32_t *iters_out;
+    uint8_t *ok_out;
+    uint8_t *ws;             // caller workspace (device), per-frame stride below
+    uint64_t ws_stride;
+    // layout plan
+    int32_t zpack;           // Z accumulator fields per 32-bit LDS word: 1, 2 or 3
+    uint32_t off_zold;       // LDS byte offsets
+    uint32_t off_zacc;
+    uint32_t off_msg;
+    uint32_t off_z;
+    uint32_t off_aux;
+    uint64_t ws_off_msg;     // workspace byte offsets inside one frame's stride
+    uint64_t ws_off_z;
+};
+
+struct LaunchCfg {
+    int dmax;        // register-array bucket: 8, 16, 32 or 64 slots
+    int threads;     // workgroup size (multiple of 64)
+    size_t lds;      // dynamic LDS bytes
+    bool msg_lds;    // message state in LDS (else workspace)
+    bool z_lds;      // posterior array in LDS (else workspace)
+};
+
+// Kernel launchers, one per family (defined next to their kernels).
+hipError_t launch_ss_int(const DecodeArgs &a, int msg, const LaunchCfg &cfg, hipStream_t s);
+hipError_t launch_ss_f32(const DecodeArgs &a, const LaunchCfg &cfg, hipStream_t s);
+hipError_t launch_two_scan(const DecodeArgs &a, int msg, const LaunchCfg &cfg, hipStream_t s);
+hipError_t launch_check_input(const void *llr, int64_t count, int msg, int32_t *bad,
+                              hipStream_t s);
+
+// Launch bound (threads) of each register-array bucket.
+__host__ __device__ constexpr int launch_bound_for(int dmax) {
+    return dmax <= 16 ? 1024 : (dmax <= 32 ? 512 : 256);
+}
+
+}  // namespace ldpc

@@ -1,0 +1,411 @@
+// C ABI of the decoder library (declared in include/ldpc.h): code handles,
+// argument validation, the per-call layout plan and kernel dispatch.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ldpc.h"
+#include "ldpc_internal.h"
+
+struct ldpc_code {
+    int32_t device = 0;
+    int32_t M = 0, N = 0;
+    int64_t E = 0;
+    int32_t D = 0, Mp = 0, dummy = 0;
+    int32_t min_row_deg = 0, max_col_deg = 0;
+    int32_t lds_limit = 65536;
+    uint32_t *d_ell = nullptr;
+    int32_t *d_vc_ptr = nullptr;
+    uint32_t *d_vc_slot = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+// LDS per workgroup assumed for host-only handles: one gfx950 CU (160 KiB).
+constexpr int kHostOnlyLds = 160 * 1024;
+
+ldpc_status fail(ldpc_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+// Per-call layout plan (which state lives in LDS, which in the workspace).
+struct Plan {
+    ldpc::LaunchCfg cfg{};
+    int family = 0;  // 0: single-scan int8/1-bit, 1: single-scan fp32, 2: two-scan
+    int zpack = 1;
+    uint32_t off_zold = 0, off_zacc = 0, off_msg = 0, off_z = 0, off_aux = 0;
+    uint64_t ws_off_msg = 0, ws_off_z = 0, ws_stride = 0;
+    size_t check_bytes = 0;  // LDPC_F_CHECK_INPUT scratch at the end of the workspace
+};
+
+ldpc_status validate_params(const ldpc_decode_params *p) {
+    if (!p) return fail(LDPC_EINVAL, "params is NULL");
+    if (p->max_iter < 0) return fail(LDPC_EINVAL, "max_iter < 0");
+    if (!(p->alpha > 0.0f && p->alpha <= 1.0f)) return fail(LDPC_EINVAL, "alpha outside (0, 1]");
+    if (!(p->beta >= 0.0f) || !std::isfinite(p->beta)) return fail(LDPC_EINVAL, "beta < 0 or not finite");
+    if (p->msg < LDPC_MSG_FP32 || p->msg > LDPC_MSG_1BIT) return fail(LDPC_EINVAL, "unknown msg type");
+    if (p->sched != LDPC_SINGLE_SCAN && p->sched != LDPC_TWO_SCAN)
+        return fail(LDPC_EINVAL, "unknown schedule");
+    if (p->msg != LDPC_MSG_FP32 && !(p->llr_step > 0.0f && std::isfinite(p->llr_step)))
+        return fail(LDPC_EINVAL, "llr_step must be > 0 for fixed-point messages");
+    if (p->sched == LDPC_TWO_SCAN && p->msg == LDPC_MSG_1BIT)
+        return fail(LDPC_EUNSUPPORTED, "two-scan has no 1-bit form (Sec. V compresses single-scan)");
+    const uint32_t layout = (p->flags >> LDPC_F_LAYOUT_SHIFT) & 0xFu;
+    if (layout > LDPC_LAYOUT_HBM) return fail(LDPC_EINVAL, "unknown layout override");
+    return LDPC_OK;
+}
+
+ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl) {
+    const int D = c->D, Mp = c->Mp;
+    const size_t nz = (size_t)c->dummy + 1;
+    const uint32_t layout = (p->flags >> LDPC_F_LAYOUT_SHIFT) & 0xFu;
+    const size_t limit = (size_t)c->lds_limit;
+    const size_t aux = 16;
+    int dmax = D <= 8 ? 8 : (D <= 16 ? 16 : (D <= 32 ? 32 : 64));
+    pl->cfg.dmax = dmax;
+    pl->cfg.threads = std::min(ldpc::launch_bound_for(dmax), Mp);
+    const bool allow_lds = layout != LDPC_LAYOUT_HBM;
+    const bool allow_hbm = layout != LDPC_LAYOUT_LDS;
+
+    if (p->sched == LDPC_SINGLE_SCAN && p->msg != LDPC_MSG_FP32) {
+        pl->family = 0;
+        const size_t zold = align_up(nz, 16);
+        const size_t msg = align_up(p->msg == LDPC_MSG_INT8 ? (size_t)D * Mp
+                                                             : (size_t)D * (Mp / 64) * 8 + 2 * (size_t)Mp,
+                                    16);
+        const int span = 31 * (c->max_col_deg + 1);  // bound on |partial Z| (Eq. 3 sums)
+        for (int pass = 0; pass < 2; ++pass) {
+            const bool msg_lds = pass == 0;
+            if ((msg_lds && !allow_lds) || (!msg_lds && !allow_hbm)) continue;
+            for (int P = 1; P <= 3; ++P) {
+                if (P == 2 && span > 32767) continue;
+                if (P == 3 && span > 511) continue;
+                const size_t zacc = align_up(4 * ((size_t)c->dummy / P + 1), 16);
+                const size_t total = zold + zacc + aux + (msg_lds ? msg : 0);
+                if (total > limit) continue;
+                pl->zpack = P;
+                pl->off_zold = 0;
+                pl->off_zacc = (uint32_t)zold;
+                pl->off_aux = (uint32_t)(zold + zacc);
+                pl->off_msg = (uint32_t)(zold + zacc + aux);
+                pl->cfg.lds = total;
+                pl->cfg.msg_lds = msg_lds;
+                pl->cfg.z_lds = true;
+                pl->ws_stride = msg_lds ? 0 : align_up(msg, 256);
+                pl->ws_off_msg = 0;
+                return LDPC_OK;
+            }
+        }
+        return fail(LDPC_EUNSUPPORTED, "posterior arrays of this code do not fit in LDS");
+    }
+    // binary32 single-scan and the two-scan baseline: message array + posterior array
+    size_t msg, zb;
+    if (p->sched == LDPC_SINGLE_SCAN) {
+        pl->family = 1;
+        msg = align_up((size_t)4 * D * Mp, 16);
+        zb = align_up(4 * nz, 16);
+    } else {
+        pl->family = 2;
+        const size_t esz = p->msg == LDPC_MSG_INT8 ? 1 : 4;
+        msg = align_up(2 * esz * (size_t)D * Mp, 16);
+        zb = align_up((p->msg == LDPC_MSG_INT8 ? 2 : 4) * nz, 16);
+    }
+    const bool opts[3][2] = {{true, true}, {false, true}, {false, false}};
+    for (auto &o : opts) {
+        const bool ml = o[0], zl = o[1];
+        if ((ml && !allow_lds) || (!ml && !allow_hbm)) continue;
+        const size_t total = (zl ? zb : 0) + (ml ? msg : 0) + aux;
+        if (total > limit) continue;
+        pl->cfg.msg_lds = ml;
+        pl->cfg.z_lds = zl;
+        pl->cfg.lds = total;
+        pl->off_z = 0;
+        pl->off_msg = (uint32_t)(zl ? zb : 0);
+        pl->off_aux = (uint32_t)((zl ? zb : 0) + (ml ? msg : 0));
+        pl->ws_off_msg = 0;
+        pl->ws_off_z = ml ? 0 : align_up(msg, 256);
+        pl->ws_stride = align_up((ml ? 0 : align_up(msg, 256)) + (zl ? 0 : zb), 256);
+        return LDPC_OK;
+    }
+    return fail(LDPC_EUNSUPPORTED, "no layout fits the requested override");
+}
+
+__global__ void check_input_kernel(const void *llr, int64_t count, int msg, int32_t *bad) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+        bool b;
+        if (msg == ldpc::MSG_FP32) {
+            b = !isfinite(static_cast<const float *>(llr)[i]);
+        } else {
+            const int v = static_cast<const int8_t *>(llr)[i];
+            b = v < -ldpc::kQmax || v > ldpc::kQmax;
+        }
+        if (b) atomicOr(bad, 1);
+    }
+}
+
+__global__ void zero_word_kernel(int32_t *p) { *p = 0; }
+
+}  // namespace
+
+namespace ldpc {
+hipError_t launch_check_input(const void *llr, int64_t count, int msg, int32_t *bad, hipStream_t s) {
+    hipLaunchKernelGGL(zero_word_kernel, dim3(1), dim3(1), 0, s, bad);
+    if (count > 0) {
+        const int64_t blocks = std::min<int64_t>((count + 255) / 256, 4096);
+        hipLaunchKernelGGL(check_input_kernel, dim3((unsigned)blocks), dim3(256), 0, s, llr, count, msg, bad);
+    }
+    return hipGetLastError();
+}
+}  // namespace ldpc
+
+extern "C" {
+
+const char *ldpc_last_error(void) { return g_err.c_str(); }
+
+const char *ldpc_version(void) { return "ldpc-singlescan-gfx950 0.1"; }
+
+ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *row_ptr,
+                             const int32_t *col_idx, int32_t device, ldpc_code **out) {
+    if (!out) return fail(LDPC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!row_ptr || (nnz > 0 && !col_idx)) return fail(LDPC_EINVAL, "row_ptr/col_idx is NULL");
+    if (M < 1 || N < 1) return fail(LDPC_EBADCODE, "M and N must be >= 1");
+    if (N > (1 << 30)) return fail(LDPC_EUNSUPPORTED, "N too large");
+    if (row_ptr[0] != 0 || (int64_t)row_ptr[M] != nnz) return fail(LDPC_EBADCODE, "row_ptr[0] != 0 or row_ptr[M] != nnz");
+    int D = 0, dmin = 1 << 30;
+    std::vector<int32_t> scratch;
+    for (int m = 0; m < M; ++m) {
+        const int d = row_ptr[m + 1] - row_ptr[m];
+        if (d < 0) return fail(LDPC_EBADCODE, "row_ptr decreases at row " + std::to_string(m));
+        if (d < 2) return fail(LDPC_EBADCODE, "row " + std::to_string(m) + " has degree < 2");
+        D = std::max(D, d);
+        dmin = std::min(dmin, d);
+        scratch.assign(col_idx + row_ptr[m], col_idx + row_ptr[m + 1]);
+        std::sort(scratch.begin(), scratch.end());
+        for (int j = 0; j < d; ++j) {
+            if (scratch[j] < 0 || scratch[j] >= N)
+                return fail(LDPC_EBADCODE, "column index out of range in row " + std::to_string(m));
+            if (j > 0 && scratch[j] == scratch[j - 1])
+                return fail(LDPC_EBADCODE, "duplicate column in row " + std::to_string(m));
+        }
+    }
+    if (D > 64) return fail(LDPC_EUNSUPPORTED, "row degree above 64");
+
+    ldpc_code *c = new ldpc_code();
+    c->device = device;
+    c->M = M;
+    c->N = N;
+    c->E = nnz;
+    c->D = D;
+    c->Mp = (M + 63) / 64 * 64;
+    c->dummy = (N + 5) / 6 * 6;
+    c->min_row_deg = dmin;
+    const size_t slots = (size_t)c->D * c->Mp;
+    std::vector<uint32_t> ell(slots, (uint32_t)c->dummy);
+    std::vector<int32_t> vc_ptr((size_t)N + 1, 0);
+    for (int64_t e = 0; e < nnz; ++e) vc_ptr[col_idx[e] + 1]++;
+    for (int n = 0; n < N; ++n) {
+        c->max_col_deg = std::max(c->max_col_deg, vc_ptr[n + 1]);
+        vc_ptr[n + 1] += vc_ptr[n];
+    }
+    std::vector<uint32_t> vc_slot((size_t)std::max<int64_t>(nnz, 1));
+    std::vector<int32_t> fill(vc_ptr.begin(), vc_ptr.end() - 1);
+    for (int m = 0; m < M; ++m)
+        for (int j = 0; j < row_ptr[m + 1] - row_ptr[m]; ++j) {
+            const int n = col_idx[row_ptr[m] + j];
+            const uint32_t slot = (uint32_t)((size_t)j * c->Mp + m);
+            ell[slot] = (uint32_t)n;
+            vc_slot[fill[n]++] = slot;  // rows visited in ascending order
+        }
+
+    if (device < 0) {  // host-only handle: planning and queries, no decoding
+        c->lds_limit = kHostOnlyLds;
+        *out = c;
+        g_err.clear();
+        return LDPC_OK;
+    }
+    DeviceGuard g(device);
+    if (!g.ok) {
+        delete c;
+        return fail(LDPC_EDEVICE, "hipSetDevice failed");
+    }
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+        c->lds_limit = lds;
+    hipError_t e1 = hipMalloc(&c->d_ell, slots * sizeof(uint32_t));
+    hipError_t e2 = hipMalloc(&c->d_vc_ptr, vc_ptr.size() * sizeof(int32_t));
+    hipError_t e3 = hipMalloc(&c->d_vc_slot, vc_slot.size() * sizeof(uint32_t));
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+        ldpc_code_destroy(c);
+        (void)hipGetLastError();
+        return fail(LDPC_ENOMEM, "device allocation failed");
+    }
+    if (hipMemcpy(c->d_ell, ell.data(), slots * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_vc_ptr, vc_ptr.data(), vc_ptr.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_vc_slot, vc_slot.data(), vc_slot.size() * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess) {
+        ldpc_code_destroy(c);
+        return fail(LDPC_EDEVICE, "copy of the code to the device failed");
+    }
+    *out = c;
+    g_err.clear();
+    return LDPC_OK;
+}
+
+ldpc_status ldpc_code_destroy(ldpc_code *code) {
+    if (!code) return LDPC_OK;
+    if (code->device < 0) {
+        delete code;
+        return LDPC_OK;
+    }
+    DeviceGuard g(code->device);
+    if (code->d_ell) (void)hipFree(code->d_ell);
+    if (code->d_vc_ptr) (void)hipFree(code->d_vc_ptr);
+    if (code->d_vc_slot) (void)hipFree(code->d_vc_slot);
+    delete code;
+    return LDPC_OK;
+}
+
+ldpc_status ldpc_code_query(const ldpc_code *c, ldpc_code_info *o) {
+    if (!c || !o) return fail(LDPC_EINVAL, "NULL argument");
+    std::memset(o, 0, sizeof(*o));
+    o->M = c->M;
+    o->N = c->N;
+    o->E = c->E;
+    o->min_row_deg = c->min_row_deg;
+    o->max_row_deg = c->D;
+    o->max_col_deg = c->max_col_deg;
+    o->slots_per_row = c->D;
+    o->rows_padded = c->Mp;
+    o->device = c->device;
+    o->addr_bytes_single = c->E * 4;
+    o->addr_bytes_two = c->E * 8;
+    o->msg_bits_int8 = c->E * 8;
+    int lg = 0;
+    while ((1 << lg) < c->D) ++lg;
+    o->msg_bits_1bit = c->E + (int64_t)c->M * (5 + 5 + lg);
+    o->lds_bytes_per_cu = c->lds_limit;
+    return LDPC_OK;
+}
+
+ldpc_status ldpc_decode_workspace_size(const ldpc_code *c, int32_t n_frames,
+                                       const ldpc_decode_params *p, size_t *bytes) {
+    if (!c || !bytes) return fail(LDPC_EINVAL, "NULL argument");
+    if (n_frames < 0) return fail(LDPC_EINVAL, "n_frames < 0");
+    ldpc_status st = validate_params(p);
+    if (st != LDPC_OK) return st;
+    Plan pl;
+    st = make_plan(c, p, &pl);
+    if (st != LDPC_OK) return st;
+    size_t b = (size_t)pl.ws_stride * (size_t)n_frames;
+    if (p->flags & LDPC_F_CHECK_INPUT) b = align_up(b, 256) + 256;
+    *bytes = b;
+    return LDPC_OK;
+}
+
+ldpc_status ldpc_decode_batch(const ldpc_code *c, int32_t n_frames, const void *llr_in,
+                              const ldpc_decode_params *p, uint8_t *hard_out, float *llr_out,
+                              int32_t *iters_out, uint8_t *syndrome_ok, void *workspace,
+                              size_t workspace_bytes, void *stream) {
+    if (!c) return fail(LDPC_EINVAL, "code is NULL");
+    if (n_frames < 0) return fail(LDPC_EINVAL, "n_frames < 0");
+    ldpc_status st = validate_params(p);
+    if (st != LDPC_OK) return st;
+    if (n_frames > 0 && (!llr_in || !hard_out || !iters_out || !syndrome_ok))
+        return fail(LDPC_EINVAL, "llr_in, hard_out, iters_out and syndrome_ok are required");
+    Plan pl;
+    st = make_plan(c, p, &pl);
+    if (st != LDPC_OK) return st;
+    size_t need = (size_t)pl.ws_stride * (size_t)n_frames;
+    size_t check_off = 0;
+    if (p->flags & LDPC_F_CHECK_INPUT) {
+        check_off = align_up(need, 256);
+        need = check_off + 256;
+    }
+    if (need > 0 && (!workspace || workspace_bytes < need))
+        return fail(LDPC_EINVAL, "workspace missing or smaller than ldpc_decode_workspace_size()");
+    if (workspace && (reinterpret_cast<uintptr_t>(workspace) & 255u))
+        return fail(LDPC_EINVAL, "workspace must be 256-byte aligned");
+    if (c->device < 0) return fail(LDPC_EINVAL, "host-only handle (device < 0) cannot decode");
+    if (n_frames == 0) return LDPC_OK;
+
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(LDPC_EDEVICE, "hipSetDevice failed");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    if (p->flags & LDPC_F_CHECK_INPUT) {
+        int32_t *bad = reinterpret_cast<int32_t *>(static_cast<uint8_t *>(workspace) + check_off);
+        hipError_t e = ldpc::launch_check_input(llr_in, (int64_t)n_frames * c->N, p->msg, bad, s);
+        int32_t hbad = 0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return fail(LDPC_EDEVICE, std::string("input check failed: ") + hipGetErrorString(e));
+        if (hbad) return fail(LDPC_EINVAL, "llr_in holds non-finite or out-of-range values");
+    }
+
+    ldpc::DecodeArgs a{};
+    a.c.M = c->M;
+    a.c.N = c->N;
+    a.c.Mp = c->Mp;
+    a.c.D = c->D;
+    a.c.dummy = c->dummy;
+    a.c.ell = c->d_ell;
+    a.c.vc_ptr = c->d_vc_ptr;
+    a.c.vc_slot = c->d_vc_slot;
+    a.n_frames = n_frames;
+    a.max_iter = p->max_iter;
+    a.early_stop = p->early_stop ? 1 : 0;
+    a.llr_in = llr_in;
+    a.a8 = (int32_t)std::lround((double)p->alpha * 256.0);
+    a.b_int = p->msg == LDPC_MSG_FP32 ? 0 : (int32_t)std::lround((double)p->beta / (double)p->llr_step);
+    a.alpha = p->alpha;
+    a.beta = p->beta;
+    a.step = (double)p->llr_step;
+    a.hard_out = hard_out;
+    a.llr_out = llr_out;
+    a.iters_out = iters_out;
+    a.ok_out = syndrome_ok;
+    a.ws = static_cast<uint8_t *>(workspace);
+    a.ws_stride = pl.ws_stride;
+    a.zpack = pl.zpack;
+    a.off_zold = pl.off_zold;
+    a.off_zacc = pl.off_zacc;
+    a.off_msg = pl.off_msg;
+    a.off_z = pl.off_z;
+    a.off_aux = pl.off_aux;
+    a.ws_off_msg = pl.ws_off_msg;
+    a.ws_off_z = pl.ws_off_z;
+
+    hipError_t e;
+    if (pl.family == 0)
+        e = ldpc::launch_ss_int(a, p->msg, pl.cfg, s);
+    else if (pl.family == 1)
+        e = ldpc::launch_ss_f32(a, pl.cfg, s);
+    else
+        e = ldpc::launch_two_scan(a, p->msg, pl.cfg, s);
+    if (e != hipSuccess) return fail(LDPC_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return LDPC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,195 @@
+"""Python binding of ``libldpc.so`` (include/ldpc.h): argument marshalling only.
+
+Every decoding step runs in the library's HIP kernels; torch provides device
+memory and the stream.  If the library is not built this module raises
+instead of falling back to anything else.
+
+    code = Code.from_parity_check(H, device=0)
+    out = code.decode(llr_cuda_tensor, max_iter=50, alpha=0.8, msg="int8")
+    out["hard"], out["llr"], out["iters"], out["ok"]
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libldpc.so")
+
+LDPC_OK, LDPC_EINVAL, LDPC_EBADCODE, LDPC_ENOMEM, LDPC_EDEVICE, LDPC_EUNSUPPORTED = range(6)
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "EBADCODE", 3: "ENOMEM", 4: "EDEVICE", 5: "EUNSUPPORTED"}
+MSG = {"fp32": 0, "int8": 1, "1bit": 2}
+SCHED = {"single_scan": 0, "two_scan": 1}
+F_CHECK_INPUT = 0x1
+LAYOUT = {"auto": 0, "lds": 1, "hbm": 2}
+LAYOUT_SHIFT = 8
+
+EXPORTS = ("ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query",
+           "ldpc_decode_workspace_size", "ldpc_decode_batch", "ldpc_last_error",
+           "ldpc_version")
+
+
+class LdpcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class DecodeParams(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("alpha", ctypes.c_float),
+                ("beta", ctypes.c_float), ("early_stop", ctypes.c_int32),
+                ("msg", ctypes.c_int32), ("sched", ctypes.c_int32),
+                ("llr_step", ctypes.c_float), ("flags", ctypes.c_uint32)]
+
+
+class CodeInfo(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("N", ctypes.c_int32), ("E", ctypes.c_int64),
+                ("min_row_deg", ctypes.c_int32), ("max_row_deg", ctypes.c_int32),
+                ("max_col_deg", ctypes.c_int32), ("slots_per_row", ctypes.c_int32),
+                ("rows_padded", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("addr_bytes_single", ctypes.c_int64), ("addr_bytes_two", ctypes.c_int64),
+                ("msg_bits_int8", ctypes.c_int64), ("msg_bits_1bit", ctypes.c_int64),
+                ("lds_bytes_per_cu", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libldpc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_cs_0609090_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        L.ldpc_code_create.argtypes = [i32, i32, i64, vp, vp, i32, ctypes.POINTER(vp)]
+        L.ldpc_code_destroy.argtypes = [vp]
+        L.ldpc_code_query.argtypes = [vp, ctypes.POINTER(CodeInfo)]
+        L.ldpc_decode_workspace_size.argtypes = [vp, i32, ctypes.POINTER(DecodeParams),
+                                                 ctypes.POINTER(sz)]
+        L.ldpc_decode_batch.argtypes = [vp, i32, vp, ctypes.POINTER(DecodeParams), vp, vp, vp,
+                                        vp, vp, sz, vp]
+        for f in ("ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query",
+                  "ldpc_decode_workspace_size", "ldpc_decode_batch"):
+            getattr(L, f).restype = ctypes.c_int
+        L.ldpc_last_error.restype = ctypes.c_char_p
+        L.ldpc_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != LDPC_OK:
+        raise LdpcError(status, lib().ldpc_last_error().decode())
+
+
+def make_params(max_iter=50, alpha=0.8, beta=0.0, early_stop=True, msg="int8",
+                sched="single_scan", llr_step=0.5, check_input=False, layout="auto") -> DecodeParams:
+    flags = (F_CHECK_INPUT if check_input else 0) | (LAYOUT[layout] << LAYOUT_SHIFT)
+    return DecodeParams(int(max_iter), float(alpha), float(beta), 1 if early_stop else 0,
+                        MSG[msg] if isinstance(msg, str) else int(msg),
+                        SCHED[sched] if isinstance(sched, str) else int(sched),
+                        float(llr_step), int(flags))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Code:
+    """Handle of a parity-check matrix resident on one GPU."""
+
+    def __init__(self, M: int, N: int, row_ptr, col_idx, device: int = 0):
+        self._h = None
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        h = ctypes.c_void_p()
+        _check(lib().ldpc_code_create(int(M), int(N), int(rp[-1]) if rp.size else 0,
+                                      rp.ctypes.data_as(ctypes.c_void_p),
+                                      ci.ctypes.data_as(ctypes.c_void_p), int(device),
+                                      ctypes.byref(h)))
+        self._h = h
+        self.M, self.N, self.device = int(M), int(N), int(device)
+
+    @classmethod
+    def from_parity_check(cls, H, device: int = 0) -> "Code":
+        return cls(H.M, H.N, H.row_ptr, H.col_idx, device)
+
+    def close(self):
+        if self._h is not None and _lib is not None:
+            lib().ldpc_code_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        i = CodeInfo()
+        _check(lib().ldpc_code_query(self._h, ctypes.byref(i)))
+        return {k: getattr(i, k) for k, _ in CodeInfo._fields_}
+
+    def workspace_size(self, n_frames: int, params: DecodeParams) -> int:
+        b = ctypes.c_size_t()
+        _check(lib().ldpc_decode_workspace_size(self._h, int(n_frames), ctypes.byref(params),
+                                                ctypes.byref(b)))
+        return int(b.value)
+
+    def decode_into(self, llr, params: DecodeParams, hard, llr_out, iters, ok, workspace,
+                    stream=None) -> None:
+        """Raw call: all tensors are caller-allocated device tensors."""
+        n_frames = llr.shape[0] if llr.dim() == 2 else llr.numel() // self.N
+        s = stream if stream is not None else torch.cuda.current_stream(llr.device)
+        ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+        _check(lib().ldpc_decode_batch(self._h, int(n_frames), _ptr(llr), ctypes.byref(params),
+                                       _ptr(hard), _ptr(llr_out), _ptr(iters), _ptr(ok),
+                                       _ptr(workspace), ws_bytes, ctypes.c_void_p(s.cuda_stream)))
+
+    def alloc_outputs(self, n_frames: int, device, with_llr: bool = True) -> dict:
+        return {
+            "hard": torch.empty((n_frames, self.N), dtype=torch.uint8, device=device),
+            "llr": torch.empty((n_frames, self.N), dtype=torch.float32, device=device)
+            if with_llr else None,
+            "iters": torch.empty(n_frames, dtype=torch.int32, device=device),
+            "ok": torch.empty(n_frames, dtype=torch.uint8, device=device),
+        }
+
+    def alloc_workspace(self, n_frames: int, params: DecodeParams, device):
+        b = self.workspace_size(n_frames, params)
+        if b == 0:
+            return None
+        # torch's caching allocator returns 512-byte aligned blocks
+        return torch.empty(b, dtype=torch.uint8, device=device)
+
+    def decode(self, llr, max_iter=50, alpha=0.8, beta=0.0, early_stop=True, msg=None,
+               sched="single_scan", llr_step=0.5, check_input=False, layout="auto",
+               with_llr=True, stream=None) -> dict:
+        """Decode a [F, N] device tensor (float32 or int8) and return device
+        tensors ``hard``, ``llr``, ``iters``, ``ok``."""
+        if not llr.is_cuda:
+            raise ValueError("llr must be a device tensor")
+        llr = llr.contiguous()
+        if msg is None:
+            msg = "fp32" if llr.dtype == torch.float32 else "int8"
+        want = torch.float32 if msg == "fp32" else torch.int8
+        if llr.dtype != want:
+            raise ValueError(f"msg={msg} needs a {want} tensor")
+        p = make_params(max_iter, alpha, beta, early_stop, msg, sched, llr_step,
+                        check_input, layout)
+        F = llr.shape[0]
+        out = self.alloc_outputs(F, llr.device, with_llr)
+        ws = self.alloc_workspace(F, p, llr.device)
+        self.decode_into(llr, p, out["hard"], out["llr"], out["iters"], out["ok"], ws, stream)
+        return out
+
+
+def version() -> str:
+    return lib().ldpc_version().decode()

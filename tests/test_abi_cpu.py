@@ -1,0 +1,141 @@
+"""C-ABI surface on the CPU: the library loads, exports every symbol of
+include/ldpc.h, validates codes and parameters, and sizes workspaces, all
+without a GPU (host-only handles, device = -1)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_cs_0609090_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_cs_0609090_amd import ldpc
+    return ldpc
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "ldpc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(ldpc_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared_functions()
+    assert len(names) >= 7
+    lib = L.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.EXPORTS)
+    assert L.version().startswith("ldpc")
+
+
+def test_struct_layouts_match_header(L):
+    assert ctypes.sizeof(L.DecodeParams) == 32
+    assert ctypes.sizeof(L.CodeInfo) == 8 + 8 + 4 * 6 + 8 * 4 + 4 + 4  # with tail padding
+
+
+def _create(L, M, N, rp, ci, device=-1):
+    h = ctypes.c_void_p()
+    rp = np.ascontiguousarray(rp, dtype=np.int32)
+    ci = np.ascontiguousarray(ci, dtype=np.int32)
+    st = L.lib().ldpc_code_create(M, N, int(rp[-1]) if rp.size else 0,
+                                  rp.ctypes.data_as(ctypes.c_void_p),
+                                  ci.ctypes.data_as(ctypes.c_void_p), device, ctypes.byref(h))
+    return st, h
+
+
+def test_bad_codes_rejected(L):
+    # degree-1 row
+    st, _ = _create(L, 2, 4, [0, 1, 3], [0, 1, 2])
+    assert st == L.LDPC_EBADCODE and b"degree" in L.lib().ldpc_last_error()
+    # duplicate entry
+    st, _ = _create(L, 1, 4, [0, 3], [1, 2, 1])
+    assert st == L.LDPC_EBADCODE and b"duplicate" in L.lib().ldpc_last_error()
+    # out of range
+    st, _ = _create(L, 1, 4, [0, 2], [1, 4])
+    assert st == L.LDPC_EBADCODE
+    st, _ = _create(L, 1, 4, [0, 2], [-1, 2])
+    assert st == L.LDPC_EBADCODE
+    # inconsistent row_ptr
+    st, _ = _create(L, 2, 4, [1, 2, 4], [0, 1, 2, 3])
+    assert st == L.LDPC_EBADCODE
+    st, _ = _create(L, 2, 4, [0, 3, 2], [0, 1, 2, 3])
+    assert st == L.LDPC_EBADCODE
+    # row degree above 64
+    st, _ = _create(L, 1, 70, [0, 65], np.arange(65))
+    assert st == L.LDPC_EUNSUPPORTED
+    # null pointers
+    h = ctypes.c_void_p()
+    assert L.lib().ldpc_code_create(1, 4, 2, None, None, -1, ctypes.byref(h)) == L.LDPC_EINVAL
+    assert L.lib().ldpc_code_create(1, 4, 2, None, None, -1, None) == L.LDPC_EINVAL
+
+
+def test_host_only_handle_query_and_footprint(L):
+    """P11: single-scan needs only the check-to-variable index (half of the
+    two-scan addressing, Sec. IV); the 1-bit store is E sign bits plus
+    M (5 + 5 + ceil(log2 d_c)) state bits (Sec. V)."""
+    code = W.code_c0_peg1008()
+    c = L.Code.from_parity_check(code, device=-1)
+    info = c.info()
+    assert (info["M"], info["N"], info["E"]) == (504, 1008, 3024)
+    assert info["max_row_deg"] == 6 and info["min_row_deg"] == 6 and info["max_col_deg"] == 3
+    assert info["rows_padded"] == 512
+    assert info["addr_bytes_two"] == 2 * info["addr_bytes_single"]
+    assert info["msg_bits_int8"] == 8 * 3024
+    assert info["msg_bits_1bit"] == 3024 + 504 * (5 + 5 + 3)
+    assert info["lds_bytes_per_cu"] == 160 * 1024
+    c.close()
+
+
+def test_param_validation(L):
+    c = L.Code.from_parity_check(W.code_c0_peg1008(), device=-1)
+    ok = L.make_params()
+    assert c.workspace_size(10, ok) == 0  # everything of the 1008-bit code fits in LDS
+    bad = [L.make_params(max_iter=-1), L.make_params(alpha=0.0), L.make_params(alpha=1.5),
+           L.make_params(beta=-0.1), L.make_params(llr_step=0.0), L.make_params(msg=7),
+           L.make_params(sched=3)]
+    for p in bad:
+        with pytest.raises(L.LdpcError) as ei:
+            c.workspace_size(10, p)
+        assert ei.value.status == L.LDPC_EINVAL
+    with pytest.raises(L.LdpcError) as ei:
+        c.workspace_size(10, L.make_params(msg="1bit", sched="two_scan"))
+    assert ei.value.status == L.LDPC_EUNSUPPORTED
+    with pytest.raises(L.LdpcError) as ei:
+        c.workspace_size(-1, ok)
+    assert ei.value.status == L.LDPC_EINVAL
+    # a host-only handle cannot decode
+    p = L.make_params()
+    st = L.lib().ldpc_decode_batch(c._h, 1, None, ctypes.byref(p), None, None, None, None,
+                                   None, 0, None)
+    assert st == L.LDPC_EINVAL
+    c.close()
+
+
+def test_workspace_plans(L):
+    """Layout planning: the 64800-bit code keeps its messages in the
+    workspace, smaller codes fit in LDS; forcing HBM always costs workspace."""
+    big = L.Code.from_parity_check(W.code_c2_ira64800(), device=-1)
+    for msg in ("int8", "1bit", "fp32"):
+        assert big.workspace_size(4, L.make_params(msg=msg)) > 0
+    b1 = big.workspace_size(1, L.make_params(msg="int8"))
+    assert big.workspace_size(8, L.make_params(msg="int8")) == 8 * b1
+    assert b1 >= 226799  # one int8 message per edge
+    small = L.Code.from_parity_check(W.code_c0_peg1008(), device=-1)
+    for msg in ("int8", "1bit", "fp32"):
+        assert small.workspace_size(4, L.make_params(msg=msg)) == 0
+        assert small.workspace_size(4, L.make_params(msg=msg, layout="hbm")) > 0
+    assert small.workspace_size(4, L.make_params(msg="int8", sched="two_scan")) == 0
+    chk = small.workspace_size(4, L.make_params(msg="int8", check_input=True))
+    assert chk >= 4
+    with pytest.raises(L.LdpcError) as ei:
+        big.workspace_size(4, L.make_params(msg="fp32", layout="lds"))
+    assert ei.value.status == L.LDPC_EUNSUPPORTED
+    big.close()
+    small.close()

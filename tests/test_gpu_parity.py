@@ -1,0 +1,239 @@
+"""GPU parity: the HIP decoders (through the C ABI) against the CPU oracle on
+the same seeded inputs.
+
+Bar: fixed point (int8, 1-bit) bit-exact in posteriors, hard decisions,
+iteration counts and syndrome flags; binary32 bit-exact against the oracle's
+binary32 single-scan (posterior sums in ascending check order, no FMA), which
+is stricter than the 1e-5 relative tolerance asked of the float path.
+The two-scan baseline is held to the same bar: its vertical scan forms
+Z_mn = Z_n - L_mn, which is exactly the single-scan extrinsic.
+"""
+import functools
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_cs_0609090_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def L(torch_dev):
+    from paper_cs_0609090_amd import ldpc
+    ldpc.lib()
+    return ldpc
+
+
+VARIANTS = [  # (gpu msg, gpu sched, oracle algo, oracle arith)
+    ("int8", "single_scan", "single_scan", "int"),
+    ("1bit", "single_scan", "one_bit", "int"),
+    ("fp32", "single_scan", "single_scan", "f32"),
+    ("int8", "two_scan", "two_scan", "int"),
+    ("fp32", "two_scan", "single_scan", "f32"),
+]
+
+
+@functools.lru_cache(maxsize=16)
+def _llr_cached(code_name, N, rate, F, ebn0, key):
+    return W.awgn_llr(N, F, ebn0, rate, key=key)
+
+
+def _inputs(code, F, ebn0, key, msg):
+    llr = _llr_cached(code.name, code.N, code.design_rate, F, ebn0, key)
+    return W.quantize_llr(llr) if msg in ("int8", "1bit") else llr
+
+
+def _gpu(torch, L, gcode, x, msg, sched, **kw):
+    t = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    out = gcode.decode(t, msg=msg, sched=sched, **kw)
+    torch.cuda.synchronize()
+    return {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+
+
+def _compare(g, r, frames=None, where=""):
+    sel = slice(None) if frames is None else frames
+    np.testing.assert_array_equal(g["iters"][sel], r["iters"], err_msg=f"iters {where}")
+    np.testing.assert_array_equal(g["ok"][sel], r["ok"], err_msg=f"ok {where}")
+    np.testing.assert_array_equal(g["hard"][sel], r["hard"], err_msg=f"hard {where}")
+    np.testing.assert_array_equal(g["llr"][sel], r["post"].astype(np.float32), err_msg=f"llr {where}")
+
+
+def _run_pair(torch, L, orc, code, x, variant, frames=None, **kw):
+    msg, sched, algo, arith = variant
+    gcode = L.Code.from_parity_check(code)
+    g = _gpu(torch, L, gcode, x, msg, sched, **kw)
+    gcode.close()
+    xo = x if frames is None else x[frames]
+    okw = {k: v for k, v in kw.items() if k in ("max_iter", "alpha", "beta", "early_stop")}
+    if arith == "int":
+        okw["step"] = kw.get("llr_step", 0.5)
+    r = orc.decode(code, xo, algo=algo, arith=arith, **okw)
+    _compare(g, r, frames, where=f"{code.name} {variant} {kw}")
+    return g, r
+
+
+# ---------------------------------------------------------------------------
+def test_golden_tiny(torch_dev, L, orc):
+    g = json.load(open(os.path.join(GOLDEN, "tiny3x6.json")))
+    code = W.ParityCheck.from_rows(3, 6, g["H_rows"], "tiny3x6")
+    c = g["cases"][0]
+    x = np.array([c["llr_steps"]], dtype=np.int8)
+    gc = L.Code.from_parity_check(code)
+    for msg in ("int8", "1bit"):
+        out = _gpu(torch_dev, L, gc, x, msg, "single_scan", max_iter=2, alpha=0.8,
+                   early_stop=False)
+        assert (out["llr"][0] / 0.5).tolist() == c["iter2_Z_steps"]
+        assert out["hard"][0].tolist() == c["iter2_hard"] and out["ok"][0] == 0
+        out = _gpu(torch_dev, L, gc, x, msg, "single_scan", max_iter=2, alpha=0.8,
+                   early_stop=True)
+        assert out["iters"][0] == 1 and out["ok"][0] == 1
+    cf = g["cases"][2]
+    xf = np.array([cf["llr"]], dtype=np.float32)
+    for sched in ("single_scan", "two_scan"):
+        out = _gpu(torch_dev, L, gc, xf, "fp32", sched, max_iter=2, alpha=0.75, early_stop=False)
+        assert out["llr"][0].tolist() == cf["iter2_Z"]
+    gc.close()
+
+
+@pytest.mark.parametrize("variant", VARIANTS, ids=lambda v: f"{v[0]}-{v[1]}")
+def test_random_small_codes(torch_dev, L, orc, variant):
+    rng = np.random.default_rng(123)
+    for i in range(14):
+        M = int(rng.integers(3, 40))
+        N = int(rng.integers(M + 2, 3 * M + 4))
+        dmax = [6, 12, 20, 30, 45][i % 5]
+        code = W.random_small_code(M, N, (2, min(dmax, N)), seed=500 + i)
+        F = int(rng.integers(1, 9))
+        if variant[0] == "fp32":
+            x = rng.normal(0.7, 2.0, size=(F, N)).astype(np.float32)
+        else:
+            x = rng.integers(-31, 32, size=(F, N)).astype(np.int8)
+        for alpha, beta, es in ((0.8, 0.0, True), (1.0, 0.0, False), (0.75, 0.5, False),
+                                (0.9, 1.5, True)):
+            _run_pair(torch_dev, L, orc, code, x, variant, max_iter=int(rng.integers(0, 12)),
+                      alpha=alpha, beta=beta, early_stop=es)
+
+
+@pytest.mark.parametrize("variant", VARIANTS, ids=lambda v: f"{v[0]}-{v[1]}")
+def test_peg1008_full_config(torch_dev, L, orc, variant):
+    """(3,6) PEG code, N=1008: 200 frames at Eb/N0 = 2 dB, max 50, alpha 0.8,
+    syndrome early stop -- every frame checked."""
+    code = W.code_c0_peg1008()
+    x = _inputs(code, 200, 2.0, (0xC0, 1), variant[0])
+    g, r = _run_pair(torch_dev, L, orc, code, x, variant, max_iter=50, alpha=0.8,
+                     early_stop=True)
+    assert r["ok"].sum() > 150  # most frames decode at 2 dB
+
+
+@pytest.mark.parametrize("variant", VARIANTS[:3], ids=lambda v: f"{v[0]}-{v[1]}")
+def test_ira16200(torch_dev, L, orc, variant):
+    code = W.code_ira16200()
+    x = _inputs(code, 24, 1.2, (0x16, 2), variant[0])
+    _run_pair(torch_dev, L, orc, code, x, variant, max_iter=25, alpha=0.8, early_stop=True)
+
+
+@pytest.mark.parametrize("variant", [VARIANTS[0], VARIANTS[1], VARIANTS[3]],
+                         ids=lambda v: f"{v[0]}-{v[1]}")
+def test_qc7493_batch_sampled(torch_dev, L, orc, variant):
+    """QC code N=7493: a 4096-frame batch at 2 dB, max 30; sampled frames
+    against the oracle."""
+    code = W.code_c1_qc7493()
+    x = _inputs(code, 4096, 2.0, (0xC1, 3), variant[0])
+    frames = np.array([0, 1, 777, 2048, 4095])
+    _run_pair(torch_dev, L, orc, code, x, variant, frames=frames, max_iter=30, alpha=0.8,
+              early_stop=True)
+
+
+@pytest.mark.parametrize("variant", VARIANTS, ids=lambda v: f"{v[0]}-{v[1]}")
+def test_ira64800_bench_config_sampled(torch_dev, L, orc, variant):
+    """N=64800 IRA code in the benchmark configuration (512 frames, 1 dB,
+    max 50, no early stop); frames sampled across the batch."""
+    code = W.code_c2_ira64800()
+    x = _inputs(code, 512, 1.0, (0xC2, 4), variant[0])
+    frames = np.array([0, 255, 511])
+    _run_pair(torch_dev, L, orc, code, x, variant, frames=frames, max_iter=50, alpha=0.8,
+              early_stop=False)
+
+
+@pytest.mark.parametrize("msg", ["int8", "1bit", "fp32"])
+@pytest.mark.parametrize("sched", ["single_scan", "two_scan"])
+def test_layout_and_batch_invariance(torch_dev, L, msg, sched):
+    """P10: a frame's result does not depend on the layout or on the other
+    frames of the batch."""
+    if msg == "1bit" and sched == "two_scan":
+        pytest.skip("no two-scan 1-bit form")
+    code = W.code_c0_peg1008()
+    x = _inputs(code, 64, 1.5, (0xBA, 5), msg)
+    gc = L.Code.from_parity_check(code)
+    kw = dict(max_iter=30, alpha=0.8, early_stop=True)
+    a = _gpu(torch_dev, L, gc, x, msg, sched, layout="lds", **kw)
+    b = _gpu(torch_dev, L, gc, x, msg, sched, layout="hbm", **kw)
+    c = _gpu(torch_dev, L, gc, x[::-1].copy(), msg, sched, **kw)
+    d = _gpu(torch_dev, L, gc, x[5:9], msg, sched, **kw)
+    for k in ("hard", "llr", "iters", "ok"):
+        np.testing.assert_array_equal(a[k], b[k])
+        np.testing.assert_array_equal(a[k], c[k][::-1])
+        np.testing.assert_array_equal(a[k][5:9], d[k])
+    gc.close()
+
+
+def test_edge_cases(torch_dev, L, orc):
+    torch = torch_dev
+    code = W.code_c0_peg1008()
+    gc = L.Code.from_parity_check(code)
+    # empty batch: nothing launched, no error
+    out = gc.decode(torch.zeros((0, code.N), dtype=torch.int8, device="cuda"), msg="int8")
+    assert out["hard"].shape == (0, code.N)
+    # max_iter = 0: channel decisions
+    x = _inputs(code, 5, 2.0, (1, 1), "int8")
+    for msg in ("int8", "1bit"):
+        g = _gpu(torch, L, gc, x, msg, "single_scan", max_iter=0)
+        np.testing.assert_array_equal(g["hard"], (x <= 0).astype(np.uint8))
+        np.testing.assert_array_equal(g["llr"], x.astype(np.float32) * 0.5)
+        assert np.all(g["iters"] == 0)
+    # all-zero LLRs (every decision ties at Z = 0), and saturated inputs
+    for x in (np.zeros((3, code.N), np.int8), np.full((3, code.N), 31, np.int8),
+              np.full((3, code.N), -31, np.int8)):
+        for v in VARIANTS[:2] + VARIANTS[3:4]:
+            _run_pair(torch, L, orc, code, x, v, max_iter=7, alpha=0.8, early_stop=True)
+    # input checking
+    bad = np.zeros((2, code.N), np.int8)
+    bad[1, 7] = 40
+    with pytest.raises(L.LdpcError) as ei:
+        gc.decode(torch.from_numpy(bad).cuda(), msg="int8", check_input=True)
+    assert ei.value.status == L.LDPC_EINVAL
+    badf = np.zeros((2, code.N), np.float32)
+    badf[0, 3] = np.nan
+    with pytest.raises(L.LdpcError):
+        gc.decode(torch.from_numpy(badf).cuda(), msg="fp32", check_input=True)
+    good = gc.decode(torch.from_numpy(x).cuda(), msg="int8", check_input=True)
+    torch.cuda.synchronize()
+    assert good["ok"].shape == (3,)
+    gc.close()
+
+
+def test_workspace_too_small_rejected(torch_dev, L):
+    torch = torch_dev
+    code = W.code_c2_ira64800()
+    gc = L.Code.from_parity_check(code)
+    p = L.make_params(msg="int8")
+    need = gc.workspace_size(2, p)
+    x = torch.zeros((2, code.N), dtype=torch.int8, device="cuda")
+    o = gc.alloc_outputs(2, x.device)
+    ws = torch.empty(need - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(L.LdpcError) as ei:
+        gc.decode_into(x, p, o["hard"], o["llr"], o["iters"], o["ok"], ws)
+    assert ei.value.status == L.LDPC_EINVAL
+    gc.close()
