@@ -111,6 +111,9 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after timing, copy a buffer of this size once (calibrates "
+                         "the HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: frames are independent, so the decoder "
@@ -197,6 +200,14 @@ def main():
         log(f"[bench] cpu oracle baseline: {args.cpu_frames} frames on {threads} threads")
         cb = cpu_baseline(code, q, args.cpu_frames, threads)
         res["cpu_baseline"] = cb
+    if args.copy_probe_mib > 0:
+        src = torch.empty(args.copy_probe_mib << 20, dtype=torch.uint8, device=dev)
+        src.fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        res["copy_probe_bytes"] = args.copy_probe_mib << 20
     gcode.close()
     print(json.dumps(res), flush=True)
 

@@ -60,6 +60,9 @@ typedef enum {
 #define LDPC_LAYOUT_AUTO 0
 #define LDPC_LAYOUT_LDS 1       /* messages in LDS (must fit) */
 #define LDPC_LAYOUT_HBM 2       /* messages in the caller's workspace (device memory) */
+#define LDPC_LAYOUT_REG 3       /* messages in registers, one workgroup of 1024 threads per
+                                   frame (single-scan INT8/1BIT; codes with an instantiated
+                                   shape, see ldpc_code_info.reg_*); AUTO prefers it */
 
 /*
  * Decoding parameters (Sec. III: normalisation lambda_k = alpha, offset
@@ -98,6 +101,9 @@ typedef struct {
     int64_t msg_bits_int8;      /* b * E with b = 8 (int8 message store, Sec. V) */
     int64_t msg_bits_1bit;      /* E sign bits + M * (5 + 5 + ceil(log2 d_c)) state bits */
     int32_t lds_bytes_per_cu;   /* LDS available to one workgroup on this device */
+    int32_t reg_slots;          /* register-resident shape: slots per row (0 = none) */
+    int32_t reg_rows_per_thread;
+    int32_t reg_zpack;          /* posterior accumulator fields per 32-bit LDS word */
 } ldpc_code_info;
 
 /*

@@ -24,6 +24,7 @@ struct DevCode {
     const uint32_t *ell; // [D][Mp] variable index of each slot (dummy for padding)
     const int32_t *vc_ptr;   // [N+1] edges of variable n: vc_slot[vc_ptr[n] .. vc_ptr[n+1])
     const uint32_t *vc_slot; // [E] slot index (j*Mp + m) of each edge, ascending m
+    const uint32_t *ell_reg; // [regD][regR*1024] index for the register-resident kernel (or null)
 };
 
 // Everything a decode kernel needs; passed by value in the kernel arguments.
@@ -65,6 +66,10 @@ struct LaunchCfg {
 hipError_t launch_ss_int(const DecodeArgs &a, int msg, const LaunchCfg &cfg, hipStream_t s);
 hipError_t launch_ss_f32(const DecodeArgs &a, const LaunchCfg &cfg, hipStream_t s);
 hipError_t launch_two_scan(const DecodeArgs &a, int msg, const LaunchCfg &cfg, hipStream_t s);
+hipError_t launch_ss_reg(const DecodeArgs &a, int msg, int D, int R, int P, size_t lds, hipStream_t s);
+bool reg_shape_available(int D, int R, int P);
+void reg_shapes(int *out, int cap, int *count);  // (D, R, P) triples
+constexpr int kRegThreads = 1024;
 hipError_t launch_check_input(const void *llr, int64_t count, int msg, int32_t *bad,
                               hipStream_t s);
 

@@ -20,6 +20,9 @@ struct ldpc_code {
     uint32_t *d_ell = nullptr;
     int32_t *d_vc_ptr = nullptr;
     uint32_t *d_vc_slot = nullptr;
+    // register-resident shape (0 = none)
+    int32_t regD = 0, regR = 0, regP = 0;
+    uint32_t *d_ell_reg = nullptr;
 };
 
 namespace {
@@ -52,7 +55,7 @@ struct DeviceGuard {
 // Per-call layout plan (which state lives in LDS, which in the workspace).
 struct Plan {
     ldpc::LaunchCfg cfg{};
-    int family = 0;  // 0: single-scan int8/1-bit, 1: single-scan fp32, 2: two-scan
+    int family = 0;  // 0: single-scan int8/1-bit, 1: single-scan fp32, 2: two-scan, 3: register-resident
     int zpack = 1;
     uint32_t off_zold = 0, off_zacc = 0, off_msg = 0, off_z = 0, off_aux = 0;
     uint64_t ws_off_msg = 0, ws_off_z = 0, ws_stride = 0;
@@ -72,7 +75,7 @@ ldpc_status validate_params(const ldpc_decode_params *p) {
     if (p->sched == LDPC_TWO_SCAN && p->msg == LDPC_MSG_1BIT)
         return fail(LDPC_EUNSUPPORTED, "two-scan has no 1-bit form (Sec. V compresses single-scan)");
     const uint32_t layout = (p->flags >> LDPC_F_LAYOUT_SHIFT) & 0xFu;
-    if (layout > LDPC_LAYOUT_HBM) return fail(LDPC_EINVAL, "unknown layout override");
+    if (layout > LDPC_LAYOUT_REG) return fail(LDPC_EINVAL, "unknown layout override");
     return LDPC_OK;
 }
 
@@ -85,8 +88,29 @@ ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl)
     int dmax = D <= 8 ? 8 : (D <= 16 ? 16 : (D <= 32 ? 32 : 64));
     pl->cfg.dmax = dmax;
     pl->cfg.threads = std::min(ldpc::launch_bound_for(dmax), Mp);
-    const bool allow_lds = layout != LDPC_LAYOUT_HBM;
-    const bool allow_hbm = layout != LDPC_LAYOUT_LDS;
+    const bool allow_lds = layout == LDPC_LAYOUT_AUTO || layout == LDPC_LAYOUT_LDS;
+    const bool allow_hbm = layout == LDPC_LAYOUT_AUTO || layout == LDPC_LAYOUT_HBM;
+
+    if (p->sched == LDPC_SINGLE_SCAN && p->msg != LDPC_MSG_FP32 &&
+        (layout == LDPC_LAYOUT_AUTO || layout == LDPC_LAYOUT_REG)) {
+        const bool ok = c->regD > 0 && (p->msg == LDPC_MSG_INT8 || c->regD + 15 <= 32);
+        if (ok) {
+            pl->family = 3;
+            const size_t zold = align_up(nz, 16);
+            const size_t zacc = align_up(4 * ((size_t)c->dummy / c->regP + 1), 16);
+            pl->zpack = c->regP;
+            pl->off_zold = 0;
+            pl->off_zacc = (uint32_t)zold;
+            pl->off_aux = (uint32_t)(zold + zacc);
+            pl->cfg.lds = zold + zacc + aux;
+            pl->cfg.threads = ldpc::kRegThreads;
+            pl->ws_stride = 0;
+            return LDPC_OK;
+        }
+        if (layout == LDPC_LAYOUT_REG)
+            return fail(LDPC_EUNSUPPORTED, "no register-resident shape for this code and message type");
+    }
+    if (layout == LDPC_LAYOUT_REG) return fail(LDPC_EUNSUPPORTED, "register layout is single-scan INT8/1BIT only");
 
     if (p->sched == LDPC_SINGLE_SCAN && p->msg != LDPC_MSG_FP32) {
         pl->family = 0;
@@ -240,6 +264,39 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
             vc_slot[fill[n]++] = slot;  // rows visited in ascending order
         }
 
+    // register-resident shape: smallest instantiated (slots, rows/thread, packing)
+    // covering the code whose posterior arrays fit the LDS budget
+    int lds_dev = kHostOnlyLds;
+    if (device >= 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && v > 0)
+            lds_dev = v;
+    }
+    {
+        int shapes[3 * 64], cnt = 0;
+        ldpc::reg_shapes(shapes, 64, &cnt);
+        const int span = 31 * (c->max_col_deg + 1);
+        int bestD = 1 << 30, bestR = 1 << 30, bestP = 0;
+        for (int i = 0; i < cnt && i < 64; ++i) {
+            const int d = shapes[3 * i], r = shapes[3 * i + 1], pk = shapes[3 * i + 2];
+            if (d < D || (int64_t)r * ldpc::kRegThreads < M) continue;
+            if (pk == 2 && span > 32767) continue;
+            if (pk == 3 && (span > 511 || c->dummy + 1 >= 98303)) continue;
+            const size_t need = align_up((size_t)c->dummy + 1, 16) +
+                                align_up(4 * ((size_t)c->dummy / pk + 1), 16) + 16;
+            if (need > (size_t)lds_dev) continue;
+            if (d < bestD || (d == bestD && r < bestR) || (d == bestD && r == bestR && pk < bestP)) {
+                bestD = d;
+                bestR = r;
+                bestP = pk;
+            }
+        }
+        if (bestP) {
+            c->regD = bestD;
+            c->regR = bestR;
+            c->regP = bestP;
+        }
+    }
     if (device < 0) {  // host-only handle: planning and queries, no decoding
         c->lds_limit = kHostOnlyLds;
         *out = c;
@@ -257,14 +314,26 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
     hipError_t e1 = hipMalloc(&c->d_ell, slots * sizeof(uint32_t));
     hipError_t e2 = hipMalloc(&c->d_vc_ptr, vc_ptr.size() * sizeof(int32_t));
     hipError_t e3 = hipMalloc(&c->d_vc_slot, vc_slot.size() * sizeof(uint32_t));
-    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+    std::vector<uint32_t> ell_reg;
+    hipError_t e4 = hipSuccess;
+    if (c->regD > 0) {
+        const size_t Mr = (size_t)c->regR * ldpc::kRegThreads;
+        ell_reg.assign((size_t)c->regD * Mr, (uint32_t)c->dummy);
+        for (int m = 0; m < M; ++m)
+            for (int j = 0; j < row_ptr[m + 1] - row_ptr[m]; ++j)
+                ell_reg[(size_t)j * Mr + m] = (uint32_t)col_idx[row_ptr[m] + j];
+        e4 = hipMalloc(&c->d_ell_reg, ell_reg.size() * sizeof(uint32_t));
+    }
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {
         ldpc_code_destroy(c);
         (void)hipGetLastError();
         return fail(LDPC_ENOMEM, "device allocation failed");
     }
     if (hipMemcpy(c->d_ell, ell.data(), slots * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_vc_ptr, vc_ptr.data(), vc_ptr.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(c->d_vc_slot, vc_slot.data(), vc_slot.size() * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(c->d_vc_slot, vc_slot.data(), vc_slot.size() * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess ||
+        (c->d_ell_reg && hipMemcpy(c->d_ell_reg, ell_reg.data(), ell_reg.size() * sizeof(uint32_t),
+                                   hipMemcpyHostToDevice) != hipSuccess)) {
         ldpc_code_destroy(c);
         return fail(LDPC_EDEVICE, "copy of the code to the device failed");
     }
@@ -283,6 +352,7 @@ ldpc_status ldpc_code_destroy(ldpc_code *code) {
     if (code->d_ell) (void)hipFree(code->d_ell);
     if (code->d_vc_ptr) (void)hipFree(code->d_vc_ptr);
     if (code->d_vc_slot) (void)hipFree(code->d_vc_slot);
+    if (code->d_ell_reg) (void)hipFree(code->d_ell_reg);
     delete code;
     return LDPC_OK;
 }
@@ -306,6 +376,9 @@ ldpc_status ldpc_code_query(const ldpc_code *c, ldpc_code_info *o) {
     while ((1 << lg) < c->D) ++lg;
     o->msg_bits_1bit = c->E + (int64_t)c->M * (5 + 5 + lg);
     o->lds_bytes_per_cu = c->lds_limit;
+    o->reg_slots = c->regD;
+    o->reg_rows_per_thread = c->regR;
+    o->reg_zpack = c->regP;
     return LDPC_OK;
 }
 
@@ -373,6 +446,7 @@ ldpc_status ldpc_decode_batch(const ldpc_code *c, int32_t n_frames, const void *
     a.c.ell = c->d_ell;
     a.c.vc_ptr = c->d_vc_ptr;
     a.c.vc_slot = c->d_vc_slot;
+    a.c.ell_reg = c->d_ell_reg;
     a.n_frames = n_frames;
     a.max_iter = p->max_iter;
     a.early_stop = p->early_stop ? 1 : 0;
@@ -400,6 +474,8 @@ ldpc_status ldpc_decode_batch(const ldpc_code *c, int32_t n_frames, const void *
     hipError_t e;
     if (pl.family == 0)
         e = ldpc::launch_ss_int(a, p->msg, pl.cfg, s);
+    else if (pl.family == 3)
+        e = ldpc::launch_ss_reg(a, p->msg, c->regD, c->regR, c->regP, pl.cfg.lds, s);
     else if (pl.family == 1)
         e = ldpc::launch_ss_f32(a, pl.cfg, s);
     else

@@ -35,9 +35,28 @@ def test_exports_every_declared_symbol(L):
     assert L.version().startswith("ldpc")
 
 
-def test_struct_layouts_match_header(L):
-    assert ctypes.sizeof(L.DecodeParams) == 32
-    assert ctypes.sizeof(L.CodeInfo) == 8 + 8 + 4 * 6 + 8 * 4 + 4 + 4  # with tail padding
+def test_struct_layouts_match_header(L, tmp_path):
+    """The ctypes mirrors of ldpc_decode_params / ldpc_code_info have the
+    C compiler's sizes and field offsets."""
+    import subprocess
+    fields = {"ldpc_decode_params": [f for f, _ in L.DecodeParams._fields_],
+              "ldpc_code_info": [f for f, _ in L.CodeInfo._fields_]}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ldpc.h"', 'int main(void) {']
+    for st, fs in fields.items():
+        lines.append(f'printf("{st} %zu\\n", sizeof({st}));')
+        for f in fs:
+            lines.append(f'printf("{st}.{f} %zu\\n", offsetof({st}, {f}));')
+    lines.append('return 0; }')
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                       check=True).stdout.splitlines())
+    for st, cls in (("ldpc_decode_params", L.DecodeParams), ("ldpc_code_info", L.CodeInfo)):
+        assert int(out[st]) == ctypes.sizeof(cls), st
+        for f in fields[st]:
+            assert int(out[f"{st}.{f}"]) == getattr(cls, f).offset, f"{st}.{f}"
 
 
 def _create(L, M, N, rp, ci, device=-1):
@@ -119,13 +138,22 @@ def test_param_validation(L):
 
 
 def test_workspace_plans(L):
-    """Layout planning: the 64800-bit code keeps its messages in the
-    workspace, smaller codes fit in LDS; forcing HBM always costs workspace."""
+    """Layout planning: fixed-point messages of the 64800-bit code live in
+    registers (no workspace); the generic kernels keep them in the workspace;
+    smaller codes fit in LDS; forcing HBM always costs workspace."""
     big = L.Code.from_parity_check(W.code_c2_ira64800(), device=-1)
-    for msg in ("int8", "1bit", "fp32"):
-        assert big.workspace_size(4, L.make_params(msg=msg)) > 0
-    b1 = big.workspace_size(1, L.make_params(msg="int8"))
-    assert big.workspace_size(8, L.make_params(msg="int8")) == 8 * b1
+    info = big.info()
+    assert (info["reg_slots"], info["reg_rows_per_thread"], info["reg_zpack"]) == (7, 32, 3)
+    for msg in ("int8", "1bit"):
+        assert big.workspace_size(4, L.make_params(msg=msg)) == 0
+        assert big.workspace_size(4, L.make_params(msg=msg, layout="reg")) == 0
+        assert big.workspace_size(4, L.make_params(msg=msg, layout="hbm")) > 0
+    assert big.workspace_size(4, L.make_params(msg="fp32")) > 0
+    with pytest.raises(L.LdpcError) as ei:
+        big.workspace_size(4, L.make_params(msg="fp32", layout="reg"))
+    assert ei.value.status == L.LDPC_EUNSUPPORTED
+    b1 = big.workspace_size(1, L.make_params(msg="int8", layout="hbm"))
+    assert big.workspace_size(8, L.make_params(msg="int8", layout="hbm")) == 8 * b1
     assert b1 >= 226799  # one int8 message per edge
     small = L.Code.from_parity_check(W.code_c0_peg1008(), device=-1)
     for msg in ("int8", "1bit", "fp32"):

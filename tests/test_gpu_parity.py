@@ -108,7 +108,8 @@ def test_golden_tiny(torch_dev, L, orc):
 
 
 @pytest.mark.parametrize("variant", VARIANTS, ids=lambda v: f"{v[0]}-{v[1]}")
-def test_random_small_codes(torch_dev, L, orc, variant):
+@pytest.mark.parametrize("layout", ["auto", "lds", "hbm"])
+def test_random_small_codes(torch_dev, L, orc, variant, layout):
     rng = np.random.default_rng(123)
     for i in range(14):
         M = int(rng.integers(3, 40))
@@ -123,7 +124,7 @@ def test_random_small_codes(torch_dev, L, orc, variant):
         for alpha, beta, es in ((0.8, 0.0, True), (1.0, 0.0, False), (0.75, 0.5, False),
                                 (0.9, 1.5, True)):
             _run_pair(torch_dev, L, orc, code, x, variant, max_iter=int(rng.integers(0, 12)),
-                      alpha=alpha, beta=beta, early_stop=es)
+                      alpha=alpha, beta=beta, early_stop=es, layout=layout)
 
 
 @pytest.mark.parametrize("variant", VARIANTS, ids=lambda v: f"{v[0]}-{v[1]}")
@@ -144,27 +145,42 @@ def test_ira16200(torch_dev, L, orc, variant):
     _run_pair(torch_dev, L, orc, code, x, variant, max_iter=25, alpha=0.8, early_stop=True)
 
 
-@pytest.mark.parametrize("variant", [VARIANTS[0], VARIANTS[1], VARIANTS[3]],
-                         ids=lambda v: f"{v[0]}-{v[1]}")
-def test_qc7493_batch_sampled(torch_dev, L, orc, variant):
+@pytest.mark.parametrize("variant,layout", [(VARIANTS[0], "auto"), (VARIANTS[0], "lds"),
+                                            (VARIANTS[0], "hbm"), (VARIANTS[1], "lds"),
+                                            (VARIANTS[3], "auto")],
+                         ids=lambda v: v if isinstance(v, str) else f"{v[0]}-{v[1]}")
+def test_qc7493_batch_sampled(torch_dev, L, orc, variant, layout):
     """QC code N=7493: a 4096-frame batch at 2 dB, max 30; sampled frames
     against the oracle."""
     code = W.code_c1_qc7493()
     x = _inputs(code, 4096, 2.0, (0xC1, 3), variant[0])
     frames = np.array([0, 1, 777, 2048, 4095])
     _run_pair(torch_dev, L, orc, code, x, variant, frames=frames, max_iter=30, alpha=0.8,
-              early_stop=True)
+              early_stop=True, layout=layout)
 
 
-@pytest.mark.parametrize("variant", VARIANTS, ids=lambda v: f"{v[0]}-{v[1]}")
-def test_ira64800_bench_config_sampled(torch_dev, L, orc, variant):
+@pytest.mark.parametrize("variant,layout", [(v, "auto") for v in VARIANTS] +
+                         [(VARIANTS[0], "hbm"), (VARIANTS[1], "hbm")],
+                         ids=lambda v: v if isinstance(v, str) else f"{v[0]}-{v[1]}")
+def test_ira64800_bench_config_sampled(torch_dev, L, orc, variant, layout):
     """N=64800 IRA code in the benchmark configuration (512 frames, 1 dB,
     max 50, no early stop); frames sampled across the batch."""
     code = W.code_c2_ira64800()
     x = _inputs(code, 512, 1.0, (0xC2, 4), variant[0])
     frames = np.array([0, 255, 511])
     _run_pair(torch_dev, L, orc, code, x, variant, frames=frames, max_iter=50, alpha=0.8,
-              early_stop=False)
+              early_stop=False, layout=layout)
+
+
+def test_register_path_selected(torch_dev, L):
+    """The fixed-point single-scan path of every workload code runs on the
+    register-resident kernel (shape chosen at create time)."""
+    for code, shape in ((W.code_c0_peg1008(), (6, 1, 1)), (W.code_ira16200(), (7, 8, 1)),
+                        (W.code_c1_qc7493(), (21, 3, 1)), (W.code_c2_ira64800(), (7, 32, 3))):
+        gc = L.Code.from_parity_check(code)
+        i = gc.info()
+        assert (i["reg_slots"], i["reg_rows_per_thread"], i["reg_zpack"]) == shape, code.name
+        gc.close()
 
 
 @pytest.mark.parametrize("msg", ["int8", "1bit", "fp32"])
@@ -180,6 +196,10 @@ def test_layout_and_batch_invariance(torch_dev, L, msg, sched):
     kw = dict(max_iter=30, alpha=0.8, early_stop=True)
     a = _gpu(torch_dev, L, gc, x, msg, sched, layout="lds", **kw)
     b = _gpu(torch_dev, L, gc, x, msg, sched, layout="hbm", **kw)
+    if sched == "single_scan" and msg != "fp32":
+        r = _gpu(torch_dev, L, gc, x, msg, sched, layout="reg", **kw)
+        for k in ("hard", "llr", "iters", "ok"):
+            np.testing.assert_array_equal(a[k], r[k])
     c = _gpu(torch_dev, L, gc, x[::-1].copy(), msg, sched, **kw)
     d = _gpu(torch_dev, L, gc, x[5:9], msg, sched, **kw)
     for k in ("hard", "llr", "iters", "ok"):
@@ -228,8 +248,9 @@ def test_workspace_too_small_rejected(torch_dev, L):
     torch = torch_dev
     code = W.code_c2_ira64800()
     gc = L.Code.from_parity_check(code)
-    p = L.make_params(msg="int8")
+    p = L.make_params(msg="int8", layout="hbm")
     need = gc.workspace_size(2, p)
+    assert need > 256
     x = torch.zeros((2, code.N), dtype=torch.int8, device="cuda")
     o = gc.alloc_outputs(2, x.device)
     ws = torch.empty(need - 256, dtype=torch.uint8, device="cuda")
