@@ -134,7 +134,7 @@ def main():
     ap.add_argument("--frames", type=int, default=512)
     ap.add_argument("--msg", default="int8", choices=["int8", "1bit", "fp32"])
     ap.add_argument("--sched", default="single_scan", choices=["single_scan", "two_scan"])
-    ap.add_argument("--layout", default="auto", choices=["auto", "lds", "hbm"])
+    ap.add_argument("--layout", default="auto", choices=["auto", "lds", "hbm", "reg", "reg1"])
     ap.add_argument("--cpu-frames", type=int, default=192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
@@ -182,9 +182,12 @@ def main():
     alg_ops = (ALG_OPS_PER_EDGE * E + ALG_OPS_PER_ROW * M) * r["iters"]
     achieved_alu = alg_ops / r["kernel_s"] / 1e12
     info = gcode.info()
-    reg = (args.msg in ("int8", "1bit") and args.sched == "single_scan"
-           and args.layout in ("auto", "reg") and info["reg_slots"] > 0)
-    kernel_src = "ss_reg.hip" if reg else None
+    kernel_src = None
+    if args.msg in ("int8", "1bit") and args.sched == "single_scan":
+        if args.msg == "int8" and args.layout in ("auto", "reg") and info["pk_slots"] > 0:
+            kernel_src = "ss_pk.hip"
+        elif args.layout in ("auto", "reg", "reg1") and info["reg_slots"] > 0:
+            kernel_src = "ss_reg.hip"
     traffic = None
     if kernel_src:
         t = MEASURED_TRAFFIC.get(kernel_src, {}).get(source_hash(kernel_src))
@@ -215,7 +218,7 @@ def main():
                      "traffic": traffic,
                      "kernel_ms": round(r["kernel_s"] * 1e3, 4),
                      "alg_ops_per_launch": alg_ops,
-                     "kernel": "ss_reg_kernel" if reg else "generic"},
+                     "kernel": kernel_src or "generic"},
         "hbm_equivalent": {"achieved": round(achieved_hbm, 2), "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": round(achieved_hbm / HBM_PEAK_GBS, 4),
                            "alg_bytes_per_launch": r["alg_bytes"],

@@ -62,7 +62,10 @@ typedef enum {
 #define LDPC_LAYOUT_HBM 2       /* messages in the caller's workspace (device memory) */
 #define LDPC_LAYOUT_REG 3       /* messages in registers, one workgroup of 1024 threads per
                                    frame (single-scan INT8/1BIT; codes with an instantiated
-                                   shape, see ldpc_code_info.reg_*); AUTO prefers it */
+                                   shape, see ldpc_code_info.reg_* / pk_*); INT8 uses the
+                                   packed two-rows-per-lane kernel when it has a shape.
+                                   AUTO prefers this layout */
+#define LDPC_LAYOUT_REG1 4      /* as LDPC_LAYOUT_REG, one row at a time (no packing) */
 
 /*
  * Decoding parameters (Sec. III: normalisation lambda_k = alpha, offset
@@ -104,6 +107,8 @@ typedef struct {
     int32_t reg_slots;          /* register-resident shape: slots per row (0 = none) */
     int32_t reg_rows_per_thread;
     int32_t reg_zpack;          /* posterior accumulator fields per 32-bit LDS word */
+    int32_t pk_slots;           /* packed (two rows per lane) INT8 shape: slots per row (0 = none) */
+    int32_t pk_rows_per_thread;
 } ldpc_code_info;
 
 /*

@@ -25,6 +25,7 @@ struct DevCode {
     const int32_t *vc_ptr;   // [N+1] edges of variable n: vc_slot[vc_ptr[n] .. vc_ptr[n+1])
     const uint32_t *vc_slot; // [E] slot index (j*Mp + m) of each edge, ascending m
     const uint32_t *ell_reg; // [regD][regR*1024] index for the register-resident kernel (or null)
+    const uint32_t *pk_idx;  // [pkR/2][pkD][1024] x {n_a, n_b, acc_a, acc_b} for the packed kernel (or null)
 };
 
 // Everything a decode kernel needs; passed by value in the kernel arguments.
@@ -67,6 +68,8 @@ hipError_t launch_ss_int(const DecodeArgs &a, int msg, const LaunchCfg &cfg, hip
 hipError_t launch_ss_f32(const DecodeArgs &a, const LaunchCfg &cfg, hipStream_t s);
 hipError_t launch_two_scan(const DecodeArgs &a, int msg, const LaunchCfg &cfg, hipStream_t s);
 hipError_t launch_ss_reg(const DecodeArgs &a, int msg, int D, int R, int P, size_t lds, hipStream_t s);
+hipError_t launch_ss_pk(const DecodeArgs &a, int D, int R, size_t lds, hipStream_t s);
+void pk_shapes(int *out, int cap, int *count);   // (D, R) pairs
 bool reg_shape_available(int D, int R, int P);
 void reg_shapes(int *out, int cap, int *count);  // (D, R, P) triples
 constexpr int kRegThreads = 1024;

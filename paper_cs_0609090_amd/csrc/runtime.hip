@@ -23,6 +23,9 @@ struct ldpc_code {
     // register-resident shape (0 = none)
     int32_t regD = 0, regR = 0, regP = 0;
     uint32_t *d_ell_reg = nullptr;
+    // packed two-rows-per-lane INT8 shape (0 = none); uses regP's packing
+    int32_t pkD = 0, pkR = 0;
+    uint32_t *d_pk_idx = nullptr;
 };
 
 namespace {
@@ -55,7 +58,7 @@ struct DeviceGuard {
 // Per-call layout plan (which state lives in LDS, which in the workspace).
 struct Plan {
     ldpc::LaunchCfg cfg{};
-    int family = 0;  // 0: single-scan int8/1-bit, 1: single-scan fp32, 2: two-scan, 3: register-resident
+    int family = 0;  // 0: single-scan int8/1-bit, 1: single-scan fp32, 2: two-scan, 3: register-resident, 4: packed
     int zpack = 1;
     uint32_t off_zold = 0, off_zacc = 0, off_msg = 0, off_z = 0, off_aux = 0;
     uint64_t ws_off_msg = 0, ws_off_z = 0, ws_stride = 0;
@@ -75,7 +78,7 @@ ldpc_status validate_params(const ldpc_decode_params *p) {
     if (p->sched == LDPC_TWO_SCAN && p->msg == LDPC_MSG_1BIT)
         return fail(LDPC_EUNSUPPORTED, "two-scan has no 1-bit form (Sec. V compresses single-scan)");
     const uint32_t layout = (p->flags >> LDPC_F_LAYOUT_SHIFT) & 0xFu;
-    if (layout > LDPC_LAYOUT_REG) return fail(LDPC_EINVAL, "unknown layout override");
+    if (layout > LDPC_LAYOUT_REG1) return fail(LDPC_EINVAL, "unknown layout override");
     return LDPC_OK;
 }
 
@@ -91,11 +94,13 @@ ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl)
     const bool allow_lds = layout == LDPC_LAYOUT_AUTO || layout == LDPC_LAYOUT_LDS;
     const bool allow_hbm = layout == LDPC_LAYOUT_AUTO || layout == LDPC_LAYOUT_HBM;
 
+    const bool reg_layout = layout == LDPC_LAYOUT_REG || layout == LDPC_LAYOUT_REG1;
     if (p->sched == LDPC_SINGLE_SCAN && p->msg != LDPC_MSG_FP32 &&
-        (layout == LDPC_LAYOUT_AUTO || layout == LDPC_LAYOUT_REG)) {
-        const bool ok = c->regD > 0 && (p->msg == LDPC_MSG_INT8 || c->regD + 15 <= 32);
+        (layout == LDPC_LAYOUT_AUTO || reg_layout)) {
+        const bool packed = p->msg == LDPC_MSG_INT8 && c->pkD > 0 && layout != LDPC_LAYOUT_REG1;
+        const bool ok = packed || (c->regD > 0 && (p->msg == LDPC_MSG_INT8 || c->regD + 15 <= 32));
         if (ok) {
-            pl->family = 3;
+            pl->family = packed ? 4 : 3;
             const size_t zold = align_up(nz, 16);
             const size_t zacc = align_up(4 * ((size_t)c->dummy / c->regP + 1), 16);
             pl->zpack = c->regP;
@@ -107,10 +112,10 @@ ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl)
             pl->ws_stride = 0;
             return LDPC_OK;
         }
-        if (layout == LDPC_LAYOUT_REG)
+        if (reg_layout)
             return fail(LDPC_EUNSUPPORTED, "no register-resident shape for this code and message type");
     }
-    if (layout == LDPC_LAYOUT_REG) return fail(LDPC_EUNSUPPORTED, "register layout is single-scan INT8/1BIT only");
+    if (reg_layout) return fail(LDPC_EUNSUPPORTED, "register layout is single-scan INT8/1BIT only");
 
     if (p->sched == LDPC_SINGLE_SCAN && p->msg != LDPC_MSG_FP32) {
         pl->family = 0;
@@ -295,6 +300,23 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
             c->regD = bestD;
             c->regR = bestR;
             c->regP = bestP;
+            // packed kernel: any instantiated (slots, even rows/thread) covering the
+            // code; its accumulator addressing comes from the per-edge records
+            int pks[2 * 64], pcnt = 0;
+            ldpc::pk_shapes(pks, 64, &pcnt);
+            int pD = 1 << 30, pR = 1 << 30;
+            for (int i = 0; i < pcnt && i < 64; ++i) {
+                const int d = pks[2 * i], r = pks[2 * i + 1];
+                if (d < D || (int64_t)r * ldpc::kRegThreads < M) continue;
+                if (d < pD || (d == pD && r < pR)) {
+                    pD = d;
+                    pR = r;
+                }
+            }
+            if (pD < (1 << 30)) {
+                c->pkD = pD;
+                c->pkR = pR;
+            }
         }
     }
     if (device < 0) {  // host-only handle: planning and queries, no decoding
@@ -324,7 +346,37 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
                 ell_reg[(size_t)j * Mr + m] = (uint32_t)col_idx[row_ptr[m] + j];
         e4 = hipMalloc(&c->d_ell_reg, ell_reg.size() * sizeof(uint32_t));
     }
-    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {
+    std::vector<uint32_t> pk_idx;
+    hipError_t e5 = hipSuccess;
+    if (c->pkD > 0) {
+        // record {n_a, n_b, acc_a, acc_b} of slot j of rows a = p*1024 + t, b = (p + R/2)*1024 + t
+        const int T = ldpc::kRegThreads, RP = c->pkR / 2, Dk = c->pkD, Pk = c->regP;
+        const int fbits = Pk == 1 ? 32 : (Pk == 2 ? 16 : 10);
+        pk_idx.assign((size_t)RP * Dk * T * 4, 0u);
+        auto var_of = [&](int m, int j) -> uint32_t {
+            if (m >= M || j >= row_ptr[m + 1] - row_ptr[m]) return (uint32_t)c->dummy;
+            return (uint32_t)col_idx[row_ptr[m] + j];
+        };
+        // absolute LDS byte address: Z_old bytes first, the accumulator words
+        // after them (the layout make_plan uses for the register kernels)
+        const uint32_t zacc_off = (uint32_t)align_up((size_t)c->dummy + 1, 16);
+        auto acc_of = [&](uint32_t n) -> uint32_t {
+            const uint32_t w = n / (uint32_t)Pk, fld = n % (uint32_t)Pk;
+            return ((zacc_off + w * 4u) << 5) | (fld * (uint32_t)fbits);
+        };
+        for (int pp = 0; pp < RP; ++pp)
+            for (int j = 0; j < Dk; ++j)
+                for (int t = 0; t < T; ++t) {
+                    const uint32_t na = var_of(pp * T + t, j), nb = var_of((pp + RP) * T + t, j);
+                    uint32_t *r = &pk_idx[(((size_t)pp * Dk + j) * T + t) * 4];
+                    r[0] = na;
+                    r[1] = nb;
+                    r[2] = acc_of(na);
+                    r[3] = acc_of(nb);
+                }
+        e5 = hipMalloc(&c->d_pk_idx, pk_idx.size() * sizeof(uint32_t));
+    }
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || e5 != hipSuccess) {
         ldpc_code_destroy(c);
         (void)hipGetLastError();
         return fail(LDPC_ENOMEM, "device allocation failed");
@@ -333,7 +385,9 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
         hipMemcpy(c->d_vc_ptr, vc_ptr.data(), vc_ptr.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_vc_slot, vc_slot.data(), vc_slot.size() * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess ||
         (c->d_ell_reg && hipMemcpy(c->d_ell_reg, ell_reg.data(), ell_reg.size() * sizeof(uint32_t),
-                                   hipMemcpyHostToDevice) != hipSuccess)) {
+                                   hipMemcpyHostToDevice) != hipSuccess) ||
+        (c->d_pk_idx && hipMemcpy(c->d_pk_idx, pk_idx.data(), pk_idx.size() * sizeof(uint32_t),
+                                  hipMemcpyHostToDevice) != hipSuccess)) {
         ldpc_code_destroy(c);
         return fail(LDPC_EDEVICE, "copy of the code to the device failed");
     }
@@ -353,6 +407,7 @@ ldpc_status ldpc_code_destroy(ldpc_code *code) {
     if (code->d_vc_ptr) (void)hipFree(code->d_vc_ptr);
     if (code->d_vc_slot) (void)hipFree(code->d_vc_slot);
     if (code->d_ell_reg) (void)hipFree(code->d_ell_reg);
+    if (code->d_pk_idx) (void)hipFree(code->d_pk_idx);
     delete code;
     return LDPC_OK;
 }
@@ -379,6 +434,8 @@ ldpc_status ldpc_code_query(const ldpc_code *c, ldpc_code_info *o) {
     o->reg_slots = c->regD;
     o->reg_rows_per_thread = c->regR;
     o->reg_zpack = c->regP;
+    o->pk_slots = c->pkD;
+    o->pk_rows_per_thread = c->pkR;
     return LDPC_OK;
 }
 
@@ -447,6 +504,7 @@ ldpc_status ldpc_decode_batch(const ldpc_code *c, int32_t n_frames, const void *
     a.c.vc_ptr = c->d_vc_ptr;
     a.c.vc_slot = c->d_vc_slot;
     a.c.ell_reg = c->d_ell_reg;
+    a.c.pk_idx = c->d_pk_idx;
     a.n_frames = n_frames;
     a.max_iter = p->max_iter;
     a.early_stop = p->early_stop ? 1 : 0;
@@ -476,6 +534,8 @@ ldpc_status ldpc_decode_batch(const ldpc_code *c, int32_t n_frames, const void *
         e = ldpc::launch_ss_int(a, p->msg, pl.cfg, s);
     else if (pl.family == 3)
         e = ldpc::launch_ss_reg(a, p->msg, c->regD, c->regR, c->regP, pl.cfg.lds, s);
+    else if (pl.family == 4)
+        e = ldpc::launch_ss_pk(a, c->pkD, c->pkR, pl.cfg.lds, s);
     else if (pl.family == 1)
         e = ldpc::launch_ss_f32(a, pl.cfg, s);
     else

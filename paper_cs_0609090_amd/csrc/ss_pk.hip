@@ -1,0 +1,277 @@
+// Register-resident single-scan min-sum, int8 messages, two check rows per
+// thread processed together in the low and high halves of 32-bit registers
+// (packed 16-bit VALU).  Same method and results as ss_reg.hip (Sec. IV,
+// Eq. 3, 6-bit fixed point); only the instruction mapping differs:
+//
+//   thread t owns the rows a = p*1024 + t and b = (p + R/2)*1024 + t for
+//   p < R/2; for every slot j the pair (row a, row b) is one 16-bit lane pair:
+//     t2   = Zold2 - Lold2                  (v_pk_sub_i16; both stored +64)
+//     key2 = |t2| * 32 + j                  (v_pk_mad_u16)
+//     min2 = min(min2, max(min1, key2)), min1 = min(min1, key2)   (v_pk_*_u16)
+//     parity ^= t2                          (sign bits 15 and 31)
+//   per pair of rows: A2, B2 = normalised min1/min2, a one-hot mask of the
+//   argmin positions, B2 - A2;
+//     mag2 = A2 + (B2 - A2) * [j == argmin] (v_pk_mad_u16)
+//     L2   = sign-applied mag2, delta2 = L2 - Lold2
+//   and one LDS atomic per edge adds the delta into the posterior field.
+//
+// Per-slot index record (host-built, 16 bytes, coalesced per wavefront):
+//   { n_a, n_b, acc_a, acc_b },  acc = (LDS byte address of the accumulator
+//   word << 5) | field shift.
+// The byte address/shift pair encodes any accumulator packing, so the kernel
+// needs no division by the field count.  Z_old is stored as Z + 64 (bytes),
+// messages as L + 64.
+#include "ldpc_internal.h"
+
+namespace ldpc {
+namespace {
+
+constexpr int kT = kRegThreads;
+constexpr uint32_t kRsrcWord3 = 0x00020000u;  // raw buffer, gfx9 family
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+
+// LDS accessed by absolute byte address (the kernel declares only dynamic LDS,
+// which starts at address 0): per-edge addresses need no base add.
+typedef __attribute__((address_space(3))) uint8_t lds_u8_t;
+typedef __attribute__((address_space(3))) uint32_t lds_u32_t;
+__device__ __forceinline__ uint32_t lds_byte(uint32_t addr) { return *(lds_u8_t *)(size_t)addr; }
+__device__ __forceinline__ void lds_add(uint32_t addr, uint32_t v) {
+    __hip_atomic_fetch_add((lds_u32_t *)(size_t)addr, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ u16x2 as_u(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
+__device__ __forceinline__ i16x2 as_i(uint32_t v) { return __builtin_bit_cast(i16x2, v); }
+__device__ __forceinline__ uint32_t bits(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+__device__ __forceinline__ uint32_t bits(i16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+
+// bytes (2s, 2s+1) of w -> the low bytes of the two 16-bit halves
+__device__ __forceinline__ uint32_t pair_of(uint32_t w, int s) {
+    return __builtin_amdgcn_perm(w, w, s == 0 ? 0x0c010c00u : 0x0c030c02u);
+}
+
+template <int D, int R>
+__global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
+    static_assert(R % 2 == 0, "rows are processed in pairs");
+    constexpr int RP = R / 2;        // row pairs per thread
+    constexpr int W = (D + 1) / 2;   // registers per row pair: two slots (4 bytes) each
+    extern __shared__ __align__(16) uint8_t lds[];
+    const int tid = threadIdx.x;
+    const int f = blockIdx.x;
+    const int N = a.c.N;
+    const int P = a.zpack;
+    const uint32_t dummy = (uint32_t)a.c.dummy;
+    uint8_t *zold = lds;  // Z_old + 64 at LDS offset 0 (the planner places it there)
+    uint32_t *zacc = reinterpret_cast<uint32_t *>(lds + a.off_zacc);
+    int *flag = reinterpret_cast<int *>(lds + a.off_aux);
+    const int8_t *__restrict__ z0 = static_cast<const int8_t *>(a.llr_in) + (size_t)f * N;
+    const __amdgpu_buffer_rsrc_t rec = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)a.c.pk_idx, (short)0, RP * D * kT * 16, kRsrcWord3);
+    const int bitsP = (P == 1) ? 32 : (P == 2 ? 16 : 10);
+    const int biasP = (P == 1) ? 0 : (1 << (bitsP - 1));
+    const uint32_t maskP = (P == 1) ? 0xFFFFFFFFu : ((1u << bitsP) - 1u);
+    const int nwords = (int)(dummy / (uint32_t)P) + 1;
+
+    for (int w = tid; w < nwords; w += kT) {
+        uint32_t v = 0;
+        for (int i = 0; i < P; ++i) {
+            const int n = w * P + i;
+            const int z = n < N ? min(max((int)z0[n], -kQmax), kQmax) : 0;
+            v |= (uint32_t)(z + biasP) << (i * bitsP);
+        }
+        zacc[w] = v;
+    }
+    for (int n = tid; n <= (int)dummy; n += kT)
+        zold[n] = (uint8_t)(64 + (n < N ? min(max((int)z0[n], -kQmax), kQmax) : (n == (int)dummy ? kZoldMax : 0)));
+    if (tid == 0) *flag = 0;
+
+    uint32_t Lw[RP][W];  // byte 2s / 2s+1 of Lw[p][j/2]: slot j (s = j%2) of rows a / b, as L + 64
+#pragma unroll
+    for (int p = 0; p < RP; ++p)
+#pragma unroll
+        for (int i = 0; i < W; ++i) Lw[p][i] = 0x40404040u;
+    __syncthreads();
+
+    const uint32_t tid16 = (uint32_t)tid * 16u;
+    const uint32_t a8x2 = (uint32_t)a.a8 * 0x00010001u;
+    const uint32_t bx2 = (uint32_t)a.b_int * 0x00010001u;
+    int iters = 0;
+    bool converged = false;
+    for (int it = 1; it <= a.max_iter; ++it) {
+        uint32_t it0 = 0;  // opaque zero: keeps the index loads inside the iteration loop
+        asm volatile("" : "+s"(it0));
+#pragma unroll
+        for (int p = 0; p < RP; ++p) {
+            __builtin_amdgcn_sched_barrier(0);
+            uint32_t acc_a[D], acc_b[D], t2[D];
+            u16x2 min1 = {0xFFFF, 0xFFFF}, min2 = {0xFFFF, 0xFFFF};
+            uint32_t par = 0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const auto r4 = __builtin_amdgcn_raw_buffer_load_b128(
+                    rec, tid16, it0 + (uint32_t)((p * D + j) * kT * 16), 0);
+                const uint32_t na = r4[0], nb = r4[1];
+                acc_a[j] = r4[2];
+                acc_b[j] = r4[3];
+                const u16x2 zv = {(unsigned short)lds_byte(na), (unsigned short)lds_byte(nb)};
+                const uint32_t z2 = bits(zv);
+                const uint32_t l2 = pair_of(Lw[p][j >> 1], j & 1);
+                const i16x2 t = as_i(z2) - as_i(l2);  // Z_old - L_old per row
+                t2[j] = bits(t);
+                par ^= bits(t);
+                const i16x2 mag = __builtin_elementwise_max(t, -t);
+                const u16x2 key = as_u(bits(mag)) * (u16x2){32, 32} + (u16x2){(unsigned short)j, (unsigned short)j};
+                min2 = __builtin_elementwise_min(min2, __builtin_elementwise_max(min1, key));
+                min1 = __builtin_elementwise_min(min1, key);
+            }
+            // per row pair: normalised magnitudes (saturated to 31 first), argmin one-hot
+            const u16x2 m1 = __builtin_elementwise_min(min1 >> (u16x2){5, 5}, (u16x2){31, 31});
+            const u16x2 m2 = __builtin_elementwise_min(min2 >> (u16x2){5, 5}, (u16x2){31, 31});
+            const u16x2 idx = min1 & (u16x2){31, 31};
+            const i16x2 Ar = as_i(bits((m1 * as_u(a8x2) + (u16x2){128, 128}) >> (u16x2){8, 8})) - as_i(bx2);
+            const i16x2 Br = as_i(bits((m2 * as_u(a8x2) + (u16x2){128, 128}) >> (u16x2){8, 8})) - as_i(bx2);
+            const i16x2 Am = __builtin_elementwise_max(Ar, (i16x2){0, 0});
+            const i16x2 Dm = __builtin_elementwise_max(Br, (i16x2){0, 0}) - Am;  // B - A >= 0
+            // sign of the whole row's product folded in once per row: the
+            // message of slot j is then flipped only by the sign of t_j
+            const i16x2 ps = as_i(par) >> (i16x2){15, 15};
+            uint32_t A2 = bits((Am ^ ps) - ps);
+            uint32_t D2 = bits((Dm ^ ps) - ps);
+            uint32_t oh = bits((u16x2){1, 1} << idx);
+            asm volatile("" : "+v"(A2), "+v"(D2), "+v"(oh));
+            uint32_t nl[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const uint32_t sel = (oh >> j) & 0x00010001u;
+                const u16x2 mag = as_u(sel) * as_u(D2) + as_u(A2);  // signed by the row parity
+                const i16x2 sm = as_i(t2[j]) >> (i16x2){15, 15};   // 0 or -1: own sign
+                const i16x2 lnew = (as_i(bits(mag)) ^ sm) - sm;
+                const i16x2 lb = lnew + (i16x2){64, 64};
+                nl[j] = bits(lb);
+                const uint32_t l2 = pair_of(Lw[p][j >> 1], j & 1);
+                const uint32_t d = bits(lb - as_i(l2));
+                const int da = (int)(d << 16) >> 16;
+                const int db = (int)d >> 16;
+                lds_add(acc_a[j] >> 5, (uint32_t)da << (acc_a[j] & 31u));
+                lds_add(acc_b[j] >> 5, (uint32_t)db << (acc_b[j] & 31u));
+            }
+#pragma unroll
+            for (int i = 0; i < W; ++i) {
+                const uint32_t lo = nl[2 * i];
+                const uint32_t hi = (2 * i + 1 < D) ? nl[2 * i + 1] : 0x00400040u;
+                Lw[p][i] = __builtin_amdgcn_perm(hi, lo, 0x06040200u);
+                asm volatile("" : "+v"(Lw[p][i]));
+            }
+        }
+        __syncthreads();
+        if (tid == 0) *flag = 0;
+        for (int w = tid; w < nwords; w += kT) {
+            const uint32_t v = zacc[w];
+            for (int i = 0; i < P; ++i) {
+                const int n = w * P + i;
+                if (n < N) {
+                    const int z = (P == 1) ? (int)v : (int)((v >> (i * bitsP)) & maskP) - biasP;
+                    zold[n] = (uint8_t)(64 + min(max(z, -kZoldMax), kZoldMax));
+                }
+            }
+        }
+        __syncthreads();
+        iters = it;
+        if (a.early_stop) {
+            for (int p = 0; p < RP; ++p) {
+                int pa = 0, pb = 0;
+                for (int j = 0; j < D; ++j) {
+                    const auto r4 = __builtin_amdgcn_raw_buffer_load_b128(
+                        rec, tid16, (uint32_t)((p * D + j) * kT * 16), 0);
+                    pa ^= zold[r4[0]] <= 64 ? 1 : 0;
+                    pb ^= zold[r4[1]] <= 64 ? 1 : 0;
+                }
+                if (pa | pb) atomicOr(flag, 1);
+            }
+            __syncthreads();
+            if (*flag == 0) {
+                converged = true;
+                break;
+            }
+        }
+    }
+    int ok = 1;
+    if (!converged) {
+        __syncthreads();
+        if (tid == 0) *flag = 0;
+        __syncthreads();
+        for (int p = 0; p < RP; ++p) {
+            int pa = 0, pb = 0;
+            for (int j = 0; j < D; ++j) {
+                const auto r4 = __builtin_amdgcn_raw_buffer_load_b128(
+                    rec, tid16, (uint32_t)((p * D + j) * kT * 16), 0);
+                pa ^= zold[r4[0]] <= 64 ? 1 : 0;
+                pb ^= zold[r4[1]] <= 64 ? 1 : 0;
+            }
+            if (pa | pb) atomicOr(flag, 1);
+        }
+        __syncthreads();
+        ok = (*flag == 0);
+    }
+    for (int n = tid; n < N; n += kT) {
+        const uint32_t w = (P == 1) ? (uint32_t)n : (P == 2 ? (uint32_t)n >> 1 : (uint32_t)n / 3u);
+        const int i = n - (int)w * P;
+        const uint32_t v = zacc[w];
+        const int z = (P == 1) ? (int)v : (int)((v >> (i * bitsP)) & maskP) - biasP;
+        a.hard_out[(size_t)f * N + n] = z <= 0 ? 1 : 0;
+        if (a.llr_out) a.llr_out[(size_t)f * N + n] = (float)((double)z * a.step);
+    }
+    if (tid == 0) {
+        a.iters_out[f] = iters;
+        a.ok_out[f] = (uint8_t)ok;
+    }
+}
+
+template <int D, int R>
+hipError_t launch_one(const DecodeArgs &a, size_t lds, hipStream_t s) {
+    auto kern = ss_pk_kernel<D, R>;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)a.n_frames), dim3(kT), lds, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// Instantiated (slots per row, rows per thread) shapes of the packed kernel.
+#define LDPC_PK_SHAPES(X) \
+    X(6, 2)               \
+    X(6, 4)               \
+    X(7, 8)               \
+    X(7, 16)              \
+    X(7, 32)              \
+    X(8, 8)               \
+    X(8, 16)              \
+    X(8, 32)
+
+void pk_shapes(int *out, int cap, int *count) {
+    int i = 0;
+#define X(d, r)              \
+    if (i < cap) {           \
+        out[2 * i] = d;      \
+        out[2 * i + 1] = r;  \
+    }                        \
+    ++i;
+    LDPC_PK_SHAPES(X)
+#undef X
+    *count = i;
+}
+
+hipError_t launch_ss_pk(const DecodeArgs &a, int D, int R, size_t lds, hipStream_t s) {
+#define X(d, r) \
+    if (D == d && R == r) return launch_one<d, r>(a, lds, s);
+    LDPC_PK_SHAPES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+}  // namespace ldpc

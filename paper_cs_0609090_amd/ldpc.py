@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "EBADCODE", 3: "ENOMEM", 4: "EDEVICE", 
 MSG = {"fp32": 0, "int8": 1, "1bit": 2}
 SCHED = {"single_scan": 0, "two_scan": 1}
 F_CHECK_INPUT = 0x1
-LAYOUT = {"auto": 0, "lds": 1, "hbm": 2, "reg": 3}
+LAYOUT = {"auto": 0, "lds": 1, "hbm": 2, "reg": 3, "reg1": 4}
 LAYOUT_SHIFT = 8
 
 EXPORTS = ("ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query",
@@ -54,7 +54,8 @@ class CodeInfo(ctypes.Structure):
                 ("addr_bytes_single", ctypes.c_int64), ("addr_bytes_two", ctypes.c_int64),
                 ("msg_bits_int8", ctypes.c_int64), ("msg_bits_1bit", ctypes.c_int64),
                 ("lds_bytes_per_cu", ctypes.c_int32), ("reg_slots", ctypes.c_int32),
-                ("reg_rows_per_thread", ctypes.c_int32), ("reg_zpack", ctypes.c_int32)]
+                ("reg_rows_per_thread", ctypes.c_int32), ("reg_zpack", ctypes.c_int32),
+                ("pk_slots", ctypes.c_int32), ("pk_rows_per_thread", ctypes.c_int32)]
 
 
 _lib = None

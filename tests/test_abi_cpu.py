@@ -144,9 +144,11 @@ def test_workspace_plans(L):
     big = L.Code.from_parity_check(W.code_c2_ira64800(), device=-1)
     info = big.info()
     assert (info["reg_slots"], info["reg_rows_per_thread"], info["reg_zpack"]) == (7, 32, 3)
+    assert (info["pk_slots"], info["pk_rows_per_thread"]) == (7, 32)
     for msg in ("int8", "1bit"):
         assert big.workspace_size(4, L.make_params(msg=msg)) == 0
         assert big.workspace_size(4, L.make_params(msg=msg, layout="reg")) == 0
+        assert big.workspace_size(4, L.make_params(msg=msg, layout="reg1")) == 0
         assert big.workspace_size(4, L.make_params(msg=msg, layout="hbm")) > 0
     assert big.workspace_size(4, L.make_params(msg="fp32")) > 0
     with pytest.raises(L.LdpcError) as ei:

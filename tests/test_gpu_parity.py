@@ -108,8 +108,10 @@ def test_golden_tiny(torch_dev, L, orc):
 
 
 @pytest.mark.parametrize("variant", VARIANTS, ids=lambda v: f"{v[0]}-{v[1]}")
-@pytest.mark.parametrize("layout", ["auto", "lds", "hbm"])
+@pytest.mark.parametrize("layout", ["auto", "reg1", "lds", "hbm"])
 def test_random_small_codes(torch_dev, L, orc, variant, layout):
+    if layout == "reg1" and variant[0] == "fp32":
+        pytest.skip("register layouts are fixed-point only")
     rng = np.random.default_rng(123)
     for i in range(14):
         M = int(rng.integers(3, 40))
@@ -123,8 +125,13 @@ def test_random_small_codes(torch_dev, L, orc, variant, layout):
             x = rng.integers(-31, 32, size=(F, N)).astype(np.int8)
         for alpha, beta, es in ((0.8, 0.0, True), (1.0, 0.0, False), (0.75, 0.5, False),
                                 (0.9, 1.5, True)):
+            lay = layout
+            if layout == "reg1":
+                rs = L.Code.from_parity_check(code, device=-1).info()["reg_slots"]
+                if variant[1] != "single_scan" or rs == 0 or (variant[0] == "1bit" and rs + 15 > 32):
+                    lay = "auto"
             _run_pair(torch_dev, L, orc, code, x, variant, max_iter=int(rng.integers(0, 12)),
-                      alpha=alpha, beta=beta, early_stop=es, layout=layout)
+                      alpha=alpha, beta=beta, early_stop=es, layout=lay)
 
 
 @pytest.mark.parametrize("variant", VARIANTS, ids=lambda v: f"{v[0]}-{v[1]}")
@@ -138,11 +145,13 @@ def test_peg1008_full_config(torch_dev, L, orc, variant):
     assert r["ok"].sum() > 150  # most frames decode at 2 dB
 
 
-@pytest.mark.parametrize("variant", VARIANTS[:3], ids=lambda v: f"{v[0]}-{v[1]}")
-def test_ira16200(torch_dev, L, orc, variant):
+@pytest.mark.parametrize("variant,layout", [(v, "auto") for v in VARIANTS[:3]] + [(VARIANTS[0], "reg1")],
+                         ids=lambda v: v if isinstance(v, str) else f"{v[0]}-{v[1]}")
+def test_ira16200(torch_dev, L, orc, variant, layout):
     code = W.code_ira16200()
     x = _inputs(code, 24, 1.2, (0x16, 2), variant[0])
-    _run_pair(torch_dev, L, orc, code, x, variant, max_iter=25, alpha=0.8, early_stop=True)
+    _run_pair(torch_dev, L, orc, code, x, variant, max_iter=25, alpha=0.8, early_stop=True,
+              layout=layout)
 
 
 @pytest.mark.parametrize("variant,layout", [(VARIANTS[0], "auto"), (VARIANTS[0], "lds"),
@@ -160,7 +169,7 @@ def test_qc7493_batch_sampled(torch_dev, L, orc, variant, layout):
 
 
 @pytest.mark.parametrize("variant,layout", [(v, "auto") for v in VARIANTS] +
-                         [(VARIANTS[0], "hbm"), (VARIANTS[1], "hbm")],
+                         [(VARIANTS[0], "hbm"), (VARIANTS[1], "hbm"), (VARIANTS[0], "reg1")],
                          ids=lambda v: v if isinstance(v, str) else f"{v[0]}-{v[1]}")
 def test_ira64800_bench_config_sampled(torch_dev, L, orc, variant, layout):
     """N=64800 IRA code in the benchmark configuration (512 frames, 1 dB,
@@ -173,13 +182,17 @@ def test_ira64800_bench_config_sampled(torch_dev, L, orc, variant, layout):
 
 
 def test_register_path_selected(torch_dev, L):
-    """The fixed-point single-scan path of every workload code runs on the
-    register-resident kernel (shape chosen at create time)."""
-    for code, shape in ((W.code_c0_peg1008(), (6, 1, 1)), (W.code_ira16200(), (7, 8, 1)),
-                        (W.code_c1_qc7493(), (21, 3, 1)), (W.code_c2_ira64800(), (7, 32, 3))):
+    """The fixed-point single-scan path of every workload code runs on a
+    register-resident kernel (shapes chosen at create time); int8 on the
+    packed two-rows-per-lane kernel where it has a shape."""
+    for code, shape, pk in ((W.code_c0_peg1008(), (6, 1, 1), (6, 2)),
+                            (W.code_ira16200(), (7, 8, 1), (7, 8)),
+                            (W.code_c1_qc7493(), (21, 3, 1), (0, 0)),
+                            (W.code_c2_ira64800(), (7, 32, 3), (7, 32))):
         gc = L.Code.from_parity_check(code)
         i = gc.info()
         assert (i["reg_slots"], i["reg_rows_per_thread"], i["reg_zpack"]) == shape, code.name
+        assert (i["pk_slots"], i["pk_rows_per_thread"]) == pk, code.name
         gc.close()
 
 
@@ -197,9 +210,10 @@ def test_layout_and_batch_invariance(torch_dev, L, msg, sched):
     a = _gpu(torch_dev, L, gc, x, msg, sched, layout="lds", **kw)
     b = _gpu(torch_dev, L, gc, x, msg, sched, layout="hbm", **kw)
     if sched == "single_scan" and msg != "fp32":
-        r = _gpu(torch_dev, L, gc, x, msg, sched, layout="reg", **kw)
-        for k in ("hard", "llr", "iters", "ok"):
-            np.testing.assert_array_equal(a[k], r[k])
+        for lay in ("reg", "reg1"):
+            r = _gpu(torch_dev, L, gc, x, msg, sched, layout=lay, **kw)
+            for k in ("hard", "llr", "iters", "ok"):
+                np.testing.assert_array_equal(a[k], r[k])
     c = _gpu(torch_dev, L, gc, x[::-1].copy(), msg, sched, **kw)
     d = _gpu(torch_dev, L, gc, x[5:9], msg, sched, **kw)
     for k in ("hard", "llr", "iters", "ok"):
