@@ -45,6 +45,10 @@ ALG_OPS_PER_ROW = 10
 # hash of the kernel source the counters were taken on; any other source
 # reports traffic as null.
 MEASURED_TRAFFIC = {
+    "ss_pk.hip": {
+        "9e5ac36d83a8d64a": {"bytes": 240.5e6, "workload": ("int8", 512, 50),
+                             "profile": "profiles/ss_pk_int8_ira64800_512f.md"},
+    },
     "ss_reg.hip": {
         "2cb1e30dc64ed9f4": {"bytes": 221.3e6, "workload": ("int8", 512, 50),
                              "profile": "profiles/ss_reg_int8_ira64800_512f.md"},
