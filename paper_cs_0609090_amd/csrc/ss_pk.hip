@@ -6,12 +6,13 @@
 //   thread t owns the rows a = p*1024 + t and b = (p + R/2)*1024 + t for
 //   p < R/2; for every slot j the pair (row a, row b) is one 16-bit lane pair:
 //     t2   = Zold2 - Lold2                  (v_pk_sub_i16; both stored +64)
-//     key2 = |t2| * 32 + j                  (v_pk_mad_u16)
-//     min2 = min(min2, max(min1, key2)), min1 = min(min1, key2)   (v_pk_*_u16)
+//     m2   = |t2|
+//     min2 = min(min2, max(min1, m2)), min1 = min(min1, m2)   (v_pk_*_u16)
 //     parity ^= t2                          (sign bits 15 and 31)
-//   per pair of rows: A2, B2 = normalised min1/min2, a one-hot mask of the
-//   argmin positions, B2 - A2;
-//     mag2 = A2 + (B2 - A2) * [j == argmin] (v_pk_mad_u16)
+//   per pair of rows: A2, B2 = normalised min1/min2 (signed by the row parity);
+//     mag2 = |t2| == min1 ? B2 : A2         (one v_bfi_b32 on a per-row mask)
+//   i.e. B where |t_j| equals the row minimum and A elsewhere: no argmin is
+//   needed, since a tie at the minimum forces min2 = min1 and so A = B.
 //     L2   = sign-applied mag2, delta2 = L2 - Lold2
 //   and one LDS atomic per edge adds the delta into the posterior field.
 //
@@ -104,7 +105,7 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
 #pragma unroll
         for (int p = 0; p < RP; ++p) {
             __builtin_amdgcn_sched_barrier(0);
-            uint32_t acc_a[D], acc_b[D], t2[D];
+            uint32_t acc_a[D], acc_b[D], t2[D], lo2[D], mg2[D];
             u16x2 min1 = {0xFFFF, 0xFFFF}, min2 = {0xFFFF, 0xFFFF};
             uint32_t par = 0;
 #pragma unroll
@@ -117,40 +118,42 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
                 const u16x2 zv = {(unsigned short)lds_byte(na), (unsigned short)lds_byte(nb)};
                 const uint32_t z2 = bits(zv);
                 const uint32_t l2 = pair_of(Lw[p][j >> 1], j & 1);
+                lo2[j] = l2;
                 const i16x2 t = as_i(z2) - as_i(l2);  // Z_old - L_old per row
                 t2[j] = bits(t);
                 par ^= bits(t);
-                const i16x2 mag = __builtin_elementwise_max(t, -t);
-                const u16x2 key = as_u(bits(mag)) * (u16x2){32, 32} + (u16x2){(unsigned short)j, (unsigned short)j};
-                min2 = __builtin_elementwise_min(min2, __builtin_elementwise_max(min1, key));
-                min1 = __builtin_elementwise_min(min1, key);
+                const u16x2 mag = as_u(bits(__builtin_elementwise_max(t, -t)));
+                mg2[j] = bits(mag);
+                min2 = __builtin_elementwise_min(min2, __builtin_elementwise_max(min1, mag));
+                min1 = __builtin_elementwise_min(min1, mag);
             }
-            // per row pair: normalised magnitudes (saturated to 31 first), argmin one-hot
-            const u16x2 m1 = __builtin_elementwise_min(min1 >> (u16x2){5, 5}, (u16x2){31, 31});
-            const u16x2 m2 = __builtin_elementwise_min(min2 >> (u16x2){5, 5}, (u16x2){31, 31});
-            const u16x2 idx = min1 & (u16x2){31, 31};
+            // per row pair: normalised magnitudes of the saturated minima, signed
+            // once by the row parity (each message is then flipped only by its
+            // own extrinsic's sign)
+            const u16x2 m1 = __builtin_elementwise_min(min1, (u16x2){31, 31});
+            const u16x2 m2 = __builtin_elementwise_min(min2, (u16x2){31, 31});
             const i16x2 Ar = as_i(bits((m1 * as_u(a8x2) + (u16x2){128, 128}) >> (u16x2){8, 8})) - as_i(bx2);
             const i16x2 Br = as_i(bits((m2 * as_u(a8x2) + (u16x2){128, 128}) >> (u16x2){8, 8})) - as_i(bx2);
             const i16x2 Am = __builtin_elementwise_max(Ar, (i16x2){0, 0});
-            const i16x2 Dm = __builtin_elementwise_max(Br, (i16x2){0, 0}) - Am;  // B - A >= 0
-            // sign of the whole row's product folded in once per row: the
-            // message of slot j is then flipped only by the sign of t_j
+            const i16x2 Bm = __builtin_elementwise_max(Br, (i16x2){0, 0});
             const i16x2 ps = as_i(par) >> (i16x2){15, 15};
+            uint32_t B2 = bits((Bm ^ ps) - ps);
             uint32_t A2 = bits((Am ^ ps) - ps);
-            uint32_t D2 = bits((Dm ^ ps) - ps);
-            uint32_t oh = bits((u16x2){1, 1} << idx);
-            asm volatile("" : "+v"(A2), "+v"(D2), "+v"(oh));
+            uint32_t mn1 = bits(min1);
+            asm volatile("" : "+v"(B2), "+v"(A2), "+v"(mn1));
             uint32_t nl[D];
 #pragma unroll
             for (int j = 0; j < D; ++j) {
-                const uint32_t sel = (oh >> j) & 0x00010001u;
-                const u16x2 mag = as_u(sel) * as_u(D2) + as_u(A2);  // signed by the row parity
+                // |t_j| >= min1, so (min1 - |t_j|) >> 15 is 0 at the minimum and
+                // -1 elsewhere; one bit-select then picks B or A per row
+                uint32_t nsel = bits(as_i(bits(as_u(mn1) - as_u(mg2[j]))) >> (i16x2){15, 15});
+                asm volatile("" : "+v"(nsel));  // stays a mask: no per-half compares
+                const uint32_t mag = (nsel & A2) | (~nsel & B2);
                 const i16x2 sm = as_i(t2[j]) >> (i16x2){15, 15};   // 0 or -1: own sign
-                const i16x2 lnew = (as_i(bits(mag)) ^ sm) - sm;
+                const i16x2 lnew = (as_i(mag) ^ sm) - sm;
                 const i16x2 lb = lnew + (i16x2){64, 64};
                 nl[j] = bits(lb);
-                const uint32_t l2 = pair_of(Lw[p][j >> 1], j & 1);
-                const uint32_t d = bits(lb - as_i(l2));
+                const uint32_t d = bits(lb - as_i(lo2[j]));
                 const int da = (int)(d << 16) >> 16;
                 const int db = (int)d >> 16;
                 lds_add(acc_a[j] >> 5, (uint32_t)da << (acc_a[j] & 31u));
@@ -166,13 +169,40 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
         }
         __syncthreads();
         if (tid == 0) *flag = 0;
-        for (int w = tid; w < nwords; w += kT) {
-            const uint32_t v = zacc[w];
-            for (int i = 0; i < P; ++i) {
-                const int n = w * P + i;
-                if (n < N) {
-                    const int z = (P == 1) ? (int)v : (int)((v >> (i * bitsP)) & maskP) - biasP;
-                    zold[n] = (uint8_t)(64 + min(max(z, -kZoldMax), kZoldMax));
+        if (P == 3) {
+            // four accumulator words (twelve variables) per step: one 16-byte LDS
+            // read, three 4-byte writes of saturated Z_old + 64 bytes.  Bytes of
+            // variables >= N (padding, the dummy) are left untouched.
+            const int ngroups = (nwords + 3) / 4;
+            for (int g = tid; g < ngroups; g += kT) {
+                const int n0 = g * 12;
+                uint32_t v[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[q] = (g * 4 + q < nwords) ? zacc[g * 4 + q] : 0u;
+                uint32_t b[12];
+#pragma unroll
+                for (int i = 0; i < 12; ++i) {
+                    const int z = (int)((v[i / 3] >> (10 * (i % 3))) & 1023u) - 512;
+                    b[i] = (uint32_t)(64 + min(max(z, -kZoldMax), kZoldMax));
+                }
+                if (n0 + 12 <= N) {
+#pragma unroll
+                    for (int q = 0; q < 3; ++q)
+                        *reinterpret_cast<uint32_t *>(zold + n0 + 4 * q) =
+                            b[4 * q] | (b[4 * q + 1] << 8) | (b[4 * q + 2] << 16) | (b[4 * q + 3] << 24);
+                } else {
+                    for (int i = 0; i < 12 && n0 + i < N; ++i) zold[n0 + i] = (uint8_t)b[i];
+                }
+            }
+        } else {
+            for (int w = tid; w < nwords; w += kT) {
+                const uint32_t v = zacc[w];
+                for (int i = 0; i < P; ++i) {
+                    const int n = w * P + i;
+                    if (n < N) {
+                        const int z = (P == 1) ? (int)v : (int)((v >> (i * bitsP)) & maskP) - biasP;
+                        zold[n] = (uint8_t)(64 + min(max(z, -kZoldMax), kZoldMax));
+                    }
                 }
             }
         }
