@@ -25,7 +25,8 @@ struct DevCode {
     const int32_t *vc_ptr;   // [N+1] edges of variable n: vc_slot[vc_ptr[n] .. vc_ptr[n+1])
     const uint32_t *vc_slot; // [E] slot index (j*Mp + m) of each edge, ascending m
     const uint32_t *ell_reg; // [regD][regR*1024] index for the register-resident kernel (or null)
-    const uint32_t *pk_idx;  // [pkR/2][pkD][1024] x {n_a, n_b, acc_a, acc_b} for the packed kernel (or null)
+    const uint32_t *pk_idx;  // [pkR/2][pkD][1024] x {slot_a, slot_b, acc_a, acc_b} for the packed kernel (or null)
+    const uint32_t *pk_slot; // [N] posterior slot of each variable (packed kernel)
 };
 
 // Everything a decode kernel needs; passed by value in the kernel arguments.

@@ -26,6 +26,7 @@ struct ldpc_code {
     // packed two-rows-per-lane INT8 shape (0 = none); uses regP's packing
     int32_t pkD = 0, pkR = 0;
     uint32_t *d_pk_idx = nullptr;
+    uint32_t *d_pk_slot = nullptr;  // [N] posterior slot of each variable
 };
 
 namespace {
@@ -102,7 +103,8 @@ ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl)
         if (ok) {
             pl->family = packed ? 4 : 3;
             const size_t zold = align_up(nz, 16);
-            const size_t zacc = align_up(4 * ((size_t)c->dummy / c->regP + 1), 16);
+            // the packed kernel adds 64 private accumulator words for padding slots
+            const size_t zacc = align_up(4 * ((size_t)c->dummy / c->regP + 1 + (packed ? 64 : 0)), 16);
             pl->zpack = c->regP;
             pl->off_zold = 0;
             pl->off_zacc = (uint32_t)zold;
@@ -195,6 +197,79 @@ __global__ void check_input_kernel(const void *llr, int64_t count, int msg, int3
 }
 
 __global__ void zero_word_kernel(int32_t *p) { *p = 0; }
+
+// Bank-aware placement of variables into posterior slots for the packed
+// kernel.  Slot s keeps Z_old in LDS byte s (bank (s/4) mod 32) and its
+// accumulator in word s/P, field s%P (bank (zacc_off/4 + s/P) mod 32).  Each
+// LDS instruction of the row loop touches the variables of one slot of 64
+// consecutive rows, served 32 lanes at a time by the 32 banks; the greedy
+// gives every variable (highest degree first) the free slot whose two banks
+// are least used by the half-wavefronts that will touch it, so each half's 32
+// gathers and 32 atomics spread over the banks.
+std::vector<uint32_t> pk_slot_assignment(int M, int N, const int32_t *row_ptr, const int32_t *col_idx,
+                                         int pkD, int pkR, int P, uint32_t zacc_off) {
+    const int T = ldpc::kRegThreads, RP = pkR / 2, nwave = T / 32;  // half-wavefront groups
+    const int ngroups = RP * 2 * pkD * nwave;
+    std::vector<int32_t> gptr((size_t)N + 1, 0);
+    auto each_edge = [&](auto &&fn) {
+        for (int pp = 0; pp < RP; ++pp)
+            for (int h = 0; h < 2; ++h)
+                for (int j = 0; j < pkD; ++j)
+                    for (int w = 0; w < nwave; ++w) {
+                        const int g = ((pp * 2 + h) * pkD + j) * nwave + w;
+                        for (int l = 0; l < 32; ++l) {
+                            const int m = (pp + h * RP) * T + w * 32 + l;
+                            if (m < M && j < row_ptr[m + 1] - row_ptr[m]) fn(col_idx[row_ptr[m] + j], g);
+                        }
+                    }
+    };
+    each_edge([&](int n, int) { gptr[n + 1]++; });
+    for (int n = 0; n < N; ++n) gptr[n + 1] += gptr[n];
+    std::vector<int32_t> gidx(gptr[N]);
+    {
+        std::vector<int32_t> fill(gptr.begin(), gptr.end() - 1);
+        each_edge([&](int n, int g) { gidx[fill[n]++] = g; });
+    }
+    std::vector<std::vector<uint32_t>> freel(32 * 32);
+    for (int sl = N - 1; sl >= 0; --sl) {
+        const int gb = (sl >> 2) & 31, ab = (int)(((zacc_off >> 2) + (uint32_t)sl / (uint32_t)P) & 31u);
+        freel[gb * 32 + ab].push_back((uint32_t)sl);
+    }
+    std::vector<uint16_t> gcnt((size_t)ngroups * 32, 0), acnt((size_t)ngroups * 32, 0);
+    std::vector<int32_t> order(N);
+    for (int n = 0; n < N; ++n) order[n] = n;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return gptr[a + 1] - gptr[a] > gptr[b + 1] - gptr[b]; });
+    std::vector<uint32_t> slot(N);
+    for (int v : order) {
+        int gs[32] = {0}, as[32] = {0};
+        for (int k = gptr[v]; k < gptr[v + 1]; ++k) {
+            const uint16_t *gc = &gcnt[(size_t)gidx[k] * 32], *ac = &acnt[(size_t)gidx[k] * 32];
+            for (int b = 0; b < 32; ++b) {
+                gs[b] += gc[b];
+                as[b] += ac[b];
+            }
+        }
+        int best = -1;
+        int64_t bestscore = INT64_MAX;
+        for (int cb = 0; cb < 1024; ++cb) {
+            if (freel[cb].empty()) continue;
+            const int64_t sc = (int64_t)(gs[cb >> 5] + as[cb & 31]) * (1 << 20) - (int64_t)freel[cb].size();
+            if (sc < bestscore) {
+                bestscore = sc;
+                best = cb;
+            }
+        }
+        const uint32_t sl = freel[best].back();
+        freel[best].pop_back();
+        slot[v] = sl;
+        for (int k = gptr[v]; k < gptr[v + 1]; ++k) {
+            gcnt[(size_t)gidx[k] * 32 + (best >> 5)]++;
+            acnt[(size_t)gidx[k] * 32 + (best & 31)]++;
+        }
+    }
+    return slot;
+}
 
 }  // namespace
 
@@ -305,7 +380,10 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
             int pks[2 * 64], pcnt = 0;
             ldpc::pk_shapes(pks, 64, &pcnt);
             int pD = 1 << 30, pR = 1 << 30;
-            for (int i = 0; i < pcnt && i < 64; ++i) {
+            // it also keeps 64 private accumulator words for padding slots
+            const size_t need_pk = align_up((size_t)c->dummy + 1, 16) +
+                                   align_up(4 * ((size_t)c->dummy / bestP + 1 + 64), 16) + 16;
+            for (int i = 0; i < pcnt && i < 64 && need_pk <= (size_t)lds_dev; ++i) {
                 const int d = pks[2 * i], r = pks[2 * i + 1];
                 if (d < D || (int64_t)r * ldpc::kRegThreads < M) continue;
                 if (d < pD || (d == pD && r < pR)) {
@@ -346,37 +424,42 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
                 ell_reg[(size_t)j * Mr + m] = (uint32_t)col_idx[row_ptr[m] + j];
         e4 = hipMalloc(&c->d_ell_reg, ell_reg.size() * sizeof(uint32_t));
     }
-    std::vector<uint32_t> pk_idx;
-    hipError_t e5 = hipSuccess;
+    std::vector<uint32_t> pk_idx, pk_slot;
+    hipError_t e5 = hipSuccess, e6 = hipSuccess;
     if (c->pkD > 0) {
-        // record {n_a, n_b, acc_a, acc_b} of slot j of rows a = p*1024 + t, b = (p + R/2)*1024 + t
+        // record {zold_a, zold_b, acc_a, acc_b} of slot j of rows a = p*1024 + t,
+        // b = (p + R/2)*1024 + t: LDS byte address of the saturated posterior and
+        // (LDS byte address of the accumulator word << 5) | field shift
         const int T = ldpc::kRegThreads, RP = c->pkR / 2, Dk = c->pkD, Pk = c->regP;
         const int fbits = Pk == 1 ? 32 : (Pk == 2 ? 16 : 10);
-        pk_idx.assign((size_t)RP * Dk * T * 4, 0u);
-        auto var_of = [&](int m, int j) -> uint32_t {
-            if (m >= M || j >= row_ptr[m + 1] - row_ptr[m]) return (uint32_t)c->dummy;
-            return (uint32_t)col_idx[row_ptr[m] + j];
-        };
-        // absolute LDS byte address: Z_old bytes first, the accumulator words
-        // after them (the layout make_plan uses for the register kernels)
         const uint32_t zacc_off = (uint32_t)align_up((size_t)c->dummy + 1, 16);
-        auto acc_of = [&](uint32_t n) -> uint32_t {
-            const uint32_t w = n / (uint32_t)Pk, fld = n % (uint32_t)Pk;
+        const uint32_t nwords = (uint32_t)c->dummy / (uint32_t)Pk + 1;
+        pk_slot = pk_slot_assignment(M, N, row_ptr, col_idx, Dk, c->pkR, Pk, zacc_off);
+        pk_idx.assign((size_t)RP * Dk * T * 4, 0u);
+        auto acc_of_slot = [&](uint32_t sl) -> uint32_t {
+            const uint32_t w = sl / (uint32_t)Pk, fld = sl % (uint32_t)Pk;
             return ((zacc_off + w * 4u) << 5) | (fld * (uint32_t)fbits);
         };
         for (int pp = 0; pp < RP; ++pp)
             for (int j = 0; j < Dk; ++j)
-                for (int t = 0; t < T; ++t) {
-                    const uint32_t na = var_of(pp * T + t, j), nb = var_of((pp + RP) * T + t, j);
-                    uint32_t *r = &pk_idx[(((size_t)pp * Dk + j) * T + t) * 4];
-                    r[0] = na;
-                    r[1] = nb;
-                    r[2] = acc_of(na);
-                    r[3] = acc_of(nb);
-                }
+                for (int t = 0; t < T; ++t)
+                    for (int h = 0; h < 2; ++h) {
+                        const int m = (pp + h * RP) * T + t;
+                        uint32_t *r = &pk_idx[(((size_t)pp * Dk + j) * T + t) * 4];
+                        if (m < M && j < row_ptr[m + 1] - row_ptr[m]) {
+                            const uint32_t sl = pk_slot[col_idx[row_ptr[m] + j]];
+                            r[h] = sl;
+                            r[2 + h] = acc_of_slot(sl);
+                        } else {  // padding: shared Z_old byte, a private accumulator word per lane
+                            r[h] = (uint32_t)c->dummy;
+                            r[2 + h] = (zacc_off + (nwords + (uint32_t)(t & 63)) * 4u) << 5;
+                        }
+                    }
         e5 = hipMalloc(&c->d_pk_idx, pk_idx.size() * sizeof(uint32_t));
+        e6 = hipMalloc(&c->d_pk_slot, pk_slot.size() * sizeof(uint32_t));
     }
-    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || e5 != hipSuccess) {
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || e5 != hipSuccess ||
+        e6 != hipSuccess) {
         ldpc_code_destroy(c);
         (void)hipGetLastError();
         return fail(LDPC_ENOMEM, "device allocation failed");
@@ -387,7 +470,9 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
         (c->d_ell_reg && hipMemcpy(c->d_ell_reg, ell_reg.data(), ell_reg.size() * sizeof(uint32_t),
                                    hipMemcpyHostToDevice) != hipSuccess) ||
         (c->d_pk_idx && hipMemcpy(c->d_pk_idx, pk_idx.data(), pk_idx.size() * sizeof(uint32_t),
-                                  hipMemcpyHostToDevice) != hipSuccess)) {
+                                  hipMemcpyHostToDevice) != hipSuccess) ||
+        (c->d_pk_slot && hipMemcpy(c->d_pk_slot, pk_slot.data(), pk_slot.size() * sizeof(uint32_t),
+                                   hipMemcpyHostToDevice) != hipSuccess)) {
         ldpc_code_destroy(c);
         return fail(LDPC_EDEVICE, "copy of the code to the device failed");
     }
@@ -408,6 +493,7 @@ ldpc_status ldpc_code_destroy(ldpc_code *code) {
     if (code->d_vc_slot) (void)hipFree(code->d_vc_slot);
     if (code->d_ell_reg) (void)hipFree(code->d_ell_reg);
     if (code->d_pk_idx) (void)hipFree(code->d_pk_idx);
+    if (code->d_pk_slot) (void)hipFree(code->d_pk_slot);
     delete code;
     return LDPC_OK;
 }
@@ -505,6 +591,7 @@ ldpc_status ldpc_decode_batch(const ldpc_code *c, int32_t n_frames, const void *
     a.c.vc_slot = c->d_vc_slot;
     a.c.ell_reg = c->d_ell_reg;
     a.c.pk_idx = c->d_pk_idx;
+    a.c.pk_slot = c->d_pk_slot;
     a.n_frames = n_frames;
     a.max_iter = p->max_iter;
     a.early_stop = p->early_stop ? 1 : 0;

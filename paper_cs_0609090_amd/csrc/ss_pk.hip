@@ -16,12 +16,19 @@
 //     L2   = sign-applied mag2, delta2 = L2 - Lold2
 //   and one LDS atomic per edge adds the delta into the posterior field.
 //
+// Variables live in LDS "slots" chosen at code creation: slot s holds Z_old
+// in byte s and the accumulator in field s%P of word s/P, and the placement
+// spreads the variables each half-wavefront touches over the LDS banks.  The
+// slot table maps variables to slots only at load and store time.
+//
 // Per-slot index record (host-built, 16 bytes, coalesced per wavefront):
-//   { n_a, n_b, acc_a, acc_b },  acc = (LDS byte address of the accumulator
+//   { s_a, s_b, acc_a, acc_b },  acc = (LDS byte address of the accumulator
 //   word << 5) | field shift.
 // The byte address/shift pair encodes any accumulator packing, so the kernel
-// needs no division by the field count.  Z_old is stored as Z + 64 (bytes),
-// messages as L + 64.
+// needs no division by the field count; padding entries of short rows read
+// the dummy slot (Z_old at its maximum, never the row minimum) and add into a
+// private word per lane.  Z_old is stored as Z + 64 (bytes), messages as
+// L + 64.
 #include "ldpc_internal.h"
 
 namespace ldpc {
@@ -74,17 +81,23 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
     const uint32_t maskP = (P == 1) ? 0xFFFFFFFFu : ((1u << bitsP) - 1u);
     const int nwords = (int)(dummy / (uint32_t)P) + 1;
 
+    const uint32_t *__restrict__ slot_of = a.c.pk_slot;
+    for (int n = tid; n <= (int)dummy; n += kT) {
+        if (n < N)
+            zold[slot_of[n]] = (uint8_t)(64 + min(max((int)z0[n], -kQmax), kQmax));
+        else  // unused slots read as zero; the dummy slot as the largest magnitude
+            zold[n] = (uint8_t)(64 + (n == (int)dummy ? kZoldMax : 0));
+    }
+    __syncthreads();
     for (int w = tid; w < nwords; w += kT) {
         uint32_t v = 0;
         for (int i = 0; i < P; ++i) {
-            const int n = w * P + i;
-            const int z = n < N ? min(max((int)z0[n], -kQmax), kQmax) : 0;
+            const int sl = w * P + i;
+            const int z = sl < N ? (int)zold[sl] - 64 : 0;
             v |= (uint32_t)(z + biasP) << (i * bitsP);
         }
         zacc[w] = v;
     }
-    for (int n = tid; n <= (int)dummy; n += kT)
-        zold[n] = (uint8_t)(64 + (n < N ? min(max((int)z0[n], -kQmax), kQmax) : (n == (int)dummy ? kZoldMax : 0)));
     if (tid == 0) *flag = 0;
 
     uint32_t Lw[RP][W];  // byte 2s / 2s+1 of Lw[p][j/2]: slot j (s = j%2) of rows a / b, as L + 64
@@ -170,9 +183,9 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
         __syncthreads();
         if (tid == 0) *flag = 0;
         if (P == 3) {
-            // four accumulator words (twelve variables) per step: one 16-byte LDS
+            // four accumulator words (twelve slots) per step: one 16-byte LDS
             // read, three 4-byte writes of saturated Z_old + 64 bytes.  Bytes of
-            // variables >= N (padding, the dummy) are left untouched.
+            // slots >= N (unused, the dummy) are left untouched.
             const int ngroups = (nwords + 3) / 4;
             for (int g = tid; g < ngroups; g += kT) {
                 const int n0 = g * 12;
@@ -245,8 +258,9 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
         ok = (*flag == 0);
     }
     for (int n = tid; n < N; n += kT) {
-        const uint32_t w = (P == 1) ? (uint32_t)n : (P == 2 ? (uint32_t)n >> 1 : (uint32_t)n / 3u);
-        const int i = n - (int)w * P;
+        const uint32_t sl = slot_of[n];
+        const uint32_t w = (P == 1) ? sl : (P == 2 ? sl >> 1 : sl / 3u);
+        const int i = (int)(sl - w * (uint32_t)P);
         const uint32_t v = zacc[w];
         const int z = (P == 1) ? (int)v : (int)((v >> (i * bitsP)) & maskP) - biasP;
         a.hard_out[(size_t)f * N + n] = z <= 0 ? 1 : 0;
