@@ -47,6 +47,7 @@ struct DecodeArgs {
     uint64_t ws_stride;
     // layout plan
     int32_t zpack;           // Z accumulator fields per 32-bit LDS word: 1, 2 or 3
+    int32_t zbias;           // packed kernel: bias of each accumulator field (Z + zbias)
     uint32_t off_zold;       // LDS byte offsets
     uint32_t off_zacc;
     uint32_t off_msg;

@@ -25,6 +25,7 @@ struct ldpc_code {
     uint32_t *d_ell_reg = nullptr;
     // packed two-rows-per-lane INT8 shape (0 = none); uses regP's packing
     int32_t pkD = 0, pkR = 0;
+    int32_t pkBias = 0;  // accumulator field bias of the packed kernel
     uint32_t *d_pk_idx = nullptr;
     uint32_t *d_pk_slot = nullptr;  // [N] posterior slot of each variable
 };
@@ -391,9 +392,13 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
                     pR = r;
                 }
             }
-            if (pD < (1 << 30)) {
+            // 10-bit fields are biased by 320 or 576 (both 64 mod 256: the low
+            // byte of a field clamped to bias +- 62 is then Z_old + 64)
+            const int pbias = bestP == 1 ? 0 : bestP == 2 ? 32768 : span <= 320 ? 320 : span <= 447 ? 576 : -1;
+            if (pD < (1 << 30) && pbias >= 0) {
                 c->pkD = pD;
                 c->pkR = pR;
+                c->pkBias = pbias;
             }
         }
     }
@@ -608,6 +613,7 @@ ldpc_status ldpc_decode_batch(const ldpc_code *c, int32_t n_frames, const void *
     a.ws = static_cast<uint8_t *>(workspace);
     a.ws_stride = pl.ws_stride;
     a.zpack = pl.zpack;
+    a.zbias = c->pkBias;
     a.off_zold = pl.off_zold;
     a.off_zacc = pl.off_zacc;
     a.off_msg = pl.off_msg;

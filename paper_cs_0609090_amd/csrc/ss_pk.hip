@@ -54,6 +54,9 @@ __device__ __forceinline__ i16x2 as_i(uint32_t v) { return __builtin_bit_cast(i1
 __device__ __forceinline__ uint32_t bits(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
 __device__ __forceinline__ uint32_t bits(i16x2 v) { return __builtin_bit_cast(uint32_t, v); }
 
+// min(max(x, lo), hi): one v_med3_u32
+__device__ __forceinline__ uint32_t clamp_u(uint32_t x, uint32_t lo, uint32_t hi) { return min(max(x, lo), hi); }
+
 // bytes (2s, 2s+1) of w -> the low bytes of the two 16-bit halves
 __device__ __forceinline__ uint32_t pair_of(uint32_t w, int s) {
     return __builtin_amdgcn_perm(w, w, s == 0 ? 0x0c010c00u : 0x0c030c02u);
@@ -77,7 +80,7 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
     const __amdgpu_buffer_rsrc_t rec = __builtin_amdgcn_make_buffer_rsrc(
         (void *)a.c.pk_idx, (short)0, RP * D * kT * 16, kRsrcWord3);
     const int bitsP = (P == 1) ? 32 : (P == 2 ? 16 : 10);
-    const int biasP = (P == 1) ? 0 : (1 << (bitsP - 1));
+    const int biasP = a.zbias;
     const uint32_t maskP = (P == 1) ? 0xFFFFFFFFu : ((1u << bitsP) - 1u);
     const int nwords = (int)(dummy / (uint32_t)P) + 1;
 
@@ -120,7 +123,6 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
             __builtin_amdgcn_sched_barrier(0);
             uint32_t acc_a[D], acc_b[D], t2[D], lo2[D], mg2[D];
             u16x2 min1 = {0xFFFF, 0xFFFF}, min2 = {0xFFFF, 0xFFFF};
-            uint32_t par = 0;
 #pragma unroll
             for (int j = 0; j < D; ++j) {
                 const auto r4 = __builtin_amdgcn_raw_buffer_load_b128(
@@ -134,12 +136,16 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
                 lo2[j] = l2;
                 const i16x2 t = as_i(z2) - as_i(l2);  // Z_old - L_old per row
                 t2[j] = bits(t);
-                par ^= bits(t);
                 const u16x2 mag = as_u(bits(__builtin_elementwise_max(t, -t)));
                 mg2[j] = bits(mag);
                 min2 = __builtin_elementwise_min(min2, __builtin_elementwise_max(min1, mag));
                 min1 = __builtin_elementwise_min(min1, mag);
             }
+            // row sign parities (bits 15 and 31), three inputs per XOR
+            uint32_t par = t2[0];
+#pragma unroll
+            for (int j = 1; j + 1 < D; j += 2) par = __builtin_amdgcn_bitop3_b32(par, t2[j], t2[j + 1], 0x96);
+            if (D % 2 == 0) par ^= t2[D - 1];
             // per row pair: normalised magnitudes of the saturated minima, signed
             // once by the row parity (each message is then flipped only by its
             // own extrinsic's sign)
@@ -162,9 +168,9 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
                 uint32_t nsel = bits(as_i(bits(as_u(mn1) - as_u(mg2[j]))) >> (i16x2){15, 15});
                 asm volatile("" : "+v"(nsel));  // stays a mask: no per-half compares
                 const uint32_t mag = (nsel & A2) | (~nsel & B2);
-                const i16x2 sm = as_i(t2[j]) >> (i16x2){15, 15};   // 0 or -1: own sign
-                const i16x2 lnew = (as_i(mag) ^ sm) - sm;
-                const i16x2 lb = lnew + (i16x2){64, 64};
+                // own sign +-1, then L_new + 64 in one multiply-add
+                const i16x2 sg = (as_i(t2[j]) >> (i16x2){15, 15}) | (i16x2){1, 1};
+                const i16x2 lb = as_i(mag) * sg + (i16x2){64, 64};
                 nl[j] = bits(lb);
                 const uint32_t d = bits(lb - as_i(lo2[j]));
                 const int da = (int)(d << 16) >> 16;
@@ -184,25 +190,31 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
         if (tid == 0) *flag = 0;
         if (P == 3) {
             // four accumulator words (twelve slots) per step: one 16-byte LDS
-            // read, three 4-byte writes of saturated Z_old + 64 bytes.  Bytes of
-            // slots >= N (unused, the dummy) are left untouched.
+            // read, three 4-byte writes.  The field bias is 64 mod 256, so the
+            // low byte of a field clamped to [bias - 62, bias + 62] is the
+            // saturated Z_old + 64.  Words past the last one are private
+            // padding words (read, never used); bytes of slots >= N (unused,
+            // the dummy) are left untouched.
+            const uint32_t zlo = (uint32_t)(biasP - kZoldMax), zhi = (uint32_t)(biasP + kZoldMax);
             const int ngroups = (nwords + 3) / 4;
             for (int g = tid; g < ngroups; g += kT) {
                 const int n0 = g * 12;
-                uint32_t v[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) v[q] = (g * 4 + q < nwords) ? zacc[g * 4 + q] : 0u;
+                const uint4 v = *reinterpret_cast<const uint4 *>(zacc + 4 * g);
+                const uint32_t vw[4] = {v.x, v.y, v.z, v.w};
                 uint32_t b[12];
 #pragma unroll
-                for (int i = 0; i < 12; ++i) {
-                    const int z = (int)((v[i / 3] >> (10 * (i % 3))) & 1023u) - 512;
-                    b[i] = (uint32_t)(64 + min(max(z, -kZoldMax), kZoldMax));
+                for (int q = 0; q < 4; ++q) {
+                    b[3 * q] = clamp_u(vw[q] & 1023u, zlo, zhi);
+                    b[3 * q + 1] = clamp_u((vw[q] >> 10) & 1023u, zlo, zhi);
+                    b[3 * q + 2] = clamp_u(vw[q] >> 20, zlo, zhi);
                 }
                 if (n0 + 12 <= N) {
 #pragma unroll
-                    for (int q = 0; q < 3; ++q)
-                        *reinterpret_cast<uint32_t *>(zold + n0 + 4 * q) =
-                            b[4 * q] | (b[4 * q + 1] << 8) | (b[4 * q + 2] << 16) | (b[4 * q + 3] << 24);
+                    for (int q = 0; q < 3; ++q) {
+                        const uint32_t lo = __builtin_amdgcn_perm(b[4 * q + 1], b[4 * q], 0x0c0c0400u);
+                        const uint32_t hi = __builtin_amdgcn_perm(b[4 * q + 3], b[4 * q + 2], 0x04000c0cu);
+                        *reinterpret_cast<uint32_t *>(zold + n0 + 4 * q) = lo | hi;
+                    }
                 } else {
                     for (int i = 0; i < 12 && n0 + i < N; ++i) zold[n0 + i] = (uint8_t)b[i];
                 }
