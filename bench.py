@@ -138,7 +138,7 @@ def main():
     ap.add_argument("--frames", type=int, default=512)
     ap.add_argument("--msg", default="int8", choices=["int8", "1bit", "fp32"])
     ap.add_argument("--sched", default="single_scan", choices=["single_scan", "two_scan"])
-    ap.add_argument("--layout", default="auto", choices=["auto", "lds", "hbm", "reg", "reg1"])
+    ap.add_argument("--layout", default="auto", choices=["auto", "lds", "hbm", "reg", "reg1", "frames"])
     ap.add_argument("--cpu-frames", type=int, default=192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")

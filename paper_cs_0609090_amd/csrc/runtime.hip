@@ -28,6 +28,11 @@ struct ldpc_code {
     int32_t pkBias = 0;  // accumulator field bias of the packed kernel
     uint32_t *d_pk_idx = nullptr;
     uint32_t *d_pk_slot = nullptr;  // [N] posterior slot of each variable
+    // frames-across-lanes binary32 path: CSR rows and, per edge, {variable,
+    // position of the edge in variable-major order}
+    int32_t *d_row_ptr = nullptr;
+    uint32_t *d_row_ent = nullptr;
+    int32_t cu_count = 256;
 };
 
 namespace {
@@ -60,7 +65,8 @@ struct DeviceGuard {
 // Per-call layout plan (which state lives in LDS, which in the workspace).
 struct Plan {
     ldpc::LaunchCfg cfg{};
-    int family = 0;  // 0: single-scan int8/1-bit, 1: single-scan fp32, 2: two-scan, 3: register-resident, 4: packed
+    int family = 0;  // 0: single-scan int8/1-bit, 1: single-scan fp32, 2: two-scan, 3: register-resident,
+                     // 4: packed, 5: fp32 frames across lanes
     int zpack = 1;
     uint32_t off_zold = 0, off_zacc = 0, off_msg = 0, off_z = 0, off_aux = 0;
     uint64_t ws_off_msg = 0, ws_off_z = 0, ws_stride = 0;
@@ -80,7 +86,7 @@ ldpc_status validate_params(const ldpc_decode_params *p) {
     if (p->sched == LDPC_TWO_SCAN && p->msg == LDPC_MSG_1BIT)
         return fail(LDPC_EUNSUPPORTED, "two-scan has no 1-bit form (Sec. V compresses single-scan)");
     const uint32_t layout = (p->flags >> LDPC_F_LAYOUT_SHIFT) & 0xFu;
-    if (layout > LDPC_LAYOUT_REG1) return fail(LDPC_EINVAL, "unknown layout override");
+    if (layout > LDPC_LAYOUT_FRAMES) return fail(LDPC_EINVAL, "unknown layout override");
     return LDPC_OK;
 }
 
@@ -119,6 +125,12 @@ ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl)
             return fail(LDPC_EUNSUPPORTED, "no register-resident shape for this code and message type");
     }
     if (reg_layout) return fail(LDPC_EUNSUPPORTED, "register layout is single-scan INT8/1BIT only");
+    if (layout == LDPC_LAYOUT_FRAMES) {
+        if (p->sched != LDPC_SINGLE_SCAN || p->msg != LDPC_MSG_FP32)
+            return fail(LDPC_EUNSUPPORTED, "frames-across-lanes layout is single-scan FP32 only");
+        pl->family = 5;
+        return LDPC_OK;
+    }
 
     if (p->sched == LDPC_SINGLE_SCAN && p->msg != LDPC_MSG_FP32) {
         pl->family = 0;
@@ -157,6 +169,11 @@ ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl)
         pl->family = 1;
         msg = align_up((size_t)4 * D * Mp, 16);
         zb = align_up(4 * nz, 16);
+        // messages that do not fit on chip stream through HBM frames-across-lanes
+        if (layout == LDPC_LAYOUT_AUTO && zb + msg + aux > limit) {
+            pl->family = 5;
+            return LDPC_OK;
+        }
     } else {
         pl->family = 2;
         const size_t esz = p->msg == LDPC_MSG_INT8 ? 1 : 4;
@@ -336,12 +353,15 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
         vc_ptr[n + 1] += vc_ptr[n];
     }
     std::vector<uint32_t> vc_slot((size_t)std::max<int64_t>(nnz, 1));
+    std::vector<uint32_t> row_ent((size_t)2 * std::max<int64_t>(nnz, 1));
     std::vector<int32_t> fill(vc_ptr.begin(), vc_ptr.end() - 1);
     for (int m = 0; m < M; ++m)
         for (int j = 0; j < row_ptr[m + 1] - row_ptr[m]; ++j) {
             const int n = col_idx[row_ptr[m] + j];
             const uint32_t slot = (uint32_t)((size_t)j * c->Mp + m);
             ell[slot] = (uint32_t)n;
+            row_ent[2 * (size_t)(row_ptr[m] + j)] = (uint32_t)n;
+            row_ent[2 * (size_t)(row_ptr[m] + j) + 1] = (uint32_t)fill[n];
             vc_slot[fill[n]++] = slot;  // rows visited in ascending order
         }
 
@@ -413,10 +433,14 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
         delete c;
         return fail(LDPC_EDEVICE, "hipSetDevice failed");
     }
-    int lds = 0;
+    int lds = 0, cus = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
         c->lds_limit = lds;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        c->cu_count = cus;
     hipError_t e1 = hipMalloc(&c->d_ell, slots * sizeof(uint32_t));
+    hipError_t e7 = hipMalloc(&c->d_row_ptr, ((size_t)M + 1) * sizeof(int32_t));
+    hipError_t e8 = hipMalloc(&c->d_row_ent, row_ent.size() * sizeof(uint32_t));
     hipError_t e2 = hipMalloc(&c->d_vc_ptr, vc_ptr.size() * sizeof(int32_t));
     hipError_t e3 = hipMalloc(&c->d_vc_slot, vc_slot.size() * sizeof(uint32_t));
     std::vector<uint32_t> ell_reg;
@@ -464,7 +488,7 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
         e6 = hipMalloc(&c->d_pk_slot, pk_slot.size() * sizeof(uint32_t));
     }
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || e5 != hipSuccess ||
-        e6 != hipSuccess) {
+        e6 != hipSuccess || e7 != hipSuccess || e8 != hipSuccess) {
         ldpc_code_destroy(c);
         (void)hipGetLastError();
         return fail(LDPC_ENOMEM, "device allocation failed");
@@ -472,6 +496,9 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
     if (hipMemcpy(c->d_ell, ell.data(), slots * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_vc_ptr, vc_ptr.data(), vc_ptr.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_vc_slot, vc_slot.data(), vc_slot.size() * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_row_ptr, row_ptr, ((size_t)M + 1) * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_row_ent, row_ent.data(), row_ent.size() * sizeof(uint32_t), hipMemcpyHostToDevice) !=
+            hipSuccess ||
         (c->d_ell_reg && hipMemcpy(c->d_ell_reg, ell_reg.data(), ell_reg.size() * sizeof(uint32_t),
                                    hipMemcpyHostToDevice) != hipSuccess) ||
         (c->d_pk_idx && hipMemcpy(c->d_pk_idx, pk_idx.data(), pk_idx.size() * sizeof(uint32_t),
@@ -496,6 +523,8 @@ ldpc_status ldpc_code_destroy(ldpc_code *code) {
     if (code->d_ell) (void)hipFree(code->d_ell);
     if (code->d_vc_ptr) (void)hipFree(code->d_vc_ptr);
     if (code->d_vc_slot) (void)hipFree(code->d_vc_slot);
+    if (code->d_row_ptr) (void)hipFree(code->d_row_ptr);
+    if (code->d_row_ent) (void)hipFree(code->d_row_ent);
     if (code->d_ell_reg) (void)hipFree(code->d_ell_reg);
     if (code->d_pk_idx) (void)hipFree(code->d_pk_idx);
     if (code->d_pk_slot) (void)hipFree(code->d_pk_slot);
@@ -539,7 +568,8 @@ ldpc_status ldpc_decode_workspace_size(const ldpc_code *c, int32_t n_frames,
     Plan pl;
     st = make_plan(c, p, &pl);
     if (st != LDPC_OK) return st;
-    size_t b = (size_t)pl.ws_stride * (size_t)n_frames;
+    size_t b = pl.family == 5 ? ldpc::fl_workspace_bytes(c->N, c->E, n_frames, p->max_iter)
+                              : (size_t)pl.ws_stride * (size_t)n_frames;
     if (p->flags & LDPC_F_CHECK_INPUT) b = align_up(b, 256) + 256;
     *bytes = b;
     return LDPC_OK;
@@ -558,7 +588,8 @@ ldpc_status ldpc_decode_batch(const ldpc_code *c, int32_t n_frames, const void *
     Plan pl;
     st = make_plan(c, p, &pl);
     if (st != LDPC_OK) return st;
-    size_t need = (size_t)pl.ws_stride * (size_t)n_frames;
+    size_t need = pl.family == 5 ? ldpc::fl_workspace_bytes(c->N, c->E, n_frames, p->max_iter)
+                                 : (size_t)pl.ws_stride * (size_t)n_frames;
     size_t check_off = 0;
     if (p->flags & LDPC_F_CHECK_INPUT) {
         check_off = align_up(need, 256);
@@ -631,6 +662,9 @@ ldpc_status ldpc_decode_batch(const ldpc_code *c, int32_t n_frames, const void *
         e = ldpc::launch_ss_pk(a, c->pkD, c->pkR, pl.cfg.lds, s);
     else if (pl.family == 1)
         e = ldpc::launch_ss_f32(a, pl.cfg, s);
+    else if (pl.family == 5)
+        e = ldpc::launch_ss_f32_fl(a, c->d_row_ptr, reinterpret_cast<const uint2 *>(c->d_row_ent), c->E, c->D,
+                                   c->cu_count, s);
     else
         e = ldpc::launch_two_scan(a, p->msg, pl.cfg, s);
     if (e != hipSuccess) return fail(LDPC_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));

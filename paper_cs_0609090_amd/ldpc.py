@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "EBADCODE", 3: "ENOMEM", 4: "EDEVICE", 
 MSG = {"fp32": 0, "int8": 1, "1bit": 2}
 SCHED = {"single_scan": 0, "two_scan": 1}
 F_CHECK_INPUT = 0x1
-LAYOUT = {"auto": 0, "lds": 1, "hbm": 2, "reg": 3, "reg1": 4}
+LAYOUT = {"auto": 0, "lds": 1, "hbm": 2, "reg": 3, "reg1": 4, "frames": 5}
 LAYOUT_SHIFT = 8
 
 EXPORTS = ("ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query",

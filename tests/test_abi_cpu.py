@@ -150,7 +150,18 @@ def test_workspace_plans(L):
         assert big.workspace_size(4, L.make_params(msg=msg, layout="reg")) == 0
         assert big.workspace_size(4, L.make_params(msg=msg, layout="reg1")) == 0
         assert big.workspace_size(4, L.make_params(msg=msg, layout="hbm")) > 0
-    assert big.workspace_size(4, L.make_params(msg="fp32")) > 0
+    # binary32 single-scan of the big code streams frames-across-lanes: the
+    # workspace covers the call (64-frame groups) and holds one flag row per iteration
+    f1 = big.workspace_size(1, L.make_params(msg="fp32"))
+    assert f1 == big.workspace_size(64, L.make_params(msg="fp32"))
+    assert f1 >= 64 * 4 * (3 * 64800 + 226799)
+    assert big.workspace_size(65, L.make_params(msg="fp32")) > f1
+    assert big.workspace_size(1, L.make_params(msg="fp32", max_iter=80)) > f1
+    assert big.workspace_size(1, L.make_params(msg="fp32", layout="frames")) == f1
+    for bad in (dict(msg="int8", layout="frames"), dict(msg="fp32", sched="two_scan", layout="frames")):
+        with pytest.raises(L.LdpcError) as ei:
+            big.workspace_size(4, L.make_params(**bad))
+        assert ei.value.status == L.LDPC_EUNSUPPORTED
     with pytest.raises(L.LdpcError) as ei:
         big.workspace_size(4, L.make_params(msg="fp32", layout="reg"))
     assert ei.value.status == L.LDPC_EUNSUPPORTED
