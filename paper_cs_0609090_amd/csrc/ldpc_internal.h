@@ -68,9 +68,11 @@ struct LaunchCfg {
 // Kernel launchers, one per family (defined next to their kernels).
 hipError_t launch_ss_int(const DecodeArgs &a, int msg, const LaunchCfg &cfg, hipStream_t s);
 hipError_t launch_ss_f32(const DecodeArgs &a, const LaunchCfg &cfg, hipStream_t s);
-// binary32 single-scan, frames across lanes; workspace of one call
+// binary32 single-scan, frames across lanes; workspace of one call (the
+// batch runs in chunks of fl_chunk_frames frames, 0 = code too large)
+int fl_chunk_frames(int N, int64_t E);
 size_t fl_workspace_bytes(int N, int64_t E, int n_frames, int max_iter);
-hipError_t launch_ss_f32_fl(const DecodeArgs &a, const int32_t *row_ptr, const uint2 *row_ent, int64_t E,
+hipError_t launch_ss_f32_fl(const DecodeArgs &a, const int32_t *row_ptr, const uint32_t *row_ent, int64_t E,
                             int max_row_deg, int cu_count, hipStream_t s);
 hipError_t launch_two_scan(const DecodeArgs &a, int msg, const LaunchCfg &cfg, hipStream_t s);
 hipError_t launch_ss_reg(const DecodeArgs &a, int msg, int D, int R, int P, size_t lds, hipStream_t s);

@@ -128,6 +128,8 @@ ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl)
     if (layout == LDPC_LAYOUT_FRAMES) {
         if (p->sched != LDPC_SINGLE_SCAN || p->msg != LDPC_MSG_FP32)
             return fail(LDPC_EUNSUPPORTED, "frames-across-lanes layout is single-scan FP32 only");
+        if (ldpc::fl_chunk_frames(c->N, c->E) <= 0)
+            return fail(LDPC_EUNSUPPORTED, "code too large for the frames-across-lanes layout");
         pl->family = 5;
         return LDPC_OK;
     }
@@ -170,7 +172,7 @@ ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl)
         msg = align_up((size_t)4 * D * Mp, 16);
         zb = align_up(4 * nz, 16);
         // messages that do not fit on chip stream through HBM frames-across-lanes
-        if (layout == LDPC_LAYOUT_AUTO && zb + msg + aux > limit) {
+        if (layout == LDPC_LAYOUT_AUTO && zb + msg + aux > limit && ldpc::fl_chunk_frames(c->N, c->E) > 0) {
             pl->family = 5;
             return LDPC_OK;
         }
@@ -353,7 +355,8 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
         vc_ptr[n + 1] += vc_ptr[n];
     }
     std::vector<uint32_t> vc_slot((size_t)std::max<int64_t>(nnz, 1));
-    std::vector<uint32_t> row_ent((size_t)2 * std::max<int64_t>(nnz, 1));
+    // + 64 padding entries (variable 0, position 0): a row's slots load unconditionally
+    std::vector<uint32_t> row_ent((size_t)2 * (nnz + 64), 0u);
     std::vector<int32_t> fill(vc_ptr.begin(), vc_ptr.end() - 1);
     for (int m = 0; m < M; ++m)
         for (int j = 0; j < row_ptr[m + 1] - row_ptr[m]; ++j) {
@@ -663,7 +666,7 @@ ldpc_status ldpc_decode_batch(const ldpc_code *c, int32_t n_frames, const void *
     else if (pl.family == 1)
         e = ldpc::launch_ss_f32(a, pl.cfg, s);
     else if (pl.family == 5)
-        e = ldpc::launch_ss_f32_fl(a, c->d_row_ptr, reinterpret_cast<const uint2 *>(c->d_row_ent), c->E, c->D,
+        e = ldpc::launch_ss_f32_fl(a, c->d_row_ptr, c->d_row_ent, c->E, c->D,
                                    c->cu_count, s);
     else
         e = ldpc::launch_two_scan(a, p->msg, pl.cfg, s);

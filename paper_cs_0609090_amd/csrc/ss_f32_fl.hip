@@ -38,13 +38,21 @@ namespace {
 constexpr int kWaves = 4;  // wavefronts per workgroup
 constexpr int kBlock = 64 * kWaves;
 constexpr int kNotConverged = INT_MAX;
+constexpr uint32_t kRsrcWord3 = 0x00020000u;  // raw buffer, gfx9 family
+// Byte offset of the unused slots of a short row: every array of a chunk is
+// below 2^31 bytes and a lane adds less than that, so the sum stays past the
+// end of the buffer without wrapping: loads there return 0 and touch no
+// memory, stores are dropped.
+constexpr uint32_t kOutOfRange = 0x80000000u;
 
 struct FlArgs {
     int32_t M, N, F, Fp, G;  // Fp = 64 * G frame lanes
     int32_t rwaves;          // wavefronts per frame group in the strided passes
+    uint32_t ebytes;         // bytes of the message array (E * Fp * 4 < 2^31)
     float alpha, beta;
     const int32_t *row_ptr;  // [M+1]
-    const uint2 *row_ent;    // [E] per check-to-variable edge: {variable, message position}
+    const uint32_t *row_ent; // [E + 64][2] per check-to-variable edge: {variable, message position}
+                             // (64 padding entries: a row's slots load unconditionally)
     const int32_t *vc_ptr;   // [N+1] message positions of variable n: vc_ptr[n] .. vc_ptr[n+1]
     float *z0;               // [N][Fp]
     float *zbuf[2];          // [N][Fp] posteriors of odd / even iterations
@@ -57,6 +65,29 @@ __device__ __forceinline__ float norm_f(float m, float alpha, float beta) {
     const float v = __fsub_rn(__fmul_rn(alpha, m), beta);
     return v > 0.0f ? v : 0.0f;
 }
+
+// The code's index arrays are read-only for the whole call: reading them
+// through the constant address space lets wave-uniform loads go to the
+// scalar unit (s_load) instead of the vector memory path.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T *cptr(const T *p) {
+    return (const __attribute__((address_space(4))) T *)(p);
+}
+
+// Buffer view of one frame-minor array: every access is a scalar element
+// offset (SGPR) plus the lane's frame offset (one VGPR shared by all
+// accesses), so no per-access 64-bit address is formed.
+struct Buf {
+    __amdgpu_buffer_rsrc_t r;
+    __device__ Buf(const void *p, uint32_t bytes)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, kRsrcWord3)) {}
+    __device__ float ld(uint32_t lane_off, uint32_t elem_off) const {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, lane_off, elem_off, 0));
+    }
+    __device__ void st(float v, uint32_t lane_off, uint32_t elem_off) const {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, lane_off, elem_off, 0);
+    }
+};
 
 __device__ __forceinline__ int wave_id() {
     return __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kWaves + (threadIdx.x >> 6)));
@@ -104,52 +135,61 @@ __global__ void __launch_bounds__(kBlock) fl_check(FlArgs a, const float *__rest
     if (w >= a.rwaves * a.G) return;
     const int g = w % a.G;
     const int r0 = w / a.G;
-    const int f = g * 64 + lane;
+    const uint32_t f = (uint32_t)(g * 64 + lane);
+    const uint32_t fo = f * 4u;             // lane offset in bytes
+    const uint32_t rowb = (uint32_t)Fp * 4u;  // bytes per element row
+    const Buf zb(zold, (uint32_t)a.N * rowb), lb(a.L, a.ebytes);
+    const auto *rp = cptr(a.row_ptr);
+    const auto *re = cptr(a.row_ent);
     for (int m = r0; m < a.M; m += a.rwaves) {
-        const int e0 = a.row_ptr[m];
-        const int d = a.row_ptr[m + 1] - e0;
+        const int e0 = rp[m];
+        const int d = rp[m + 1] - e0;
         float z[DMAX], t[DMAX];
-        uint32_t pos[DMAX];
-        // all loads of the row first, then the arithmetic
+        uint32_t pos[DMAX], var[DMAX];
+        // the row's index entries (scalar loads), then all its data loads, then
+        // the arithmetic, with no branch between them (slots j >= d are out of
+        // range and masked)
 #pragma unroll
         for (int j = 0; j < DMAX; ++j) {
-            if (j < d) {
-                const uint2 ent = a.row_ent[e0 + j];
-                pos[j] = ent.y;
-                z[j] = zold[(size_t)ent.x * Fp + f];
-                if (UPDATE) t[j] = FIRST ? 0.0f : a.L[(size_t)ent.y * Fp + f];
-            }
+            const uint32_t nv = re[2 * (e0 + j)], np = re[2 * (e0 + j) + 1];
+            var[j] = j < d ? nv * rowb : kOutOfRange;
+            pos[j] = j < d ? np * rowb : kOutOfRange;
+        }
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j) {
+            z[j] = zb.ld(fo, var[j]);
+            if (UPDATE) t[j] = FIRST ? 0.0f : lb.ld(fo, pos[j]);
         }
         int syn = 0, par = 0;
         float min1 = INFINITY, min2 = INFINITY;
         int idx = 0;
 #pragma unroll
         for (int j = 0; j < DMAX; ++j) {
-            if (j < d) {
-                syn ^= z[j] > 0.0f ? 0 : 1;
-                if (UPDATE) {
-                    const float tj = __fsub_rn(z[j], t[j]);
-                    t[j] = tj;
-                    par ^= tj < 0.0f ? 1 : 0;
-                    const float av = fabsf(tj);
-                    min2 = fminf(min2, fmaxf(min1, av));
-                    idx = av < min1 ? j : idx;
-                    min1 = fminf(min1, av);
-                }
+            const bool in = j < d;
+            syn ^= (in && !(z[j] > 0.0f)) ? 1 : 0;
+            if (UPDATE) {
+                const float tj = __fsub_rn(z[j], t[j]);
+                t[j] = tj;
+                par ^= (in && tj < 0.0f) ? 1 : 0;
+                const float av = in ? fabsf(tj) : INFINITY;
+                min2 = fminf(min2, fmaxf(min1, av));
+                idx = av < min1 ? j : idx;
+                min1 = fminf(min1, av);
             }
         }
         if (syn_row >= 0 && syn) a.fail[(size_t)syn_row * Fp + f] = 1;
         if (UPDATE) {
             const float A = norm_f(min1, a.alpha, a.beta);
             const float B = norm_f(min2, a.alpha, a.beta);
+            float out[DMAX];
 #pragma unroll
             for (int j = 0; j < DMAX; ++j) {
-                if (j < d) {
-                    const float mag = j == idx ? B : A;
-                    const bool neg = (par ^ (t[j] < 0.0f ? 1 : 0)) != 0;
-                    a.L[(size_t)pos[j] * Fp + f] = neg ? -mag : mag;
-                }
+                const float mag = j == idx ? B : A;
+                const bool neg = (par ^ (t[j] < 0.0f ? 1 : 0)) != 0;
+                out[j] = neg ? -mag : mag;
             }
+#pragma unroll
+            for (int j = 0; j < DMAX; ++j) lb.st(out[j], fo, pos[j]);
         }
     }
 }
@@ -164,27 +204,33 @@ __global__ void __launch_bounds__(kBlock) fl_var(FlArgs a, const float *__restri
     const int Fp = a.Fp;
     if (w >= a.rwaves * a.G) return;
     const int g = w % a.G;
-    const int f = g * 64 + lane;
+    const uint32_t f = (uint32_t)(g * 64 + lane);
+    const uint32_t fo = f * 4u;
+    const uint32_t rowb = (uint32_t)Fp * 4u;
+    const uint32_t nb = (uint32_t)a.N * rowb;
+    const Buf zo(zold, nb), zn(znew, nb), z0(a.z0, nb), lb(a.L, a.ebytes);
     bool frozen = false;
     if (FREEZE) frozen = a.conv[f] != kNotConverged || a.fail[(size_t)fail_row * Fp + f] == 0;
+    const auto *vp = cptr(a.vc_ptr);
     for (int n = w / a.G; n < a.N; n += a.rwaves) {
-        const size_t o = (size_t)n * Fp + f;
+        const uint32_t o = (uint32_t)n * rowb;
         if (FREEZE && frozen) {
-            znew[o] = zold[o];
+            zn.st(zo.ld(fo, o), fo, o);
             continue;
         }
-        const int e0 = a.vc_ptr[n], e1 = a.vc_ptr[n + 1];
-        float s = a.z0[o];
-        int e = e0;
-        for (; e + 4 <= e1; e += 4) {
-            const float l0 = a.L[(size_t)e * Fp + f];
-            const float l1 = a.L[(size_t)(e + 1) * Fp + f];
-            const float l2 = a.L[(size_t)(e + 2) * Fp + f];
-            const float l3 = a.L[(size_t)(e + 3) * Fp + f];
-            s = __fadd_rn(__fadd_rn(__fadd_rn(__fadd_rn(s, l0), l1), l2), l3);
+        const int e0 = vp[n], e1 = vp[n + 1];
+        float s = z0.ld(fo, o);
+        // eight messages per step, all loads in flight together; slots past
+        // the variable's last edge are out of range and skipped (no +0.0 is
+        // added, so the sum is exactly the ordered one)
+        for (int e = e0; e < e1; e += 8) {
+            float l[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) l[i] = lb.ld(fo, e + i < e1 ? (uint32_t)(e + i) * rowb : kOutOfRange);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) s = e + i < e1 ? __fadd_rn(s, l[i]) : s;
         }
-        for (; e < e1; ++e) s = __fadd_rn(s, a.L[(size_t)e * Fp + f]);
-        znew[o] = s;
+        zn.st(s, fo, o);
     }
 }
 
@@ -264,50 +310,80 @@ hipError_t run(const DecodeArgs &d, const FlArgs &a, int K, unsigned grid, hipSt
 
 }  // namespace
 
+// Frames per call chunk: buffer offsets are 32-bit, so every frame-minor
+// array of a chunk stays below 2 GiB (64-frame groups; 0 if even one group
+// does not fit).
+int fl_chunk_frames(int N, int64_t E) {
+    const int64_t rowmax = std::max<int64_t>(E, N) * 4 * 64;  // bytes per element row of one group
+    const int64_t groups = ((int64_t)0x7FFFFF00) / rowmax;      // arrays below 2^31 bytes
+    return (int)std::min<int64_t>(groups * 64, (int64_t)1 << 30);
+}
+
 size_t fl_workspace_bytes(int N, int64_t E, int n_frames, int max_iter) {
-    const size_t Fp = (size_t)((n_frames + 63) / 64) * 64;
+    const int chunk = fl_chunk_frames(N, E);
+    const int fr = std::min(n_frames, std::max(chunk, 1));
+    const size_t Fp = (size_t)((fr + 63) / 64) * 64;
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
     return 3 * al((size_t)N * Fp * 4) + al((size_t)E * Fp * 4) + al((size_t)(max_iter + 1) * Fp * 4) + al(Fp * 4);
 }
 
-hipError_t launch_ss_f32_fl(const DecodeArgs &d, const int32_t *row_ptr, const uint2 *row_ent, int64_t E,
+hipError_t launch_ss_f32_fl(const DecodeArgs &d, const int32_t *row_ptr, const uint32_t *row_ent, int64_t E,
                             int max_row_deg, int cu_count, hipStream_t s) {
-    FlArgs a{};
-    a.M = d.c.M;
-    a.N = d.c.N;
-    a.F = d.n_frames;
-    a.G = (d.n_frames + 63) / 64;
-    a.Fp = a.G * 64;
-    a.alpha = d.alpha;
-    a.beta = d.beta;
-    a.row_ptr = row_ptr;
-    a.row_ent = row_ent;
-    a.vc_ptr = d.c.vc_ptr;
-    const size_t Fp = (size_t)a.Fp;
-    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    uint8_t *p = d.ws;
-    a.z0 = reinterpret_cast<float *>(p);
-    p += al((size_t)a.N * Fp * 4);
-    a.zbuf[0] = reinterpret_cast<float *>(p);
-    p += al((size_t)a.N * Fp * 4);
-    a.zbuf[1] = reinterpret_cast<float *>(p);
-    p += al((size_t)a.N * Fp * 4);
-    a.L = reinterpret_cast<float *>(p);
-    p += al((size_t)E * Fp * 4);
-    a.fail = reinterpret_cast<int32_t *>(p);
-    p += al((size_t)(d.max_iter + 1) * Fp * 4);
-    a.conv = reinterpret_cast<int32_t *>(p);
-    // about 16 wavefronts per CU, split over the frame groups; wavefronts with
-    // an id past rwaves*G (the grid's rounding) return at once
-    const int64_t want = (int64_t)std::max(cu_count, 1) * 16;
-    a.rwaves = (int)std::max<int64_t>(1, std::min<int64_t>(want / a.G, std::max(a.M, a.N)));
-    const unsigned grid = (unsigned)(((int64_t)a.rwaves * a.G + kWaves - 1) / kWaves);
-    const int K = d.max_iter;
-    if (max_row_deg <= 8) return run<8>(d, a, K, grid, s);
-    if (max_row_deg <= 16) return run<16>(d, a, K, grid, s);
-    if (max_row_deg <= 32) return run<32>(d, a, K, grid, s);
-    if (max_row_deg <= 64) return run<64>(d, a, K, grid, s);
-    return hipErrorInvalidValue;
+    const int chunk = fl_chunk_frames(d.c.N, E);
+    if (chunk <= 0 || max_row_deg > 64) return hipErrorInvalidValue;
+    for (int c0 = 0; c0 < d.n_frames; c0 += chunk) {
+        const int F = std::min(chunk, d.n_frames - c0);
+        DecodeArgs dc = d;
+        dc.n_frames = F;
+        dc.llr_in = static_cast<const float *>(d.llr_in) + (size_t)c0 * d.c.N;
+        dc.hard_out = d.hard_out + (size_t)c0 * d.c.N;
+        dc.llr_out = d.llr_out ? d.llr_out + (size_t)c0 * d.c.N : nullptr;
+        dc.iters_out = d.iters_out + c0;
+        dc.ok_out = d.ok_out + c0;
+        FlArgs a{};
+        a.M = d.c.M;
+        a.N = d.c.N;
+        a.F = F;
+        a.G = (F + 63) / 64;
+        a.Fp = a.G * 64;
+        a.alpha = d.alpha;
+        a.beta = d.beta;
+        a.row_ptr = row_ptr;
+        a.row_ent = row_ent;
+        a.vc_ptr = d.c.vc_ptr;
+        const size_t Fp = (size_t)a.Fp;
+        a.ebytes = (uint32_t)((size_t)E * Fp * 4);
+        auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+        uint8_t *p = d.ws;
+        a.z0 = reinterpret_cast<float *>(p);
+        p += al((size_t)a.N * Fp * 4);
+        a.zbuf[0] = reinterpret_cast<float *>(p);
+        p += al((size_t)a.N * Fp * 4);
+        a.zbuf[1] = reinterpret_cast<float *>(p);
+        p += al((size_t)a.N * Fp * 4);
+        a.L = reinterpret_cast<float *>(p);
+        p += al((size_t)E * Fp * 4);
+        a.fail = reinterpret_cast<int32_t *>(p);
+        p += al((size_t)(d.max_iter + 1) * Fp * 4);
+        a.conv = reinterpret_cast<int32_t *>(p);
+        // about 32 wavefronts per CU, split over the frame groups; wavefronts with
+        // an id past rwaves*G (the grid's rounding) return at once
+        const int64_t want = (int64_t)std::max(cu_count, 1) * 32;
+        a.rwaves = (int)std::max<int64_t>(1, std::min<int64_t>(want / a.G, std::max(a.M, a.N)));
+        const unsigned grid = (unsigned)(((int64_t)a.rwaves * a.G + kWaves - 1) / kWaves);
+        const int K = d.max_iter;
+        hipError_t e;
+        if (max_row_deg <= 8)
+            e = run<8>(dc, a, K, grid, s);
+        else if (max_row_deg <= 16)
+            e = run<16>(dc, a, K, grid, s);
+        else if (max_row_deg <= 32)
+            e = run<32>(dc, a, K, grid, s);
+        else
+            e = run<64>(dc, a, K, grid, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace ldpc
