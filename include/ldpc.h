@@ -62,8 +62,9 @@ typedef enum {
 #define LDPC_LAYOUT_HBM 2       /* messages in the caller's workspace (device memory) */
 #define LDPC_LAYOUT_REG 3       /* messages in registers, one workgroup of 1024 threads per
                                    frame (single-scan INT8/1BIT; codes with an instantiated
-                                   shape, see ldpc_code_info.reg_* / pk_*); INT8 uses the
-                                   packed two-rows-per-lane kernel when it has a shape.
+                                   shape, see ldpc_code_info.reg_* / pk_*); INT8 and 1BIT
+                                   use the packed two-rows-per-lane kernel when it has a
+                                   shape.
                                    AUTO prefers this layout */
 #define LDPC_LAYOUT_REG1 4      /* as LDPC_LAYOUT_REG, one row at a time (no packing) */
 #define LDPC_LAYOUT_FRAMES 5    /* single-scan FP32 only: one frame per lane, 64 frames per

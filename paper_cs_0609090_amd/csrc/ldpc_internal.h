@@ -76,7 +76,7 @@ hipError_t launch_ss_f32_fl(const DecodeArgs &a, const int32_t *row_ptr, const u
                             int max_row_deg, int cu_count, hipStream_t s);
 hipError_t launch_two_scan(const DecodeArgs &a, int msg, const LaunchCfg &cfg, hipStream_t s);
 hipError_t launch_ss_reg(const DecodeArgs &a, int msg, int D, int R, int P, size_t lds, hipStream_t s);
-hipError_t launch_ss_pk(const DecodeArgs &a, int D, int R, size_t lds, hipStream_t s);
+hipError_t launch_ss_pk(const DecodeArgs &a, int D, int R, bool onebit, size_t lds, hipStream_t s);
 void pk_shapes(int *out, int cap, int *count);   // (D, R) pairs
 bool reg_shape_available(int D, int R, int P);
 void reg_shapes(int *out, int cap, int *count);  // (D, R, P) triples

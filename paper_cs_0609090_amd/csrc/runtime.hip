@@ -105,7 +105,7 @@ ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl)
     const bool reg_layout = layout == LDPC_LAYOUT_REG || layout == LDPC_LAYOUT_REG1;
     if (p->sched == LDPC_SINGLE_SCAN && p->msg != LDPC_MSG_FP32 &&
         (layout == LDPC_LAYOUT_AUTO || reg_layout)) {
-        const bool packed = p->msg == LDPC_MSG_INT8 && c->pkD > 0 && layout != LDPC_LAYOUT_REG1;
+        const bool packed = c->pkD > 0 && layout != LDPC_LAYOUT_REG1;  // int8 and 1-bit
         const bool ok = packed || (c->regD > 0 && (p->msg == LDPC_MSG_INT8 || c->regD + 15 <= 32));
         if (ok) {
             pl->family = packed ? 4 : 3;
@@ -662,7 +662,7 @@ ldpc_status ldpc_decode_batch(const ldpc_code *c, int32_t n_frames, const void *
     else if (pl.family == 3)
         e = ldpc::launch_ss_reg(a, p->msg, c->regD, c->regR, c->regP, pl.cfg.lds, s);
     else if (pl.family == 4)
-        e = ldpc::launch_ss_pk(a, c->pkD, c->pkR, pl.cfg.lds, s);
+        e = ldpc::launch_ss_pk(a, c->pkD, c->pkR, p->msg == LDPC_MSG_1BIT, pl.cfg.lds, s);
     else if (pl.family == 1)
         e = ldpc::launch_ss_f32(a, pl.cfg, s);
     else if (pl.family == 5)

@@ -1,7 +1,8 @@
-// Register-resident single-scan min-sum, int8 messages, two check rows per
-// thread processed together in the low and high halves of 32-bit registers
-// (packed 16-bit VALU).  Same method and results as ss_reg.hip (Sec. IV,
-// Eq. 3, 6-bit fixed point); only the instruction mapping differs:
+// Register-resident single-scan min-sum, int8 messages or the 1-bit state of
+// Sec. V, two check rows per thread processed together in the low and high
+// halves of 32-bit registers (packed 16-bit VALU).  Same method and results
+// as ss_reg.hip (Sec. IV, Eq. 3, 6-bit fixed point); only the instruction
+// mapping differs:
 //
 //   thread t owns the rows a = p*1024 + t and b = (p + R/2)*1024 + t for
 //   p < R/2; for every slot j the pair (row a, row b) is one 16-bit lane pair:
@@ -62,8 +63,9 @@ __device__ __forceinline__ uint32_t pair_of(uint32_t w, int s) {
     return __builtin_amdgcn_perm(w, w, s == 0 ? 0x0c010c00u : 0x0c030c02u);
 }
 
-template <int D, int R>
+template <int D, int R, bool ONEBIT>
 __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
+    static_assert(!ONEBIT || D <= 8, "1-bit state keeps 8 slots per 16-bit half");
     static_assert(R % 2 == 0, "rows are processed in pairs");
     constexpr int RP = R / 2;        // row pairs per thread
     constexpr int W = (D + 1) / 2;   // registers per row pair: two slots (4 bytes) each
@@ -103,11 +105,20 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
     }
     if (tid == 0) *flag = 0;
 
-    uint32_t Lw[RP][W];  // byte 2s / 2s+1 of Lw[p][j/2]: slot j (s = j%2) of rows a / b, as L + 64
+    // Message state of each row pair.
+    //   int8:  Lw[p][i], bytes 2s / 2s+1: slot 2i+s of rows a / b, as L + 64.
+    //   1-bit (Sec. V): St[p] bit j / 16+j: sign of slot j's message in row
+    //          a / b; bit 8+j / 24+j: slot j held the row minimum, so its
+    //          magnitude is B (A elsewhere); Ab[p] bytes: A_a, B_a, A_b, B_b.
+    uint32_t Lw[RP][ONEBIT ? 1 : W];
+    uint32_t St[RP], Ab[RP];
 #pragma unroll
-    for (int p = 0; p < RP; ++p)
+    for (int p = 0; p < RP; ++p) {
+        St[p] = 0u;
+        Ab[p] = 0u;
 #pragma unroll
-        for (int i = 0; i < W; ++i) Lw[p][i] = 0x40404040u;
+        for (int i = 0; i < (ONEBIT ? 1 : W); ++i) Lw[p][i] = 0x40404040u;
+    }
     __syncthreads();
 
     const uint32_t tid16 = (uint32_t)tid * 16u;
@@ -123,6 +134,12 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
             __builtin_amdgcn_sched_barrier(0);
             uint32_t acc_a[D], acc_b[D], t2[D], lo2[D], mg2[D];
             u16x2 min1 = {0xFFFF, 0xFFFF}, min2 = {0xFFFF, 0xFFFF};
+            uint32_t Sp = 0, Aold = 0, Bold = 0;
+            if (ONEBIT) {
+                Sp = St[p];
+                Aold = Ab[p] & 0x00FF00FFu;
+                Bold = (Ab[p] >> 8) & 0x00FF00FFu;
+            }
 #pragma unroll
             for (int j = 0; j < D; ++j) {
                 const auto r4 = __builtin_amdgcn_raw_buffer_load_b128(
@@ -132,7 +149,20 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
                 acc_b[j] = r4[3];
                 const u16x2 zv = {(unsigned short)lds_byte(na), (unsigned short)lds_byte(nb)};
                 const uint32_t z2 = bits(zv);
-                const uint32_t l2 = pair_of(Lw[p][j >> 1], j & 1);
+                uint32_t l2;
+                if (ONEBIT) {
+                    // L_old = s * (slot held the minimum ? B : A), rebuilt per
+                    // 16-bit half from the state bits (Eqs. 4-5 inverted)
+                    constexpr unsigned short kS = 15, kI = 7;
+                    const unsigned short ss = (unsigned short)(kS - j), si = (unsigned short)(kI - j);
+                    const i16x2 sm = as_i(bits(as_u(Sp) << (u16x2){ss, ss})) >> (i16x2){15, 15};
+                    uint32_t im = bits(as_i(bits(as_u(Sp) << (u16x2){si, si})) >> (i16x2){15, 15});
+                    asm volatile("" : "+v"(im));
+                    const uint32_t mo = (im & Bold) | (~im & Aold);
+                    l2 = bits(as_i(mo) * (sm | (i16x2){1, 1}) + (i16x2){64, 64});
+                } else {
+                    l2 = pair_of(Lw[p][j >> 1], j & 1);
+                }
                 lo2[j] = l2;
                 const i16x2 t = as_i(z2) - as_i(l2);  // Z_old - L_old per row
                 t2[j] = bits(t);
@@ -161,6 +191,7 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
             uint32_t mn1 = bits(min1);
             asm volatile("" : "+v"(B2), "+v"(A2), "+v"(mn1));
             uint32_t nl[D];
+            uint32_t Sn = 0;
 #pragma unroll
             for (int j = 0; j < D; ++j) {
                 // |t_j| >= min1, so (min1 - |t_j|) >> 15 is 0 at the minimum and
@@ -170,7 +201,17 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
                 const uint32_t mag = (nsel & A2) | (~nsel & B2);
                 // own sign +-1, then L_new + 64 in one multiply-add
                 const i16x2 sg = (as_i(t2[j]) >> (i16x2){15, 15}) | (i16x2){1, 1};
-                const i16x2 lb = as_i(mag) * sg + (i16x2){64, 64};
+                i16x2 lb;
+                if (ONEBIT) {
+                    // keep the sign bit and the minimum flag of the new message
+                    const i16x2 lnew = as_i(mag) * sg;
+                    lb = lnew + (i16x2){64, 64};
+                    const uint32_t sneg = bits(lnew >> (i16x2){15, 15});
+                    Sn = __builtin_amdgcn_bitop3_b32(sneg, 0x00010001u << j, Sn, 0xEA);  // (a & b) | c
+                    Sn = __builtin_amdgcn_bitop3_b32(nsel, 0x01000100u << j, Sn, 0xAE);  // (~a & b) | c
+                } else {
+                    lb = as_i(mag) * sg + (i16x2){64, 64};
+                }
                 nl[j] = bits(lb);
                 const uint32_t d = bits(lb - as_i(lo2[j]));
                 const int da = (int)(d << 16) >> 16;
@@ -178,12 +219,18 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
                 lds_add(acc_a[j] >> 5, (uint32_t)da << (acc_a[j] & 31u));
                 lds_add(acc_b[j] >> 5, (uint32_t)db << (acc_b[j] & 31u));
             }
+            if (ONEBIT) {
+                St[p] = Sn;
+                Ab[p] = __builtin_amdgcn_perm(bits(Bm), bits(Am), 0x06020400u);
+                asm volatile("" : "+v"(St[p]), "+v"(Ab[p]));
+            } else {
 #pragma unroll
-            for (int i = 0; i < W; ++i) {
-                const uint32_t lo = nl[2 * i];
-                const uint32_t hi = (2 * i + 1 < D) ? nl[2 * i + 1] : 0x00400040u;
-                Lw[p][i] = __builtin_amdgcn_perm(hi, lo, 0x06040200u);
-                asm volatile("" : "+v"(Lw[p][i]));
+                for (int i = 0; i < W; ++i) {
+                    const uint32_t lo = nl[2 * i];
+                    const uint32_t hi = (2 * i + 1 < D) ? nl[2 * i + 1] : 0x00400040u;
+                    Lw[p][i] = __builtin_amdgcn_perm(hi, lo, 0x06040200u);
+                    asm volatile("" : "+v"(Lw[p][i]));
+                }
             }
         }
         __syncthreads();
@@ -284,9 +331,9 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
     }
 }
 
-template <int D, int R>
+template <int D, int R, bool ONEBIT>
 hipError_t launch_one(const DecodeArgs &a, size_t lds, hipStream_t s) {
-    auto kern = ss_pk_kernel<D, R>;
+    auto kern = ss_pk_kernel<D, R, ONEBIT>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -322,9 +369,9 @@ void pk_shapes(int *out, int cap, int *count) {
     *count = i;
 }
 
-hipError_t launch_ss_pk(const DecodeArgs &a, int D, int R, size_t lds, hipStream_t s) {
+hipError_t launch_ss_pk(const DecodeArgs &a, int D, int R, bool onebit, size_t lds, hipStream_t s) {
 #define X(d, r) \
-    if (D == d && R == r) return launch_one<d, r>(a, lds, s);
+    if (D == d && R == r) return onebit ? launch_one<d, r, true>(a, lds, s) : launch_one<d, r, false>(a, lds, s);
     LDPC_PK_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;
