@@ -67,11 +67,12 @@ typedef enum {
                                    shape.
                                    AUTO prefers this layout */
 #define LDPC_LAYOUT_REG1 4      /* as LDPC_LAYOUT_REG, one row at a time (no packing) */
-#define LDPC_LAYOUT_FRAMES 5    /* single-scan FP32 only: one frame per lane, 64 frames per
-                                   wavefront, messages and posteriors in the caller's workspace
-                                   (frame-minor, so every access is a whole-wavefront line).
-                                   AUTO takes it for FP32 when the messages do not fit in LDS.
-                                   The workspace then covers the whole call and depends on
+#define LDPC_LAYOUT_FRAMES 5    /* single-scan FP32 and the two-scan baseline (INT8, FP32):
+                                   one frame per lane, 64 frames per wavefront, messages and
+                                   posteriors in the caller's workspace (frame-minor, so every
+                                   access is a whole-wavefront line).  AUTO takes it for these
+                                   paths when their per-edge arrays do not fit in LDS.  The
+                                   workspace then covers the whole call and depends on
                                    max_iter: ask ldpc_decode_workspace_size() */
 
 /*

@@ -72,6 +72,11 @@ hipError_t launch_ss_f32(const DecodeArgs &a, const LaunchCfg &cfg, hipStream_t 
 // batch runs in chunks of fl_chunk_frames frames, 0 = code too large)
 int fl_chunk_frames(int N, int64_t E);
 size_t fl_workspace_bytes(int N, int64_t E, int n_frames, int max_iter);
+// two-scan baseline (int8 or binary32), frames across lanes
+int ts_fl_chunk_frames(int N, int64_t E, bool int8);
+size_t ts_fl_workspace_bytes(int N, int64_t E, int n_frames, int max_iter, bool int8);
+hipError_t launch_two_scan_fl(const DecodeArgs &d, bool int8, const int32_t *row_ptr, const uint32_t *row_ent,
+                              const uint32_t *vc_csr, int64_t E, int max_row_deg, int cu_count, hipStream_t s);
 hipError_t launch_ss_f32_fl(const DecodeArgs &a, const int32_t *row_ptr, const uint32_t *row_ent, int64_t E,
                             int max_row_deg, int cu_count, hipStream_t s);
 hipError_t launch_two_scan(const DecodeArgs &a, int msg, const LaunchCfg &cfg, hipStream_t s);

@@ -32,6 +32,7 @@ struct ldpc_code {
     // position of the edge in variable-major order}
     int32_t *d_row_ptr = nullptr;
     uint32_t *d_row_ent = nullptr;
+    uint32_t *d_vc_csr = nullptr;  // [E + 64] row-order edge of each variable-major position
     int32_t cu_count = 256;
 };
 
@@ -66,7 +67,7 @@ struct DeviceGuard {
 struct Plan {
     ldpc::LaunchCfg cfg{};
     int family = 0;  // 0: single-scan int8/1-bit, 1: single-scan fp32, 2: two-scan, 3: register-resident,
-                     // 4: packed, 5: fp32 frames across lanes
+                     // 4: packed, 5: fp32 frames across lanes, 6: two-scan frames across lanes
     int zpack = 1;
     uint32_t off_zold = 0, off_zacc = 0, off_msg = 0, off_z = 0, off_aux = 0;
     uint64_t ws_off_msg = 0, ws_off_z = 0, ws_stride = 0;
@@ -126,8 +127,14 @@ ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl)
     }
     if (reg_layout) return fail(LDPC_EUNSUPPORTED, "register layout is single-scan INT8/1BIT only");
     if (layout == LDPC_LAYOUT_FRAMES) {
-        if (p->sched != LDPC_SINGLE_SCAN || p->msg != LDPC_MSG_FP32)
-            return fail(LDPC_EUNSUPPORTED, "frames-across-lanes layout is single-scan FP32 only");
+        if (p->sched == LDPC_TWO_SCAN) {
+            if (ldpc::ts_fl_chunk_frames(c->N, c->E, p->msg == LDPC_MSG_INT8) <= 0)
+                return fail(LDPC_EUNSUPPORTED, "code too large for the frames-across-lanes layout");
+            pl->family = 6;
+            return LDPC_OK;
+        }
+        if (p->msg != LDPC_MSG_FP32)
+            return fail(LDPC_EUNSUPPORTED, "frames-across-lanes single-scan is FP32 only");
         if (ldpc::fl_chunk_frames(c->N, c->E) <= 0)
             return fail(LDPC_EUNSUPPORTED, "code too large for the frames-across-lanes layout");
         pl->family = 5;
@@ -181,6 +188,12 @@ ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl)
         const size_t esz = p->msg == LDPC_MSG_INT8 ? 1 : 4;
         msg = align_up(2 * esz * (size_t)D * Mp, 16);
         zb = align_up((p->msg == LDPC_MSG_INT8 ? 2 : 4) * nz, 16);
+        // per-edge arrays that do not fit on chip stream through HBM frames-across-lanes
+        if (layout == LDPC_LAYOUT_AUTO && zb + msg + aux > limit &&
+            ldpc::ts_fl_chunk_frames(c->N, c->E, p->msg == LDPC_MSG_INT8) > 0) {
+            pl->family = 6;
+            return LDPC_OK;
+        }
     }
     const bool opts[3][2] = {{true, true}, {false, true}, {false, false}};
     for (auto &o : opts) {
@@ -357,6 +370,7 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
     std::vector<uint32_t> vc_slot((size_t)std::max<int64_t>(nnz, 1));
     // + 64 padding entries (variable 0, position 0): a row's slots load unconditionally
     std::vector<uint32_t> row_ent((size_t)2 * (nnz + 64), 0u);
+    std::vector<uint32_t> vc_csr((size_t)nnz + 64, 0u);
     std::vector<int32_t> fill(vc_ptr.begin(), vc_ptr.end() - 1);
     for (int m = 0; m < M; ++m)
         for (int j = 0; j < row_ptr[m + 1] - row_ptr[m]; ++j) {
@@ -365,6 +379,7 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
             ell[slot] = (uint32_t)n;
             row_ent[2 * (size_t)(row_ptr[m] + j)] = (uint32_t)n;
             row_ent[2 * (size_t)(row_ptr[m] + j) + 1] = (uint32_t)fill[n];
+            vc_csr[fill[n]] = (uint32_t)(row_ptr[m] + j);
             vc_slot[fill[n]++] = slot;  // rows visited in ascending order
         }
 
@@ -444,6 +459,7 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
     hipError_t e1 = hipMalloc(&c->d_ell, slots * sizeof(uint32_t));
     hipError_t e7 = hipMalloc(&c->d_row_ptr, ((size_t)M + 1) * sizeof(int32_t));
     hipError_t e8 = hipMalloc(&c->d_row_ent, row_ent.size() * sizeof(uint32_t));
+    hipError_t e9 = hipMalloc(&c->d_vc_csr, vc_csr.size() * sizeof(uint32_t));
     hipError_t e2 = hipMalloc(&c->d_vc_ptr, vc_ptr.size() * sizeof(int32_t));
     hipError_t e3 = hipMalloc(&c->d_vc_slot, vc_slot.size() * sizeof(uint32_t));
     std::vector<uint32_t> ell_reg;
@@ -491,7 +507,7 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
         e6 = hipMalloc(&c->d_pk_slot, pk_slot.size() * sizeof(uint32_t));
     }
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || e5 != hipSuccess ||
-        e6 != hipSuccess || e7 != hipSuccess || e8 != hipSuccess) {
+        e6 != hipSuccess || e7 != hipSuccess || e8 != hipSuccess || e9 != hipSuccess) {
         ldpc_code_destroy(c);
         (void)hipGetLastError();
         return fail(LDPC_ENOMEM, "device allocation failed");
@@ -502,6 +518,7 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
         hipMemcpy(c->d_row_ptr, row_ptr, ((size_t)M + 1) * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_row_ent, row_ent.data(), row_ent.size() * sizeof(uint32_t), hipMemcpyHostToDevice) !=
             hipSuccess ||
+        hipMemcpy(c->d_vc_csr, vc_csr.data(), vc_csr.size() * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess ||
         (c->d_ell_reg && hipMemcpy(c->d_ell_reg, ell_reg.data(), ell_reg.size() * sizeof(uint32_t),
                                    hipMemcpyHostToDevice) != hipSuccess) ||
         (c->d_pk_idx && hipMemcpy(c->d_pk_idx, pk_idx.data(), pk_idx.size() * sizeof(uint32_t),
@@ -528,6 +545,7 @@ ldpc_status ldpc_code_destroy(ldpc_code *code) {
     if (code->d_vc_slot) (void)hipFree(code->d_vc_slot);
     if (code->d_row_ptr) (void)hipFree(code->d_row_ptr);
     if (code->d_row_ent) (void)hipFree(code->d_row_ent);
+    if (code->d_vc_csr) (void)hipFree(code->d_vc_csr);
     if (code->d_ell_reg) (void)hipFree(code->d_ell_reg);
     if (code->d_pk_idx) (void)hipFree(code->d_pk_idx);
     if (code->d_pk_slot) (void)hipFree(code->d_pk_slot);
@@ -571,8 +589,10 @@ ldpc_status ldpc_decode_workspace_size(const ldpc_code *c, int32_t n_frames,
     Plan pl;
     st = make_plan(c, p, &pl);
     if (st != LDPC_OK) return st;
-    size_t b = pl.family == 5 ? ldpc::fl_workspace_bytes(c->N, c->E, n_frames, p->max_iter)
-                              : (size_t)pl.ws_stride * (size_t)n_frames;
+    size_t b = pl.family == 5   ? ldpc::fl_workspace_bytes(c->N, c->E, n_frames, p->max_iter)
+               : pl.family == 6 ? ldpc::ts_fl_workspace_bytes(c->N, c->E, n_frames, p->max_iter,
+                                                              p->msg == LDPC_MSG_INT8)
+                                : (size_t)pl.ws_stride * (size_t)n_frames;
     if (p->flags & LDPC_F_CHECK_INPUT) b = align_up(b, 256) + 256;
     *bytes = b;
     return LDPC_OK;
@@ -591,8 +611,10 @@ ldpc_status ldpc_decode_batch(const ldpc_code *c, int32_t n_frames, const void *
     Plan pl;
     st = make_plan(c, p, &pl);
     if (st != LDPC_OK) return st;
-    size_t need = pl.family == 5 ? ldpc::fl_workspace_bytes(c->N, c->E, n_frames, p->max_iter)
-                                 : (size_t)pl.ws_stride * (size_t)n_frames;
+    size_t need = pl.family == 5   ? ldpc::fl_workspace_bytes(c->N, c->E, n_frames, p->max_iter)
+                  : pl.family == 6 ? ldpc::ts_fl_workspace_bytes(c->N, c->E, n_frames, p->max_iter,
+                                                                 p->msg == LDPC_MSG_INT8)
+                                   : (size_t)pl.ws_stride * (size_t)n_frames;
     size_t check_off = 0;
     if (p->flags & LDPC_F_CHECK_INPUT) {
         check_off = align_up(need, 256);
@@ -665,6 +687,9 @@ ldpc_status ldpc_decode_batch(const ldpc_code *c, int32_t n_frames, const void *
         e = ldpc::launch_ss_pk(a, c->pkD, c->pkR, p->msg == LDPC_MSG_1BIT, pl.cfg.lds, s);
     else if (pl.family == 1)
         e = ldpc::launch_ss_f32(a, pl.cfg, s);
+    else if (pl.family == 6)
+        e = ldpc::launch_two_scan_fl(a, p->msg == LDPC_MSG_INT8, c->d_row_ptr, c->d_row_ent, c->d_vc_csr, c->E,
+                                     c->D, c->cu_count, s);
     else if (pl.family == 5)
         e = ldpc::launch_ss_f32_fl(a, c->d_row_ptr, c->d_row_ent, c->E, c->D,
                                    c->cu_count, s);

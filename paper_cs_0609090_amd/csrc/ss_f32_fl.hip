@@ -27,23 +27,12 @@
 // freezes, for good, the posteriors of every frame whose syndrome passed at
 // some iteration <= k, which reproduces a per-frame decoder that stops at the
 // first iteration whose syndrome is zero.
-#include "ldpc_internal.h"
-
-#include <algorithm>
-#include <climits>
+#include "fl_common.h"
 
 namespace ldpc {
 namespace {
 
-constexpr int kWaves = 4;  // wavefronts per workgroup
-constexpr int kBlock = 64 * kWaves;
-constexpr int kNotConverged = INT_MAX;
-constexpr uint32_t kRsrcWord3 = 0x00020000u;  // raw buffer, gfx9 family
-// Byte offset of the unused slots of a short row: every array of a chunk is
-// below 2^31 bytes and a lane adds less than that, so the sum stays past the
-// end of the buffer without wrapping: loads there return 0 and touch no
-// memory, stores are dropped.
-constexpr uint32_t kOutOfRange = 0x80000000u;
+using namespace fl;
 
 struct FlArgs {
     int32_t M, N, F, Fp, G;  // Fp = 64 * G frame lanes
@@ -66,56 +55,6 @@ __device__ __forceinline__ float norm_f(float m, float alpha, float beta) {
     return v > 0.0f ? v : 0.0f;
 }
 
-// The code's index arrays are read-only for the whole call: reading them
-// through the constant address space lets wave-uniform loads go to the
-// scalar unit (s_load) instead of the vector memory path.
-template <class T>
-__device__ __forceinline__ const __attribute__((address_space(4))) T *cptr(const T *p) {
-    return (const __attribute__((address_space(4))) T *)(p);
-}
-
-// Buffer view of one frame-minor array: every access is a scalar element
-// offset (SGPR) plus the lane's frame offset (one VGPR shared by all
-// accesses), so no per-access 64-bit address is formed.
-struct Buf {
-    __amdgpu_buffer_rsrc_t r;
-    __device__ Buf(const void *p, uint32_t bytes)
-        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, kRsrcWord3)) {}
-    __device__ float ld(uint32_t lane_off, uint32_t elem_off) const {
-        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, lane_off, elem_off, 0));
-    }
-    __device__ void st(float v, uint32_t lane_off, uint32_t elem_off) const {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, lane_off, elem_off, 0);
-    }
-};
-
-__device__ __forceinline__ int wave_id() {
-    return __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kWaves + (threadIdx.x >> 6)));
-}
-
-// llr_in [F][N] -> z0 [N][Fp] (frames >= F read as 0), 64x64 tiles via LDS.
-__global__ void __launch_bounds__(kBlock) fl_transpose_in(const float *__restrict__ in, float *__restrict__ z0,
-                                                          int N, int F, int Fp) {
-    __shared__ float tile[64][65];
-    const int n0 = blockIdx.x * 64, f0 = blockIdx.y * 64;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    for (int r = ty; r < 64; r += kWaves) {
-        const int f = f0 + r, n = n0 + tx;
-        tile[r][tx] = (f < F && n < N) ? in[(size_t)f * N + n] : 0.0f;
-    }
-    __syncthreads();
-    for (int r = ty; r < 64; r += kWaves) {
-        const int n = n0 + r, f = f0 + tx;
-        if (n < N) z0[(size_t)n * Fp + f] = tile[tx][r];
-    }
-}
-
-__global__ void __launch_bounds__(kBlock) fl_init_flags(int32_t *fail, int64_t nfail, int32_t *conv, int Fp) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < nfail) fail[i] = 0;
-    if (i < Fp) conv[i] = kNotConverged;
-}
-
 // Check pass of iteration k (UPDATE), or the syndrome of zold alone.
 //   syn_row >= 0: record rows failing the syndrome of zold in fail[syn_row]
 //   conv_k  >= 1: first fold fail[conv_k] into conv (one wavefront)
@@ -126,17 +65,12 @@ __global__ void __launch_bounds__(kBlock) fl_check(FlArgs a, const float *__rest
     const int lane = threadIdx.x & 63;
     const int w = wave_id();
     const int Fp = a.Fp;
-    if (conv_k >= 1 && w == 0) {
-        for (int f = lane; f < Fp; f += 64) {
-            const int c = a.conv[f];
-            if (c == kNotConverged && a.fail[(size_t)conv_k * Fp + f] == 0) a.conv[f] = conv_k;
-        }
-    }
+    if (conv_k >= 1 && w == 0) fold_conv(a.conv, a.fail, conv_k, Fp, lane);
     if (w >= a.rwaves * a.G) return;
     const int g = w % a.G;
     const int r0 = w / a.G;
     const uint32_t f = (uint32_t)(g * 64 + lane);
-    const uint32_t fo = f * 4u;             // lane offset in bytes
+    const uint32_t fo = f * 4u;               // lane offset in bytes
     const uint32_t rowb = (uint32_t)Fp * 4u;  // bytes per element row
     const Buf zb(zold, (uint32_t)a.N * rowb), lb(a.L, a.ebytes);
     const auto *rp = cptr(a.row_ptr);
@@ -157,8 +91,8 @@ __global__ void __launch_bounds__(kBlock) fl_check(FlArgs a, const float *__rest
         }
 #pragma unroll
         for (int j = 0; j < DMAX; ++j) {
-            z[j] = zb.ld(fo, var[j]);
-            if (UPDATE) t[j] = FIRST ? 0.0f : lb.ld(fo, pos[j]);
+            z[j] = zb.ldf(fo, var[j]);
+            if (UPDATE) t[j] = FIRST ? 0.0f : lb.ldf(fo, pos[j]);
         }
         int syn = 0, par = 0;
         float min1 = INFINITY, min2 = INFINITY;
@@ -189,7 +123,7 @@ __global__ void __launch_bounds__(kBlock) fl_check(FlArgs a, const float *__rest
                 out[j] = neg ? -mag : mag;
             }
 #pragma unroll
-            for (int j = 0; j < DMAX; ++j) lb.st(out[j], fo, pos[j]);
+            for (int j = 0; j < DMAX; ++j) lb.stf(out[j], fo, pos[j]);
         }
     }
 }
@@ -215,60 +149,22 @@ __global__ void __launch_bounds__(kBlock) fl_var(FlArgs a, const float *__restri
     for (int n = w / a.G; n < a.N; n += a.rwaves) {
         const uint32_t o = (uint32_t)n * rowb;
         if (FREEZE && frozen) {
-            zn.st(zo.ld(fo, o), fo, o);
+            zn.stf(zo.ldf(fo, o), fo, o);
             continue;
         }
         const int e0 = vp[n], e1 = vp[n + 1];
-        float s = z0.ld(fo, o);
+        float s = z0.ldf(fo, o);
         // eight messages per step, all loads in flight together; slots past
         // the variable's last edge are out of range and skipped (no +0.0 is
         // added, so the sum is exactly the ordered one)
         for (int e = e0; e < e1; e += 8) {
             float l[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) l[i] = lb.ld(fo, e + i < e1 ? (uint32_t)(e + i) * rowb : kOutOfRange);
+            for (int i = 0; i < 8; ++i) l[i] = lb.ldf(fo, e + i < e1 ? (uint32_t)(e + i) * rowb : kOutOfRange);
 #pragma unroll
             for (int i = 0; i < 8; ++i) s = e + i < e1 ? __fadd_rn(s, l[i]) : s;
         }
-        zn.st(s, fo, o);
-    }
-}
-
-// Per-frame results: iterations and syndrome flag.
-__global__ void __launch_bounds__(kBlock) fl_frame_out(FlArgs a, int K, int early_stop, int32_t *__restrict__ iters,
-                                                       uint8_t *__restrict__ ok) {
-    const int f = blockIdx.x * kBlock + threadIdx.x;
-    if (f >= a.F) return;
-    const int Fp = a.Fp;
-    int it = K;
-    if (early_stop) {
-        int c = a.conv[f];
-        for (int k = (K >= 2 ? K - 1 : 1); k <= K && c == kNotConverged; ++k)
-            if (a.fail[(size_t)k * Fp + f] == 0) c = k;
-        if (c != kNotConverged) it = c;
-    }
-    iters[f] = it;
-    ok[f] = a.fail[(size_t)K * Fp + f] == 0 ? 1 : 0;
-}
-
-// z [N][Fp] -> hard [F][N] (and llr [F][N]), 64x64 tiles via LDS.
-__global__ void __launch_bounds__(kBlock) fl_transpose_out(const float *__restrict__ z, int N, int F, int Fp,
-                                                           uint8_t *__restrict__ hard, float *__restrict__ llr) {
-    __shared__ float tile[64][65];
-    const int n0 = blockIdx.x * 64, f0 = blockIdx.y * 64;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    for (int r = ty; r < 64; r += kWaves) {
-        const int n = n0 + r;
-        tile[r][tx] = n < N ? z[(size_t)n * Fp + f0 + tx] : 0.0f;
-    }
-    __syncthreads();
-    for (int r = ty; r < 64; r += kWaves) {
-        const int f = f0 + r, n = n0 + tx;
-        if (f < F && n < N) {
-            const float v = tile[tx][r];
-            hard[(size_t)f * N + n] = v > 0.0f ? 0 : 1;
-            if (llr) llr[(size_t)f * N + n] = v;
-        }
+        zn.stf(s, fo, o);
     }
 }
 
@@ -276,10 +172,10 @@ template <int DMAX>
 hipError_t run(const DecodeArgs &d, const FlArgs &a, int K, unsigned grid, hipStream_t s) {
     const bool es = d.early_stop != 0;
     const dim3 tgrid((unsigned)((a.N + 63) / 64), (unsigned)a.G);
-    hipLaunchKernelGGL(fl_transpose_in, tgrid, dim3(kBlock), 0, s, static_cast<const float *>(d.llr_in), a.z0,
+    hipLaunchKernelGGL(transpose_in<float>, tgrid, dim3(kBlock), 0, s, static_cast<const float *>(d.llr_in), a.z0,
                        a.N, a.F, a.Fp);
     const int64_t nfail = (int64_t)(K + 1) * a.Fp;
-    hipLaunchKernelGGL(fl_init_flags, dim3((unsigned)((std::max<int64_t>(nfail, a.Fp) + kBlock - 1) / kBlock)),
+    hipLaunchKernelGGL(init_flags, dim3((unsigned)((std::max<int64_t>(nfail, a.Fp) + kBlock - 1) / kBlock)),
                        dim3(kBlock), 0, s, a.fail, nfail, a.conv, a.Fp);
     const float *zold = a.z0;
     for (int k = 1; k <= K; ++k) {
@@ -302,29 +198,23 @@ hipError_t run(const DecodeArgs &d, const FlArgs &a, int K, unsigned grid, hipSt
     // syndrome of the final posteriors, then the outputs
     hipLaunchKernelGGL((fl_check<DMAX, false, false>), dim3(grid), dim3(kBlock), 0, s, a, zold, K,
                        (es && K >= 3) ? K - 2 : 0);
-    hipLaunchKernelGGL(fl_frame_out, dim3((unsigned)((a.F + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a, K,
-                       d.early_stop, d.iters_out, d.ok_out);
-    hipLaunchKernelGGL(fl_transpose_out, tgrid, dim3(kBlock), 0, s, zold, a.N, a.F, a.Fp, d.hard_out, d.llr_out);
+    hipLaunchKernelGGL(frame_out, dim3((unsigned)((a.F + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a.fail, a.conv,
+                       a.F, a.Fp, K, d.early_stop, d.iters_out, d.ok_out);
+    hipLaunchKernelGGL(transpose_out<float>, tgrid, dim3(kBlock), 0, s, zold, a.N, a.F, a.Fp, 1.0, d.hard_out,
+                       d.llr_out);
     return hipGetLastError();
 }
 
 }  // namespace
 
-// Frames per call chunk: buffer offsets are 32-bit, so every frame-minor
-// array of a chunk stays below 2 GiB (64-frame groups; 0 if even one group
-// does not fit).
-int fl_chunk_frames(int N, int64_t E) {
-    const int64_t rowmax = std::max<int64_t>(E, N) * 4 * 64;  // bytes per element row of one group
-    const int64_t groups = ((int64_t)0x7FFFFF00) / rowmax;      // arrays below 2^31 bytes
-    return (int)std::min<int64_t>(groups * 64, (int64_t)1 << 30);
-}
+// Frames per call chunk: every frame-minor array of a chunk below 2 GiB.
+int fl_chunk_frames(int N, int64_t E) { return fl::chunk_frames(std::max<int64_t>(E, N) * 4); }
 
 size_t fl_workspace_bytes(int N, int64_t E, int n_frames, int max_iter) {
-    const int chunk = fl_chunk_frames(N, E);
-    const int fr = std::min(n_frames, std::max(chunk, 1));
+    const int fr = std::min(n_frames, std::max(fl_chunk_frames(N, E), 1));
     const size_t Fp = (size_t)((fr + 63) / 64) * 64;
-    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    return 3 * al((size_t)N * Fp * 4) + al((size_t)E * Fp * 4) + al((size_t)(max_iter + 1) * Fp * 4) + al(Fp * 4);
+    return 3 * fl::al256((size_t)N * Fp * 4) + fl::al256((size_t)E * Fp * 4) +
+           fl::al256((size_t)(max_iter + 1) * Fp * 4) + fl::al256(Fp * 4);
 }
 
 hipError_t launch_ss_f32_fl(const DecodeArgs &d, const int32_t *row_ptr, const uint32_t *row_ent, int64_t E,
@@ -353,24 +243,20 @@ hipError_t launch_ss_f32_fl(const DecodeArgs &d, const int32_t *row_ptr, const u
         a.vc_ptr = d.c.vc_ptr;
         const size_t Fp = (size_t)a.Fp;
         a.ebytes = (uint32_t)((size_t)E * Fp * 4);
-        auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
         uint8_t *p = d.ws;
         a.z0 = reinterpret_cast<float *>(p);
-        p += al((size_t)a.N * Fp * 4);
+        p += fl::al256((size_t)a.N * Fp * 4);
         a.zbuf[0] = reinterpret_cast<float *>(p);
-        p += al((size_t)a.N * Fp * 4);
+        p += fl::al256((size_t)a.N * Fp * 4);
         a.zbuf[1] = reinterpret_cast<float *>(p);
-        p += al((size_t)a.N * Fp * 4);
+        p += fl::al256((size_t)a.N * Fp * 4);
         a.L = reinterpret_cast<float *>(p);
-        p += al((size_t)E * Fp * 4);
+        p += fl::al256((size_t)E * Fp * 4);
         a.fail = reinterpret_cast<int32_t *>(p);
-        p += al((size_t)(d.max_iter + 1) * Fp * 4);
+        p += fl::al256((size_t)(d.max_iter + 1) * Fp * 4);
         a.conv = reinterpret_cast<int32_t *>(p);
-        // about 32 wavefronts per CU, split over the frame groups; wavefronts with
-        // an id past rwaves*G (the grid's rounding) return at once
-        const int64_t want = (int64_t)std::max(cu_count, 1) * 32;
-        a.rwaves = (int)std::max<int64_t>(1, std::min<int64_t>(want / a.G, std::max(a.M, a.N)));
-        const unsigned grid = (unsigned)(((int64_t)a.rwaves * a.G + kWaves - 1) / kWaves);
+        unsigned grid;
+        wave_layout(cu_count, a.G, std::max(a.M, a.N), &a.rwaves, &grid);
         const int K = d.max_iter;
         hipError_t e;
         if (max_row_deg <= 8)

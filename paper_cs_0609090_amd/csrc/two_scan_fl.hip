@@ -1,0 +1,382 @@
+// Two-scan min-sum (Sec. III, Eqs. 1-2), the baseline schedule, with frames
+// across lanes: one frame per lane, 64 frames per wavefront, every per-frame
+// array frame-minor (element (i, f) at i*Fp + f), so a wavefront's access to
+// one value is one contiguous line and the code's addressing is wave-uniform.
+//
+// Both per-edge arrays of the schedule are kept in the caller's workspace,
+// in the row order of H (CSR):
+//   Z_mn  variable-to-check messages (Z^(0)_n initially)
+//   L_mn  check-to-variable messages
+// and each iteration is the paper's two scans:
+//   horizontal (rows)     L_mn = prod sgn * norm(min |Z_mn'|) over n' != n,
+//                         from min1/argmin/min2 and the sign parity of the row
+//   vertical (variables)  Z_n = Z^(0)_n + sum of L_mn over M(n) (ascending
+//                         check order), then Z_mn = Z_n - L_mn for every edge
+//                         (saturated to the message range in fixed point)
+// The vertical scan reaches the row-ordered arrays through the
+// variable-to-check index: the second addressing table that the single-scan
+// form does without.  Fixed point: 6-bit messages in int8, Z_n in int16;
+// binary32: Z_mn = Z_n - L_mn rounded once, which is exactly the single-scan
+// extrinsic.  Early stop and outputs as in the single-scan frames-across-lanes
+// decoder (syndrome of Z^(k) formed in the horizontal scan of iteration k+1).
+#include "fl_common.h"
+
+#include <type_traits>
+
+namespace ldpc {
+namespace {
+
+using namespace fl;
+
+struct TsArgs {
+    int32_t M, N, F, Fp, G;
+    int32_t rwaves;
+    uint32_t ebytes;   // bytes of each per-edge array
+    uint32_t z0bytes;  // bytes of Z^(0)
+    uint32_t znbytes;  // bytes of Z_n
+    int32_t a8, b_int;
+    float alpha, beta;
+    const int32_t *row_ptr;   // [M+1]
+    const uint32_t *row_ent;  // [E + 64][2] {variable, variable-major position} (padded)
+    const int32_t *vc_ptr;    // [N+1]
+    const uint32_t *vc_csr;   // [E + 64] row-order edge of each variable-major position (padded)
+    void *z0;                 // [N][Fp] int8 / float
+    void *zn;                 // [N][Fp] int16 / float
+    void *zmn;                // [E][Fp] int8 / float, row order
+    void *L;                  // [E][Fp] int8 / float, row order
+    int32_t *fail;            // [K+1][Fp]
+    int32_t *conv;            // [Fp]
+};
+
+// Z_n := Z^(0)_n (widened), the posterior before the first iteration.
+template <class Tin, class Tz>
+__global__ void __launch_bounds__(kBlock) widen_z0(const Tin *__restrict__ z0, Tz *__restrict__ zn, int64_t count) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) zn[i] = (Tz)z0[i];
+}
+
+__device__ __forceinline__ float norm_f(float m, float alpha, float beta) {
+    const float v = __fsub_rn(__fmul_rn(alpha, m), beta);
+    return v > 0.0f ? v : 0.0f;
+}
+
+__device__ __forceinline__ int norm_q(int m, int a8, int b) {
+    const int v = ((m * a8 + 128) >> 8) - b;
+    return v > 0 ? v : 0;
+}
+
+// Horizontal scan of iteration k (UPDATE), or the syndrome of Z_n alone.
+//   syn_row >= 0: rows failing the syndrome of Z_n set fail[syn_row]
+//   conv_k  >= 1: first fold fail[conv_k] into conv (one wavefront)
+// FIRST: Z_mn = Z^(0)_n, gathered from z0.
+template <bool INT, int DMAX, bool UPDATE, bool FIRST>
+__global__ void __launch_bounds__(kBlock) ts_rows(TsArgs a, int syn_row, int conv_k) {
+    constexpr uint32_t es = INT ? 1 : 4, zs = INT ? 2 : 4;
+    const int lane = threadIdx.x & 63;
+    const int w = wave_id();
+    const int Fp = a.Fp;
+    if (conv_k >= 1 && w == 0) fold_conv(a.conv, a.fail, conv_k, Fp, lane);
+    if (w >= a.rwaves * a.G) return;
+    const int g = w % a.G;
+    const uint32_t f = (uint32_t)(g * 64 + lane);
+    const uint32_t foe = f * es, foz = f * zs;
+    const uint32_t rowe = (uint32_t)Fp * es, rowz = (uint32_t)Fp * zs;
+    const Buf b0(a.z0, a.z0bytes), bn(a.zn, a.znbytes), bm(a.zmn, a.ebytes), bl(a.L, a.ebytes);
+    const auto *rp = cptr(a.row_ptr);
+    const auto *re = cptr(a.row_ent);
+    const bool syn_on = syn_row >= 0;
+    for (int m = w / a.G; m < a.M; m += a.rwaves) {
+        const int e0 = rp[m];
+        const int d = rp[m + 1] - e0;
+        uint32_t var[DMAX], epos[DMAX];
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j) {
+            const uint32_t nv = re[2 * (e0 + j)];
+            var[j] = j < d ? nv : 0xFFFFFFFFu;
+            epos[j] = j < d ? (uint32_t)(e0 + j) * rowe : kOutOfRange;
+        }
+        // loads first (slots j >= d out of range), then the arithmetic
+        typename std::conditional<INT, int, float>::type t[DMAX];
+        int hz[DMAX];
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j) {
+            const uint32_t vo0 = var[j] == 0xFFFFFFFFu ? kOutOfRange : var[j] * rowe;
+            const uint32_t voz = var[j] == 0xFFFFFFFFu ? kOutOfRange : var[j] * rowz;
+            if (UPDATE) {
+                if constexpr (INT)
+                    t[j] = FIRST ? b0.ld8(foe, vo0) : bm.ld8(foe, epos[j]);
+                else
+                    t[j] = FIRST ? b0.ldf(foe, vo0) : bm.ldf(foe, epos[j]);
+            }
+            if (syn_on) {
+                if constexpr (INT)
+                    hz[j] = bn.ld16(foz, voz) > 0 ? 0 : 1;
+                else
+                    hz[j] = bn.ldf(foz, voz) > 0.0f ? 0 : 1;
+            }
+        }
+        if (syn_on) {
+            int syn = 0;
+#pragma unroll
+            for (int j = 0; j < DMAX; ++j) syn ^= j < d ? hz[j] : 0;
+            if (syn) a.fail[(size_t)syn_row * Fp + f] = 1;
+        }
+        if (UPDATE) {
+            int par = 0, idx = 0;
+            if constexpr (INT) {
+                int min1 = 255, min2 = 255;
+#pragma unroll
+                for (int j = 0; j < DMAX; ++j) {
+                    const bool in = j < d;
+                    par ^= (in && t[j] < 0) ? 1 : 0;
+                    const int av = in ? abs(t[j]) : 255;
+                    min2 = min(min2, max(min1, av));
+                    idx = av < min1 ? j : idx;
+                    min1 = min(min1, av);
+                }
+                const int A = norm_q(min1, a.a8, a.b_int), B = norm_q(min2, a.a8, a.b_int);
+                int out[DMAX];
+#pragma unroll
+                for (int j = 0; j < DMAX; ++j) {
+                    const int mag = j == idx ? B : A;
+                    out[j] = (par ^ (t[j] < 0 ? 1 : 0)) ? -mag : mag;
+                }
+#pragma unroll
+                for (int j = 0; j < DMAX; ++j) bl.st8(out[j], foe, epos[j]);
+            } else {
+                float min1 = INFINITY, min2 = INFINITY;
+#pragma unroll
+                for (int j = 0; j < DMAX; ++j) {
+                    const bool in = j < d;
+                    par ^= (in && t[j] < 0.0f) ? 1 : 0;
+                    const float av = in ? fabsf(t[j]) : INFINITY;
+                    min2 = fminf(min2, fmaxf(min1, av));
+                    idx = av < min1 ? j : idx;
+                    min1 = fminf(min1, av);
+                }
+                const float A = norm_f(min1, a.alpha, a.beta), B = norm_f(min2, a.alpha, a.beta);
+                float out[DMAX];
+#pragma unroll
+                for (int j = 0; j < DMAX; ++j) {
+                    const float mag = j == idx ? B : A;
+                    out[j] = (par ^ (t[j] < 0.0f ? 1 : 0)) ? -mag : mag;
+                }
+#pragma unroll
+                for (int j = 0; j < DMAX; ++j) bl.stf(out[j], foe, epos[j]);
+            }
+        }
+    }
+}
+
+// Vertical scan of iteration k: Z_n and the new Z_mn.  Frames frozen by the
+// early stop keep their Z_n.  Variables of degree up to 8 keep their
+// messages in registers between the sum and the extrinsics; larger degrees
+// read them twice.
+template <bool INT, bool FREEZE>
+__global__ void __launch_bounds__(kBlock) ts_vars(TsArgs a, int fail_row) {
+    constexpr uint32_t es = INT ? 1 : 4, zs = INT ? 2 : 4;
+    using V = typename std::conditional<INT, int, float>::type;
+    const int lane = threadIdx.x & 63;
+    const int w = wave_id();
+    const int Fp = a.Fp;
+    if (w >= a.rwaves * a.G) return;
+    const int g = w % a.G;
+    const uint32_t f = (uint32_t)(g * 64 + lane);
+    const uint32_t foe = f * es, foz = f * zs;
+    const uint32_t rowe = (uint32_t)Fp * es, rowz = (uint32_t)Fp * zs;
+    const Buf b0(a.z0, a.z0bytes), bn(a.zn, a.znbytes), bm(a.zmn, a.ebytes), bl(a.L, a.ebytes);
+    bool frozen = false;
+    if (FREEZE) frozen = a.conv[f] != kNotConverged || a.fail[(size_t)fail_row * Fp + f] == 0;
+    const auto *vp = cptr(a.vc_ptr);
+    const auto *vcs = cptr(a.vc_csr);
+    auto ld = [&](const Buf &b, uint32_t off) -> V {
+        if constexpr (INT)
+            return b.ld8(foe, off);
+        else
+            return b.ldf(foe, off);
+    };
+    auto st_ext = [&](V zsum, V lv, uint32_t off) {  // Z_mn = Z_n - L_mn
+        if constexpr (INT) {
+            const int v = zsum - lv;
+            bm.st8(v > kQmax ? kQmax : (v < -kQmax ? -kQmax : v), foe, off);
+        } else {
+            bm.stf(__fsub_rn(zsum, lv), foe, off);
+        }
+    };
+    for (int n = w / a.G; n < a.N; n += a.rwaves) {
+        const int e0 = vp[n], e1 = vp[n + 1];
+        V s = ld(b0, (uint32_t)n * rowe);
+        V l[8];
+        uint32_t eo[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) eo[i] = kOutOfRange;
+        // Z_n: eight messages per step, all loads in flight together; slots
+        // past the last edge are out of range and skipped (nothing is added)
+        for (int e = e0; e < e1; e += 8) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const uint32_t ce = vcs[e + i];
+                eo[i] = e + i < e1 ? ce * rowe : kOutOfRange;
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) l[i] = ld(bl, eo[i]);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                if constexpr (INT)
+                    s = e + i < e1 ? s + l[i] : s;
+                else
+                    s = e + i < e1 ? __fadd_rn(s, l[i]) : s;
+            }
+        }
+        if (!(FREEZE && frozen)) {
+            if constexpr (INT)
+                bn.st16(s, foz, (uint32_t)n * rowz);
+            else
+                bn.stf(s, foz, (uint32_t)n * rowz);
+        }
+        // extrinsics: a variable of degree <= 8 still holds its messages and
+        // their offsets in registers (out-of-range slots are dropped stores);
+        // larger degrees read them again
+        if (e1 - e0 <= 8) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) st_ext(s, l[i], eo[i]);
+        } else {
+            for (int e = e0; e < e1; e += 8) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const uint32_t ce = vcs[e + i];
+                    eo[i] = e + i < e1 ? ce * rowe : kOutOfRange;
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i) l[i] = ld(bl, eo[i]);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) st_ext(s, l[i], eo[i]);
+            }
+        }
+    }
+}
+
+template <bool INT, int DMAX>
+hipError_t run(const DecodeArgs &d, const TsArgs &a, int K, unsigned grid, hipStream_t s) {
+    using Tin = typename std::conditional<INT, int8_t, float>::type;
+    using Tz = typename std::conditional<INT, int16_t, float>::type;
+    const bool es = d.early_stop != 0;
+    const dim3 tgrid((unsigned)((a.N + 63) / 64), (unsigned)a.G);
+    hipLaunchKernelGGL(transpose_in<Tin>, tgrid, dim3(kBlock), 0, s, static_cast<const Tin *>(d.llr_in),
+                       static_cast<Tin *>(a.z0), a.N, a.F, a.Fp);
+    const int64_t nfail = (int64_t)(K + 1) * a.Fp;
+    hipLaunchKernelGGL(init_flags, dim3((unsigned)((std::max<int64_t>(nfail, a.Fp) + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, s, a.fail, nfail, a.conv, a.Fp);
+    // Z_n starts as Z^(0): the syndrome and the outputs of max_iter = 0
+    const int64_t nz = (int64_t)a.N * a.Fp;
+    hipLaunchKernelGGL((widen_z0<Tin, Tz>), dim3((unsigned)std::min<int64_t>((nz + kBlock - 1) / kBlock, 65536)),
+                       dim3(kBlock), 0, s, static_cast<const Tin *>(a.z0), static_cast<Tz *>(a.zn), nz);
+    for (int k = 1; k <= K; ++k) {
+        const int syn_row = (es && k >= 2) ? k - 1 : -1;
+        const int conv_k = (es && k >= 3) ? k - 2 : 0;
+        if (k == 1)
+            hipLaunchKernelGGL((ts_rows<INT, DMAX, true, true>), dim3(grid), dim3(kBlock), 0, s, a, syn_row, conv_k);
+        else
+            hipLaunchKernelGGL((ts_rows<INT, DMAX, true, false>), dim3(grid), dim3(kBlock), 0, s, a, syn_row,
+                               conv_k);
+        if (es && k >= 2)
+            hipLaunchKernelGGL((ts_vars<INT, true>), dim3(grid), dim3(kBlock), 0, s, a, k - 1);
+        else
+            hipLaunchKernelGGL((ts_vars<INT, false>), dim3(grid), dim3(kBlock), 0, s, a, 0);
+    }
+    hipLaunchKernelGGL((ts_rows<INT, DMAX, false, false>), dim3(grid), dim3(kBlock), 0, s, a, K,
+                       (es && K >= 3) ? K - 2 : 0);
+    hipLaunchKernelGGL(frame_out, dim3((unsigned)((a.F + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a.fail, a.conv,
+                       a.F, a.Fp, K, d.early_stop, d.iters_out, d.ok_out);
+    hipLaunchKernelGGL(transpose_out<Tz>, tgrid, dim3(kBlock), 0, s, static_cast<const Tz *>(a.zn), a.N, a.F, a.Fp,
+                       d.step, d.hard_out, d.llr_out);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int ts_fl_chunk_frames(int N, int64_t E, bool int8) {
+    return fl::chunk_frames(std::max<int64_t>(E * (int8 ? 1 : 4), (int64_t)N * 4));
+}
+
+size_t ts_fl_workspace_bytes(int N, int64_t E, int n_frames, int max_iter, bool int8) {
+    const int fr = std::min(n_frames, std::max(ts_fl_chunk_frames(N, E, int8), 1));
+    const size_t Fp = (size_t)((fr + 63) / 64) * 64;
+    const size_t es = int8 ? 1 : 4, zs = int8 ? 2 : 4;
+    return fl::al256((size_t)N * Fp * es) + fl::al256((size_t)N * Fp * zs) + 2 * fl::al256((size_t)E * Fp * es) +
+           fl::al256((size_t)(max_iter + 1) * Fp * 4) + fl::al256(Fp * 4);
+}
+
+hipError_t launch_two_scan_fl(const DecodeArgs &d, bool int8, const int32_t *row_ptr, const uint32_t *row_ent,
+                              const uint32_t *vc_csr, int64_t E, int max_row_deg, int cu_count, hipStream_t s) {
+    const int chunk = ts_fl_chunk_frames(d.c.N, E, int8);
+    if (chunk <= 0 || max_row_deg > 64) return hipErrorInvalidValue;
+    const size_t es = int8 ? 1 : 4, zs = int8 ? 2 : 4;
+    for (int c0 = 0; c0 < d.n_frames; c0 += chunk) {
+        const int F = std::min(chunk, d.n_frames - c0);
+        DecodeArgs dc = d;
+        dc.n_frames = F;
+        dc.llr_in = static_cast<const uint8_t *>(d.llr_in) + (size_t)c0 * d.c.N * es;
+        dc.hard_out = d.hard_out + (size_t)c0 * d.c.N;
+        dc.llr_out = d.llr_out ? d.llr_out + (size_t)c0 * d.c.N : nullptr;
+        dc.iters_out = d.iters_out + c0;
+        dc.ok_out = d.ok_out + c0;
+        TsArgs a{};
+        a.M = d.c.M;
+        a.N = d.c.N;
+        a.F = F;
+        a.G = (F + 63) / 64;
+        a.Fp = a.G * 64;
+        a.a8 = d.a8;
+        a.b_int = d.b_int;
+        a.alpha = d.alpha;
+        a.beta = d.beta;
+        a.row_ptr = row_ptr;
+        a.row_ent = row_ent;
+        a.vc_ptr = d.c.vc_ptr;
+        a.vc_csr = vc_csr;
+        const size_t Fp = (size_t)a.Fp;
+        a.ebytes = (uint32_t)((size_t)E * Fp * es);
+        a.z0bytes = (uint32_t)((size_t)a.N * Fp * es);
+        a.znbytes = (uint32_t)((size_t)a.N * Fp * zs);
+        uint8_t *p = d.ws;
+        a.z0 = p;
+        p += fl::al256(a.z0bytes);
+        a.zn = p;
+        p += fl::al256(a.znbytes);
+        a.zmn = p;
+        p += fl::al256(a.ebytes);
+        a.L = p;
+        p += fl::al256(a.ebytes);
+        a.fail = reinterpret_cast<int32_t *>(p);
+        p += fl::al256((size_t)(d.max_iter + 1) * Fp * 4);
+        a.conv = reinterpret_cast<int32_t *>(p);
+        unsigned grid;
+        wave_layout(cu_count, a.G, std::max(a.M, a.N), &a.rwaves, &grid);
+        const int K = d.max_iter;
+        hipError_t e;
+        if (int8) {
+            if (max_row_deg <= 8)
+                e = run<true, 8>(dc, a, K, grid, s);
+            else if (max_row_deg <= 16)
+                e = run<true, 16>(dc, a, K, grid, s);
+            else if (max_row_deg <= 32)
+                e = run<true, 32>(dc, a, K, grid, s);
+            else
+                e = run<true, 64>(dc, a, K, grid, s);
+        } else {
+            if (max_row_deg <= 8)
+                e = run<false, 8>(dc, a, K, grid, s);
+            else if (max_row_deg <= 16)
+                e = run<false, 16>(dc, a, K, grid, s);
+            else if (max_row_deg <= 32)
+                e = run<false, 32>(dc, a, K, grid, s);
+            else
+                e = run<false, 64>(dc, a, K, grid, s);
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace ldpc

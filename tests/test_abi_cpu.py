@@ -158,10 +158,18 @@ def test_workspace_plans(L):
     assert big.workspace_size(65, L.make_params(msg="fp32")) > f1
     assert big.workspace_size(1, L.make_params(msg="fp32", max_iter=80)) > f1
     assert big.workspace_size(1, L.make_params(msg="fp32", layout="frames")) == f1
-    for bad in (dict(msg="int8", layout="frames"), dict(msg="fp32", sched="two_scan", layout="frames")):
+    for bad in (dict(msg="int8", layout="frames"), dict(msg="1bit", layout="frames"),
+                dict(msg="1bit", sched="two_scan", layout="frames")):
         with pytest.raises(L.LdpcError) as ei:
             big.workspace_size(4, L.make_params(**bad))
         assert ei.value.status == L.LDPC_EUNSUPPORTED
+    # the two-scan baseline of the big code streams both per-edge arrays (Z_mn
+    # and L_mn) frames-across-lanes: int8 1 byte per edge and frame, fp32 4
+    t8 = big.workspace_size(64, L.make_params(msg="int8", sched="two_scan"))
+    t32 = big.workspace_size(64, L.make_params(msg="fp32", sched="two_scan"))
+    assert t8 >= 64 * (2 * 226799 + 64800 + 2 * 64800)
+    assert t32 >= 64 * 4 * (2 * 226799 + 2 * 64800) and t32 > 3 * t8
+    assert t8 == big.workspace_size(64, L.make_params(msg="int8", sched="two_scan", layout="frames"))
     with pytest.raises(L.LdpcError) as ei:
         big.workspace_size(4, L.make_params(msg="fp32", layout="reg"))
     assert ei.value.status == L.LDPC_EUNSUPPORTED

@@ -112,8 +112,9 @@ def test_golden_tiny(torch_dev, L, orc):
 def test_random_small_codes(torch_dev, L, orc, variant, layout):
     if layout == "reg1" and variant[0] == "fp32":
         pytest.skip("register layouts are fixed-point only")
-    if layout == "frames" and variant[:2] != ("fp32", "single_scan"):
-        pytest.skip("the frames-across-lanes layout is binary32 single-scan only")
+    if layout == "frames" and variant[:2] not in (("fp32", "single_scan"), ("int8", "two_scan"),
+                                                  ("fp32", "two_scan")):
+        pytest.skip("frames across lanes: binary32 single-scan and the two-scan baseline only")
     rng = np.random.default_rng(123)
     for i in range(14):
         M = int(rng.integers(3, 40))
@@ -172,7 +173,7 @@ def test_qc7493_batch_sampled(torch_dev, L, orc, variant, layout):
 
 @pytest.mark.parametrize("variant,layout", [(v, "auto") for v in VARIANTS] +
                          [(VARIANTS[0], "hbm"), (VARIANTS[1], "hbm"), (VARIANTS[0], "reg1"),
-                          (VARIANTS[2], "hbm")],
+                          (VARIANTS[2], "hbm"), (VARIANTS[3], "hbm")],
                          ids=lambda v: v if isinstance(v, str) else f"{v[0]}-{v[1]}")
 def test_ira64800_bench_config_sampled(torch_dev, L, orc, variant, layout):
     """N=64800 IRA code in the benchmark configuration (512 frames, 1 dB,
@@ -184,14 +185,16 @@ def test_ira64800_bench_config_sampled(torch_dev, L, orc, variant, layout):
               early_stop=False, layout=layout)
 
 
+@pytest.mark.parametrize("fp", [VARIANTS[2], VARIANTS[3], VARIANTS[4]],
+                         ids=lambda v: f"{v[0]}-{v[1]}")
 @pytest.mark.parametrize("case", ["peg1008", "ira16200", "short"])
-def test_fp32_frames_layout(torch_dev, L, orc, case):
-    """Binary32 single-scan with one frame per lane: batches that are not a
-    multiple of 64 frames, early stop on and off, max_iter 0, 1, 2 and 50."""
-    fp = VARIANTS[2]
+def test_frames_layout(torch_dev, L, orc, case, fp):
+    """One frame per lane (binary32 single-scan, both two-scan baselines):
+    batches that are not a multiple of 64 frames, early stop on and off,
+    max_iter 0, 1, 2 and 50."""
     if case == "peg1008":
         code = W.code_c0_peg1008()
-        x = _inputs(code, 200, 2.0, (0xC0, 1), "fp32")
+        x = _inputs(code, 200, 2.0, (0xC0, 1), fp[0])
         g, r = _run_pair(torch_dev, L, orc, code, x, fp, max_iter=50, alpha=0.8, early_stop=True,
                          layout="frames")
         assert r["ok"].sum() > 150 and len(set(r["iters"].tolist())) > 3
@@ -199,12 +202,12 @@ def test_fp32_frames_layout(torch_dev, L, orc, case):
                   early_stop=False, layout="frames")
     elif case == "ira16200":
         code = W.code_ira16200()
-        x = _inputs(code, 24, 1.2, (0x16, 2), "fp32")
+        x = _inputs(code, 24, 1.2, (0x16, 2), fp[0])
         _run_pair(torch_dev, L, orc, code, x, fp, max_iter=25, alpha=0.8, early_stop=True,
                   layout="frames")
     else:
         code = W.code_c0_peg1008()
-        x = _inputs(code, 3, 2.5, (0xC0, 9), "fp32")
+        x = _inputs(code, 3, 2.5, (0xC0, 9), fp[0])
         for k in (0, 1, 2):
             for es in (True, False):
                 _run_pair(torch_dev, L, orc, code, x, fp, max_iter=k, alpha=0.8, early_stop=es,
@@ -239,8 +242,12 @@ def test_layout_and_batch_invariance(torch_dev, L, msg, sched):
     kw = dict(max_iter=30, alpha=0.8, early_stop=True)
     a = _gpu(torch_dev, L, gc, x, msg, sched, layout="lds", **kw)
     b = _gpu(torch_dev, L, gc, x, msg, sched, layout="hbm", **kw)
-    if sched == "single_scan":
-        for lay in (("reg", "reg1") if msg != "fp32" else ("frames",)):
+    if sched == "two_scan" or msg == "fp32":
+        r = _gpu(torch_dev, L, gc, x, msg, sched, layout="frames", **kw)
+        for k in ("hard", "llr", "iters", "ok"):
+            np.testing.assert_array_equal(a[k], r[k])
+    if sched == "single_scan" and msg != "fp32":
+        for lay in ("reg", "reg1"):
             r = _gpu(torch_dev, L, gc, x, msg, sched, layout=lay, **kw)
             for k in ("hard", "llr", "iters", "ok"):
                 np.testing.assert_array_equal(a[k], r[k])
