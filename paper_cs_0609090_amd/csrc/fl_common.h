@@ -20,6 +20,7 @@ constexpr uint32_t kRsrcWord3 = 0x00020000u;  // raw buffer, gfx9 family
 // past the end of the buffer without wrapping: loads there return 0 and touch
 // no memory, stores are dropped.
 constexpr uint32_t kOutOfRange = 0x80000000u;
+constexpr int kNonTemporal = 2;  // cache-policy bit of buffer accesses: non-temporal
 
 // The code's index arrays are read-only for the whole call: reading them
 // through the constant address space lets wave-uniform loads go to the
@@ -45,6 +46,14 @@ struct Buf {
     }
     __device__ void stf(float v, uint32_t lane_off, uint32_t elem_off) const {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, lane_off, elem_off, 0);
+    }
+    // non-temporal (streaming) forms: data read or written once per pass, so
+    // that it does not push reused data (the posterior gathers) out of the caches
+    __device__ float ldf_nt(uint32_t lane_off, uint32_t elem_off) const {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, lane_off, elem_off, kNonTemporal));
+    }
+    __device__ void stf_nt(float v, uint32_t lane_off, uint32_t elem_off) const {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, lane_off, elem_off, kNonTemporal);
     }
     __device__ int ld8(uint32_t lane_off, uint32_t elem_off) const {  // signed byte
         return (int)(int8_t)__builtin_amdgcn_raw_buffer_load_b8(r, lane_off, elem_off, 0);

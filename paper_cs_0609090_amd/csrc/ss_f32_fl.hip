@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(kBlock) fl_check(FlArgs a, const float *__rest
 #pragma unroll
         for (int j = 0; j < DMAX; ++j) {
             z[j] = zb.ldf(fo, var[j]);
-            if (UPDATE) t[j] = FIRST ? 0.0f : lb.ldf(fo, pos[j]);
+            if (UPDATE) t[j] = FIRST ? 0.0f : lb.ldf_nt(fo, pos[j]);
         }
         int syn = 0, par = 0;
         float min1 = INFINITY, min2 = INFINITY;
@@ -123,7 +123,7 @@ __global__ void __launch_bounds__(kBlock) fl_check(FlArgs a, const float *__rest
                 out[j] = neg ? -mag : mag;
             }
 #pragma unroll
-            for (int j = 0; j < DMAX; ++j) lb.stf(out[j], fo, pos[j]);
+            for (int j = 0; j < DMAX; ++j) lb.stf_nt(out[j], fo, pos[j]);
         }
     }
 }
@@ -153,14 +153,14 @@ __global__ void __launch_bounds__(kBlock) fl_var(FlArgs a, const float *__restri
             continue;
         }
         const int e0 = vp[n], e1 = vp[n + 1];
-        float s = z0.ldf(fo, o);
+        float s = z0.ldf_nt(fo, o);
         // eight messages per step, all loads in flight together; slots past
         // the variable's last edge are out of range and skipped (no +0.0 is
         // added, so the sum is exactly the ordered one)
         for (int e = e0; e < e1; e += 8) {
             float l[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) l[i] = lb.ldf(fo, e + i < e1 ? (uint32_t)(e + i) * rowb : kOutOfRange);
+            for (int i = 0; i < 8; ++i) l[i] = lb.ldf_nt(fo, e + i < e1 ? (uint32_t)(e + i) * rowb : kOutOfRange);
 #pragma unroll
             for (int i = 0; i < 8; ++i) s = e + i < e1 ? __fadd_rn(s, l[i]) : s;
         }
