@@ -1,0 +1,55 @@
+// The code handle behind the opaque ldpc_code of the C ABI (host side),
+// shared by the decoder runtime and the channel-simulation entry points.
+#pragma once
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/ldpc.h"
+
+struct ldpc_code {
+    int32_t device = 0;
+    int32_t M = 0, N = 0;
+    int64_t E = 0;
+    int32_t D = 0, Mp = 0, dummy = 0;
+    int32_t min_row_deg = 0, max_col_deg = 0;
+    int32_t lds_limit = 65536;
+    uint32_t *d_ell = nullptr;
+    int32_t *d_vc_ptr = nullptr;
+    uint32_t *d_vc_slot = nullptr;
+    // register-resident shape (0 = none)
+    int32_t regD = 0, regR = 0, regP = 0;
+    uint32_t *d_ell_reg = nullptr;
+    // packed two-rows-per-lane INT8 shape (0 = none); uses regP's packing
+    int32_t pkD = 0, pkR = 0;
+    int32_t pkBias = 0;  // accumulator field bias of the packed kernel
+    uint32_t *d_pk_idx = nullptr;
+    uint32_t *d_pk_slot = nullptr;  // [N] posterior slot of each variable
+    // frames-across-lanes binary32 path: CSR rows and, per edge, {variable,
+    // position of the edge in variable-major order}
+    int32_t *d_row_ptr = nullptr;
+    uint32_t *d_row_ent = nullptr;
+    uint32_t *d_vc_csr = nullptr;  // [E + 64] row-order edge of each variable-major position
+    int32_t cu_count = 256;
+    // host copy of H (CSR), kept for the encoder, which is built on first use
+    std::vector<int32_t> h_row_ptr, h_col_idx;
+    // systematic encoder (0 = not built yet / none; see ldpc_sim.h)
+    std::mutex enc_mu;
+    bool enc_built = false;
+    int32_t enc_kind = 0;         // LDPC_ENC_*
+    int32_t enc_K = 0;            // information bits
+    int32_t enc_rank = 0;         // parity bits (rank of H)
+    int32_t enc_words = 0;        // 32-bit words per packed row of the dense parity map
+    std::vector<int32_t> h_info_pos;  // [N]: K information columns (ascending), then the parity columns
+    int32_t *d_info_pos = nullptr;    // device copy
+    uint32_t *d_enc_rows = nullptr;   // dense: [rank][words] parity map over the information bits
+    std::string enc_error;
+};
+
+namespace ldpc {
+// error state of the calling thread (ldpc_last_error), set by every entry point
+ldpc_status set_error(ldpc_status st, const std::string &msg);
+void clear_error();
+}  // namespace ldpc

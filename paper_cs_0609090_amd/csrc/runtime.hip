@@ -10,31 +10,7 @@
 #include "../../include/ldpc.h"
 #include "ldpc_internal.h"
 
-struct ldpc_code {
-    int32_t device = 0;
-    int32_t M = 0, N = 0;
-    int64_t E = 0;
-    int32_t D = 0, Mp = 0, dummy = 0;
-    int32_t min_row_deg = 0, max_col_deg = 0;
-    int32_t lds_limit = 65536;
-    uint32_t *d_ell = nullptr;
-    int32_t *d_vc_ptr = nullptr;
-    uint32_t *d_vc_slot = nullptr;
-    // register-resident shape (0 = none)
-    int32_t regD = 0, regR = 0, regP = 0;
-    uint32_t *d_ell_reg = nullptr;
-    // packed two-rows-per-lane INT8 shape (0 = none); uses regP's packing
-    int32_t pkD = 0, pkR = 0;
-    int32_t pkBias = 0;  // accumulator field bias of the packed kernel
-    uint32_t *d_pk_idx = nullptr;
-    uint32_t *d_pk_slot = nullptr;  // [N] posterior slot of each variable
-    // frames-across-lanes binary32 path: CSR rows and, per edge, {variable,
-    // position of the edge in variable-major order}
-    int32_t *d_row_ptr = nullptr;
-    uint32_t *d_row_ent = nullptr;
-    uint32_t *d_vc_csr = nullptr;  // [E + 64] row-order edge of each variable-major position
-    int32_t cu_count = 256;
-};
+#include "code_handle.h"
 
 namespace {
 
@@ -307,6 +283,12 @@ std::vector<uint32_t> pk_slot_assignment(int M, int N, const int32_t *row_ptr, c
 }  // namespace
 
 namespace ldpc {
+// error state of the calling thread, for the other entry points of the library
+ldpc_status set_error(ldpc_status st, const std::string &msg) { return fail(st, msg); }
+void clear_error() { g_err.clear(); }
+}  // namespace ldpc
+
+namespace ldpc {
 hipError_t launch_check_input(const void *llr, int64_t count, int msg, int32_t *bad, hipStream_t s) {
     hipLaunchKernelGGL(zero_word_kernel, dim3(1), dim3(1), 0, s, bad);
     if (count > 0) {
@@ -359,6 +341,8 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
     c->Mp = (M + 63) / 64 * 64;
     c->dummy = (N + 5) / 6 * 6;
     c->min_row_deg = dmin;
+    c->h_row_ptr.assign(row_ptr, row_ptr + M + 1);
+    c->h_col_idx.assign(col_idx, col_idx + nnz);
     const size_t slots = (size_t)c->D * c->Mp;
     std::vector<uint32_t> ell(slots, (uint32_t)c->dummy);
     std::vector<int32_t> vc_ptr((size_t)N + 1, 0);
@@ -546,6 +530,8 @@ ldpc_status ldpc_code_destroy(ldpc_code *code) {
     if (code->d_row_ptr) (void)hipFree(code->d_row_ptr);
     if (code->d_row_ent) (void)hipFree(code->d_row_ent);
     if (code->d_vc_csr) (void)hipFree(code->d_vc_csr);
+    if (code->d_info_pos) (void)hipFree(code->d_info_pos);
+    if (code->d_enc_rows) (void)hipFree(code->d_enc_rows);
     if (code->d_ell_reg) (void)hipFree(code->d_ell_reg);
     if (code->d_pk_idx) (void)hipFree(code->d_pk_idx);
     if (code->d_pk_slot) (void)hipFree(code->d_pk_slot);

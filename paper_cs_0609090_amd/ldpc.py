@@ -30,7 +30,11 @@ LAYOUT_SHIFT = 8
 
 EXPORTS = ("ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query",
            "ldpc_decode_workspace_size", "ldpc_decode_batch", "ldpc_last_error",
-           "ldpc_version")
+           "ldpc_version",
+           # include/ldpc_sim.h
+           "ldpc_encoder_info", "ldpc_encode_batch", "ldpc_random_bits", "ldpc_channel_awgn",
+           "ldpc_count_errors")
+ENC_KIND = {0: "none", 1: "staircase", 2: "dense"}
 
 
 class LdpcError(RuntimeError):
@@ -77,8 +81,15 @@ def lib():
                                                  ctypes.POINTER(sz)]
         L.ldpc_decode_batch.argtypes = [vp, i32, vp, ctypes.POINTER(DecodeParams), vp, vp, vp,
                                         vp, vp, sz, vp]
+        u32, dbl = ctypes.c_uint32, ctypes.c_double
+        L.ldpc_encoder_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), vp]
+        L.ldpc_encode_batch.argtypes = [vp, i32, vp, vp, vp]
+        L.ldpc_random_bits.argtypes = [i32, i32, u32, u32, u32, u32, vp, vp]
+        L.ldpc_channel_awgn.argtypes = [i32, i32, vp, vp, u32, u32, u32, u32, vp, vp, dbl, i32, vp]
+        L.ldpc_count_errors.argtypes = [i32, i32, vp, vp, vp, vp]
         for f in ("ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query",
-                  "ldpc_decode_workspace_size", "ldpc_decode_batch"):
+                  "ldpc_decode_workspace_size", "ldpc_decode_batch", "ldpc_encoder_info",
+                  "ldpc_encode_batch", "ldpc_random_bits", "ldpc_channel_awgn", "ldpc_count_errors"):
             getattr(L, f).restype = ctypes.c_int
         L.ldpc_last_error.restype = ctypes.c_char_p
         L.ldpc_version.restype = ctypes.c_char_p
@@ -133,6 +144,22 @@ class Code:
             self.close()
         except Exception:
             pass
+
+    def encoder_info(self) -> dict:
+        """Systematic encoder of the code: kind, K and the column order
+        (K information columns, then the parity columns)."""
+        kind, k = ctypes.c_int32(), ctypes.c_int32()
+        pos = np.empty(self.N, dtype=np.int32)
+        _check(lib().ldpc_encoder_info(self._h, ctypes.byref(kind), ctypes.byref(k),
+                                       pos.ctypes.data_as(ctypes.c_void_p)))
+        return {"kind": ENC_KIND.get(kind.value, kind.value), "K": k.value, "info_pos": pos}
+
+    def encode(self, info) -> "torch.Tensor":
+        """uint8 [F, N] codewords of the uint8 [F, K] information words."""
+        F = int(info.shape[0])
+        out = torch.empty((F, self.N), dtype=torch.uint8, device=info.device)
+        _check(lib().ldpc_encode_batch(self._h, F, _ptr(info), _ptr(out), _stream()))
+        return out
 
     def info(self) -> dict:
         i = CodeInfo()
@@ -191,6 +218,43 @@ class Code:
         ws = self.alloc_workspace(F, p, llr.device)
         self.decode_into(llr, p, out["hard"], out["llr"], out["iters"], out["ok"], ws, stream)
         return out
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def random_bits(n_frames: int, n_bits: int, key=(0x5EED, 0), stream_id: int = 0,
+                frame_offset: int = 0, device="cuda") -> "torch.Tensor":
+    """uint8 [n_frames, n_bits] of Philox4x32-10 bits (include/ldpc_sim.h)."""
+    out = torch.empty((n_frames, n_bits), dtype=torch.uint8, device=device)
+    _check(lib().ldpc_random_bits(int(n_frames), int(n_bits), int(key[0]) & 0xFFFFFFFF,
+                                  int(key[1]) & 0xFFFFFFFF, int(stream_id), int(frame_offset),
+                                  _ptr(out), _stream()))
+    return out
+
+
+def channel_awgn(sigma, N: int, codewords=None, key=(0x5EED, 0), stream_id: int = 0,
+                 frame_offset: int = 0, want_f32: bool = True, want_q: bool = False,
+                 step: float = 0.5, qmax: int = 31):
+    """BPSK/AWGN channel LLRs for the frames of ``sigma`` (float64 device
+    tensor, one value per frame); returns (llr_f32 or None, llr_int8 or None)."""
+    F = int(sigma.shape[0])
+    dev = sigma.device
+    f32 = torch.empty((F, N), dtype=torch.float32, device=dev) if want_f32 else None
+    q = torch.empty((F, N), dtype=torch.int8, device=dev) if want_q else None
+    _check(lib().ldpc_channel_awgn(F, int(N), _ptr(codewords), _ptr(sigma), int(key[0]) & 0xFFFFFFFF,
+                                   int(key[1]) & 0xFFFFFFFF, int(stream_id), int(frame_offset),
+                                   _ptr(f32), _ptr(q), float(step), int(qmax), _stream()))
+    return f32, q
+
+
+def count_errors(hard, codewords=None) -> "torch.Tensor":
+    """int32 [F]: bit errors of each frame's hard decision against its codeword."""
+    F, N = int(hard.shape[0]), int(hard.shape[1])
+    out = torch.empty((F,), dtype=torch.int32, device=hard.device)
+    _check(lib().ldpc_count_errors(F, N, _ptr(hard), _ptr(codewords), _ptr(out), _stream()))
+    return out
 
 
 def version() -> str:

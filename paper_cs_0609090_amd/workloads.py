@@ -154,6 +154,20 @@ def normals(n_frames: int, n: int, key: tuple[int, int], stream: int = 0,
     return z.reshape(n_frames, nb * 4)[:, :n]
 
 
+def random_bits(n_frames: int, n_bits: int, key: tuple[int, int], stream: int = 0,
+                frame_offset: int = 0) -> np.ndarray:
+    """Uniform bits [n_frames, n_bits] (uint8): bit b of frame f is bit
+    (b mod 32) of word (b mod 128) / 32 of the Philox4x32-10 block for counter
+    (b / 128, frame_offset + f, stream, 0)."""
+    nb = (n_bits + 127) // 128
+    i = np.tile(np.arange(nb, dtype=np.uint64), n_frames)
+    f = np.repeat(np.arange(n_frames, dtype=np.uint64) + np.uint64(frame_offset), nb)
+    w = philox4x32_10(i, f, np.full_like(i, stream), np.zeros_like(i), key[0], key[1])
+    words = np.stack(w, axis=1).reshape(n_frames, nb * 4)          # word order w0..w3 per block
+    bits = (words[:, :, None] >> np.arange(32, dtype=np.uint32)) & 1  # bit order 0..31 per word
+    return bits.reshape(n_frames, nb * 128)[:, :n_bits].astype(np.uint8)
+
+
 def ebn0_to_sigma(ebn0_db: float, rate: float) -> float:
     """Noise standard deviation for unit-energy BPSK at code rate R:
     sigma^2 = 1 / (2 R 10^(Eb/N0 / 10))."""

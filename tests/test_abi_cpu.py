@@ -20,14 +20,19 @@ def L():
 
 
 def _declared_functions():
-    src = open(os.path.join(ROOT, "include", "ldpc.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(ldpc_\w+)\s*\(", src, flags=re.M)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not h.endswith(".h"):
+            continue
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(ldpc_\w+)\s*\(", src, flags=re.M))
+    return sorted(names)
 
 
 def test_exports_every_declared_symbol(L):
     names = _declared_functions()
-    assert len(names) >= 7
+    assert len(names) >= 12
     lib = L.lib()
     for n in names:
         assert hasattr(lib, n), n
@@ -188,3 +193,51 @@ def test_workspace_plans(L):
     assert ei.value.status == L.LDPC_EUNSUPPORTED
     big.close()
     small.close()
+
+
+def _gf2_rank(rows: np.ndarray) -> int:
+    """Rank over GF(2) of a 0/1 matrix (plain elimination on packed rows)."""
+    A = np.packbits(rows.astype(np.uint8), axis=1)
+    r = 0
+    ncols = rows.shape[1]
+    for c in range(ncols):
+        byte, bit = c // 8, 0x80 >> (c % 8)
+        piv = np.nonzero(A[r:, byte] & bit)[0]
+        if piv.size == 0:
+            continue
+        p = r + piv[0]
+        A[[r, p]] = A[[p, r]]
+        hit = np.nonzero(A[:, byte] & bit)[0]
+        hit = hit[hit != r]
+        A[hit] ^= A[r]
+        r += 1
+        if r == A.shape[0]:
+            break
+    return r
+
+
+@pytest.mark.parametrize("name", ["peg1008", "ira16200", "ira64800", "qc7493", "tiny"])
+def test_encoder_description(L, name):
+    """The systematic split the encoder reports is valid: K = N - rank(H) and
+    the parity columns carry a nonsingular submatrix (so every information
+    word has exactly one codeword).  IRA codes take the staircase form with
+    the information bits first."""
+    code = {"peg1008": W.code_c0_peg1008, "ira16200": W.code_ira16200, "ira64800": W.code_c2_ira64800,
+            "qc7493": W.code_c1_qc7493,
+            "tiny": lambda: W.random_small_code(9, 20, (2, 6), seed=77)}[name]()
+    c = L.Code.from_parity_check(code, device=-1)
+    e = c.encoder_info()
+    c.close()
+    pos = e["info_pos"]
+    K = e["K"]
+    assert sorted(pos.tolist()) == list(range(code.N))
+    assert list(pos[:K]) == sorted(pos[:K].tolist())
+    if name.startswith("ira"):
+        assert e["kind"] == "staircase" and K == code.N - code.M
+        assert list(pos) == list(range(code.N))
+        return
+    assert e["kind"] == "dense"
+    H = code.dense()
+    rank = _gf2_rank(H)
+    assert K == code.N - rank
+    assert _gf2_rank(H[:, pos[K:]]) == rank
