@@ -64,7 +64,9 @@ typedef enum {
                                    frame (single-scan INT8/1BIT; codes with an instantiated
                                    shape, see ldpc_code_info.reg_* / pk_*); INT8 and 1BIT
                                    use the packed two-rows-per-lane kernel when it has a
-                                   shape.
+                                   shape.  AUTO picks, for fixed point: the packed kernel
+                                   from 16 rows per thread (M > 8192), the one-row register
+                                   kernel below that, LDS-resident kernels for M <= 1024.
                                    AUTO prefers this layout */
 #define LDPC_LAYOUT_REG1 4      /* as LDPC_LAYOUT_REG, one row at a time (no packing) */
 #define LDPC_LAYOUT_FRAMES 5    /* single-scan FP32 and the two-scan baseline (INT8, FP32):

@@ -80,9 +80,16 @@ ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl)
     const bool allow_hbm = layout == LDPC_LAYOUT_AUTO || layout == LDPC_LAYOUT_HBM;
 
     const bool reg_layout = layout == LDPC_LAYOUT_REG || layout == LDPC_LAYOUT_REG1;
-    if (p->sched == LDPC_SINGLE_SCAN && p->msg != LDPC_MSG_FP32 &&
+    // AUTO for fixed point (measured on MI355X, 50 iterations): the packed
+    // two-rows-per-lane kernel pays off from 16 rows per thread (M > 8192);
+    // below that the one-row register kernel is faster, and codes of at most
+    // 1024 checks run best LDS-resident with one thread per row (the register
+    // kernels give every frame 1024 threads).
+    const bool small_auto = layout == LDPC_LAYOUT_AUTO && c->M <= 1024;
+    if (p->sched == LDPC_SINGLE_SCAN && p->msg != LDPC_MSG_FP32 && !small_auto &&
         (layout == LDPC_LAYOUT_AUTO || reg_layout)) {
-        const bool packed = c->pkD > 0 && layout != LDPC_LAYOUT_REG1;  // int8 and 1-bit
+        const bool packed = c->pkD > 0 && layout != LDPC_LAYOUT_REG1 &&
+                            (layout == LDPC_LAYOUT_REG || c->pkR >= 16);  // int8 and 1-bit
         const bool ok = packed || (c->regD > 0 && (p->msg == LDPC_MSG_INT8 || c->regD + 15 <= 32));
         if (ok) {
             pl->family = packed ? 4 : 3;
