@@ -65,16 +65,17 @@ def _check_update(tm, a, b):
     K = np.empty((F, R, d), dtype=np.int64)
     MN = np.empty_like(tm)
     SG = np.empty_like(tm)
+    zero = tm.dtype.type(0)
     ACT = np.empty(tm.shape, dtype=bool)
     for j in range(d):
         others = np.array([k for k in range(d) if k != j])
         ab = np.abs(tm[:, :, others])
         pos = np.argmin(ab, axis=2)                       # first of equal minima
         mn = np.take_along_axis(ab, pos[:, :, None], axis=2)[:, :, 0]
-        sg = np.prod(np.where(tm[:, :, others] < 0, -1.0, 1.0), axis=2)
+        sg = np.prod(np.where(tm[:, :, others] < 0, -1.0, 1.0), axis=2).astype(tm.dtype)
         v = a[None, :] * mn - b[None, :]
         act = v > 0
-        L[:, :, j] = sg * np.where(act, v, 0.0)
+        L[:, :, j] = sg * np.where(act, v, zero)
         K[:, :, j] = others[pos]
         MN[:, :, j] = mn
         SG[:, :, j] = sg
@@ -82,13 +83,15 @@ def _check_update(tm, a, b):
     return L, K, MN, SG, ACT
 
 
-def forward(code, llr, weights, target=None):
+def forward(code, llr, weights, target=None, dtype=np.float64):
     """Unrolled decoder.  llr [F, N]; weights [T, C, 2] (a, b); target [F, N]
     bits or None (all-zero word).  Returns dict with per-iteration losses
     ``loss`` [T], posteriors ``Z`` [T+1, F, N] and messages ``L`` [T+1, F, E]
-    (CSR edge order)."""
-    llr = np.asarray(llr, dtype=np.float64)
-    W = np.asarray(weights, dtype=np.float64)
+    (CSR edge order).  ``dtype=np.float32`` runs every decoder operation in
+    binary32 (a*m rounded before b is subtracted, posterior sums in ascending
+    check order); the loss is then still summed in binary64."""
+    llr = np.asarray(llr, dtype=dtype)
+    W = np.asarray(weights, dtype=dtype)
     T = W.shape[0]
     F, N = llr.shape
     ci = np.asarray(code.col_idx)
@@ -98,11 +101,11 @@ def forward(code, llr, weights, target=None):
     x = np.zeros((F, N)) if target is None else np.asarray(target, dtype=np.float64)
     s = 2.0 * x - 1.0
     Zs = [llr.copy()]
-    Ls = [np.zeros((F, E))]
+    Ls = [np.zeros((F, E), dtype=dtype)]
     losses = []
     for t in range(1, T + 1):
         Zp, Lp = Zs[-1], Ls[-1]
-        Ln = np.zeros((F, E))
+        Ln = np.zeros((F, E), dtype=dtype)
         for d, rows, e, cols in groups:
             tm = Zp[:, cols] - Lp[:, e]
             a = W[t - 1, cls[rows], 0]
@@ -115,7 +118,7 @@ def forward(code, llr, weights, target=None):
             Zn[:, ci[k]] += Ln[:, k]
         Zs.append(Zn)
         Ls.append(Ln)
-        losses.append(float(np.sum(_softplus(s * Zn))))
+        losses.append(float(np.sum(_softplus(s * Zn.astype(np.float64)))))
     return {"loss": np.array(losses), "Z": np.stack(Zs), "L": np.stack(Ls)}
 
 

@@ -27,6 +27,20 @@ def test_forward_equals_single_scan_f64(orc, alpha, beta):
         np.testing.assert_array_equal(fw["Z"][t], r["Z"][:, t - 1, :])
 
 
+def test_forward_binary32_equals_single_scan_f32(orc):
+    code = W.code_c0_peg1008()
+    llr = W.awgn_llr(code.N, 3, 1.8, code.design_rate, key=(0x1EA, 3))
+    T = 6
+    w = np.zeros((T, 1, 2), dtype=np.float32)
+    w[:, :, 0], w[:, :, 1] = 0.8, 0.25
+    fw = LO.forward(code, llr, w, dtype=np.float32)
+    r = orc.decode(code, llr, algo="single_scan", arith="f32", max_iter=T, alpha=0.8, beta=0.25,
+                   early_stop=False, trace=True)
+    assert fw["Z"].dtype == np.float32
+    for t in range(1, T + 1):
+        np.testing.assert_array_equal(fw["Z"][t], r["Z"][:, t - 1, :])
+
+
 def test_classes_of_irregular_rows():
     code = W.random_small_code(12, 30, (3, 7), seed=5)
     deg, cls, levels = LO.degree_classes(code)
