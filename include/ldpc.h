@@ -89,6 +89,12 @@ typedef enum {
  *             |L| = max(((m*a8 + 128) >> 8) - b, 0).
  *  early_stop nonzero: stop a frame after the first iteration k >= 1 whose
  *             hard decision satisfies H x^T = 0 (Sec. III decoding step).
+ *  weights    NULL, or device float32 [weight_iters][C][2]: per iteration k
+ *             (row min(k, weight_iters) - 1) and check-degree class c (the
+ *             distinct row degrees ascending, see ldpc_learn.h) the pair
+ *             (a, b) replacing (alpha, beta).  FP32 single-scan only (it runs
+ *             frames across lanes); other paths return LDPC_EUNSUPPORTED.
+ *  weight_iters rows of `weights` (>= 1 when weights is set).
  */
 typedef struct {
     int32_t max_iter;
@@ -99,6 +105,8 @@ typedef struct {
     int32_t sched; /* ldpc_sched */
     float llr_step;
     uint32_t flags;
+    const float *weights;
+    int32_t weight_iters;
 } ldpc_decode_params;
 
 /* Facts about a code handle and its planned device layouts. */

@@ -46,6 +46,10 @@ struct ldpc_code {
     int32_t *d_info_pos = nullptr;    // device copy
     uint32_t *d_enc_rows = nullptr;   // dense: [rank][words] parity map over the information bits
     std::string enc_error;
+    // learned decoder: check-degree classes (distinct row degrees, ascending)
+    int32_t learn_classes = 0;
+    std::vector<int32_t> learn_degrees;
+    int32_t *d_row_cls = nullptr;  // [M] class of each row
 };
 
 namespace ldpc {

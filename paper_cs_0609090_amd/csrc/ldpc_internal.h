@@ -78,7 +78,8 @@ size_t ts_fl_workspace_bytes(int N, int64_t E, int n_frames, int max_iter, bool 
 hipError_t launch_two_scan_fl(const DecodeArgs &d, bool int8, const int32_t *row_ptr, const uint32_t *row_ent,
                               const uint32_t *vc_csr, int64_t E, int max_row_deg, int cu_count, hipStream_t s);
 hipError_t launch_ss_f32_fl(const DecodeArgs &a, const int32_t *row_ptr, const uint32_t *row_ent, int64_t E,
-                            int max_row_deg, int cu_count, hipStream_t s);
+                            int max_row_deg, int cu_count, const float *weights, int weight_iters,
+                            const int32_t *row_cls, int n_classes, hipStream_t s);
 hipError_t launch_two_scan(const DecodeArgs &a, int msg, const LaunchCfg &cfg, hipStream_t s);
 hipError_t launch_ss_reg(const DecodeArgs &a, int msg, int D, int R, int P, size_t lds, hipStream_t s);
 hipError_t launch_ss_pk(const DecodeArgs &a, int D, int R, bool onebit, size_t lds, hipStream_t s);

@@ -64,6 +64,9 @@ ldpc_status validate_params(const ldpc_decode_params *p) {
         return fail(LDPC_EUNSUPPORTED, "two-scan has no 1-bit form (Sec. V compresses single-scan)");
     const uint32_t layout = (p->flags >> LDPC_F_LAYOUT_SHIFT) & 0xFu;
     if (layout > LDPC_LAYOUT_FRAMES) return fail(LDPC_EINVAL, "unknown layout override");
+    if (p->weights && p->weight_iters < 1) return fail(LDPC_EINVAL, "weight_iters must be >= 1 with weights");
+    if (p->weights && (p->msg != LDPC_MSG_FP32 || p->sched != LDPC_SINGLE_SCAN))
+        return fail(LDPC_EUNSUPPORTED, "per-iteration weights: FP32 single-scan only");
     return LDPC_OK;
 }
 
@@ -109,6 +112,14 @@ ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl)
             return fail(LDPC_EUNSUPPORTED, "no register-resident shape for this code and message type");
     }
     if (reg_layout) return fail(LDPC_EUNSUPPORTED, "register layout is single-scan INT8/1BIT only");
+    if (p->weights) {  // the weighted decoder runs frames across lanes
+        if (layout != LDPC_LAYOUT_AUTO && layout != LDPC_LAYOUT_FRAMES)
+            return fail(LDPC_EUNSUPPORTED, "per-iteration weights need the frames-across-lanes layout");
+        if (ldpc::fl_chunk_frames(c->N, c->E) <= 0)
+            return fail(LDPC_EUNSUPPORTED, "code too large for the frames-across-lanes layout");
+        pl->family = 5;
+        return LDPC_OK;
+    }
     if (layout == LDPC_LAYOUT_FRAMES) {
         if (p->sched == LDPC_TWO_SCAN) {
             if (ldpc::ts_fl_chunk_frames(c->N, c->E, p->msg == LDPC_MSG_INT8) <= 0)
@@ -350,6 +361,18 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
     c->min_row_deg = dmin;
     c->h_row_ptr.assign(row_ptr, row_ptr + M + 1);
     c->h_col_idx.assign(col_idx, col_idx + nnz);
+    std::vector<int32_t> row_cls(M);
+    {
+        std::vector<int32_t> degs(M);
+        for (int m = 0; m < M; ++m) degs[m] = row_ptr[m + 1] - row_ptr[m];
+        c->learn_degrees = degs;
+        std::sort(c->learn_degrees.begin(), c->learn_degrees.end());
+        c->learn_degrees.erase(std::unique(c->learn_degrees.begin(), c->learn_degrees.end()), c->learn_degrees.end());
+        c->learn_classes = (int32_t)c->learn_degrees.size();
+        for (int m = 0; m < M; ++m)
+            row_cls[m] = (int32_t)(std::lower_bound(c->learn_degrees.begin(), c->learn_degrees.end(), degs[m]) -
+                                   c->learn_degrees.begin());
+    }
     const size_t slots = (size_t)c->D * c->Mp;
     std::vector<uint32_t> ell(slots, (uint32_t)c->dummy);
     std::vector<int32_t> vc_ptr((size_t)N + 1, 0);
@@ -451,6 +474,7 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
     hipError_t e7 = hipMalloc(&c->d_row_ptr, ((size_t)M + 1) * sizeof(int32_t));
     hipError_t e8 = hipMalloc(&c->d_row_ent, row_ent.size() * sizeof(uint32_t));
     hipError_t e9 = hipMalloc(&c->d_vc_csr, vc_csr.size() * sizeof(uint32_t));
+    hipError_t e10 = hipMalloc(&c->d_row_cls, sizeof(int32_t) * std::max<size_t>(row_cls.size(), 1));
     hipError_t e2 = hipMalloc(&c->d_vc_ptr, vc_ptr.size() * sizeof(int32_t));
     hipError_t e3 = hipMalloc(&c->d_vc_slot, vc_slot.size() * sizeof(uint32_t));
     std::vector<uint32_t> ell_reg;
@@ -498,7 +522,7 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
         e6 = hipMalloc(&c->d_pk_slot, pk_slot.size() * sizeof(uint32_t));
     }
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || e5 != hipSuccess ||
-        e6 != hipSuccess || e7 != hipSuccess || e8 != hipSuccess || e9 != hipSuccess) {
+        e6 != hipSuccess || e7 != hipSuccess || e8 != hipSuccess || e9 != hipSuccess || e10 != hipSuccess) {
         ldpc_code_destroy(c);
         (void)hipGetLastError();
         return fail(LDPC_ENOMEM, "device allocation failed");
@@ -510,6 +534,8 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
         hipMemcpy(c->d_row_ent, row_ent.data(), row_ent.size() * sizeof(uint32_t), hipMemcpyHostToDevice) !=
             hipSuccess ||
         hipMemcpy(c->d_vc_csr, vc_csr.data(), vc_csr.size() * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_row_cls, row_cls.data(), sizeof(int32_t) * row_cls.size(), hipMemcpyHostToDevice) !=
+            hipSuccess ||
         (c->d_ell_reg && hipMemcpy(c->d_ell_reg, ell_reg.data(), ell_reg.size() * sizeof(uint32_t),
                                    hipMemcpyHostToDevice) != hipSuccess) ||
         (c->d_pk_idx && hipMemcpy(c->d_pk_idx, pk_idx.data(), pk_idx.size() * sizeof(uint32_t),
@@ -538,6 +564,7 @@ ldpc_status ldpc_code_destroy(ldpc_code *code) {
     if (code->d_row_ent) (void)hipFree(code->d_row_ent);
     if (code->d_vc_csr) (void)hipFree(code->d_vc_csr);
     if (code->d_info_pos) (void)hipFree(code->d_info_pos);
+    if (code->d_row_cls) (void)hipFree(code->d_row_cls);
     if (code->d_enc_rows) (void)hipFree(code->d_enc_rows);
     if (code->d_ell_reg) (void)hipFree(code->d_ell_reg);
     if (code->d_pk_idx) (void)hipFree(code->d_pk_idx);
@@ -684,8 +711,8 @@ ldpc_status ldpc_decode_batch(const ldpc_code *c, int32_t n_frames, const void *
         e = ldpc::launch_two_scan_fl(a, p->msg == LDPC_MSG_INT8, c->d_row_ptr, c->d_row_ent, c->d_vc_csr, c->E,
                                      c->D, c->cu_count, s);
     else if (pl.family == 5)
-        e = ldpc::launch_ss_f32_fl(a, c->d_row_ptr, c->d_row_ent, c->E, c->D,
-                                   c->cu_count, s);
+        e = ldpc::launch_ss_f32_fl(a, c->d_row_ptr, c->d_row_ent, c->E, c->D, c->cu_count, p->weights,
+                                   p->weight_iters, c->d_row_cls, c->learn_classes, s);
     else
         e = ldpc::launch_two_scan(a, p->msg, pl.cfg, s);
     if (e != hipSuccess) return fail(LDPC_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));

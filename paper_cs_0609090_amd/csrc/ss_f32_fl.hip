@@ -48,6 +48,9 @@ struct FlArgs {
     float *L;                // [E][Fp] messages, variable-major edge order
     int32_t *fail;           // [K+1][Fp] 1 = syndrome of Z^(k) not satisfied
     int32_t *conv;           // [Fp] first iteration whose syndrome passed
+    const float *W;          // null, or [Tw][C][2] (a, b) per iteration and row-degree class
+    int32_t Tw, C;
+    const int32_t *row_cls;  // [M] class of each row (with W)
 };
 
 __device__ __forceinline__ float norm_f(float m, float alpha, float beta) {
@@ -61,7 +64,7 @@ __device__ __forceinline__ float norm_f(float m, float alpha, float beta) {
 // FIRST: L^(k-1) = 0 (iteration 1), the message array is not read.
 template <int DMAX, bool UPDATE, bool FIRST>
 __global__ void __launch_bounds__(kBlock) fl_check(FlArgs a, const float *__restrict__ zold, int syn_row,
-                                                   int conv_k) {
+                                                   int conv_k, int it) {
     const int lane = threadIdx.x & 63;
     const int w = wave_id();
     const int Fp = a.Fp;
@@ -113,8 +116,15 @@ __global__ void __launch_bounds__(kBlock) fl_check(FlArgs a, const float *__rest
         }
         if (syn_row >= 0 && syn) a.fail[(size_t)syn_row * Fp + f] = 1;
         if (UPDATE) {
-            const float A = norm_f(min1, a.alpha, a.beta);
-            const float B = norm_f(min2, a.alpha, a.beta);
+            float wa = a.alpha, wb = a.beta;
+            if (a.W) {  // per-iteration, per-class pair
+                const auto *Wt = cptr(a.W) + (size_t)(min(it, a.Tw) - 1) * a.C * 2;
+                const int c = cptr(a.row_cls)[m];
+                wa = Wt[2 * c];
+                wb = Wt[2 * c + 1];
+            }
+            const float A = norm_f(min1, wa, wb);
+            const float B = norm_f(min2, wa, wb);
             float out[DMAX];
 #pragma unroll
             for (int j = 0; j < DMAX; ++j) {
@@ -185,10 +195,10 @@ hipError_t run(const DecodeArgs &d, const FlArgs &a, int K, unsigned grid, hipSt
         const int conv_k = (es && k >= 3) ? k - 2 : 0;
         if (k == 1)
             hipLaunchKernelGGL((fl_check<DMAX, true, true>), dim3(grid), dim3(kBlock), 0, s, a, zold, syn_row,
-                               conv_k);
+                               conv_k, k);
         else
             hipLaunchKernelGGL((fl_check<DMAX, true, false>), dim3(grid), dim3(kBlock), 0, s, a, zold, syn_row,
-                               conv_k);
+                               conv_k, k);
         if (es && k >= 2)
             hipLaunchKernelGGL(fl_var<true>, dim3(grid), dim3(kBlock), 0, s, a, zold, znew, k - 1);
         else
@@ -197,7 +207,7 @@ hipError_t run(const DecodeArgs &d, const FlArgs &a, int K, unsigned grid, hipSt
     }
     // syndrome of the final posteriors, then the outputs
     hipLaunchKernelGGL((fl_check<DMAX, false, false>), dim3(grid), dim3(kBlock), 0, s, a, zold, K,
-                       (es && K >= 3) ? K - 2 : 0);
+                       (es && K >= 3) ? K - 2 : 0, K);
     hipLaunchKernelGGL(frame_out, dim3((unsigned)((a.F + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a.fail, a.conv,
                        a.F, a.Fp, K, d.early_stop, d.iters_out, d.ok_out);
     hipLaunchKernelGGL(transpose_out<float>, tgrid, dim3(kBlock), 0, s, zold, a.N, a.F, a.Fp, 1.0, d.hard_out,
@@ -218,7 +228,8 @@ size_t fl_workspace_bytes(int N, int64_t E, int n_frames, int max_iter) {
 }
 
 hipError_t launch_ss_f32_fl(const DecodeArgs &d, const int32_t *row_ptr, const uint32_t *row_ent, int64_t E,
-                            int max_row_deg, int cu_count, hipStream_t s) {
+                            int max_row_deg, int cu_count, const float *weights, int weight_iters,
+                            const int32_t *row_cls, int n_classes, hipStream_t s) {
     const int chunk = fl_chunk_frames(d.c.N, E);
     if (chunk <= 0 || max_row_deg > 64) return hipErrorInvalidValue;
     for (int c0 = 0; c0 < d.n_frames; c0 += chunk) {
@@ -241,6 +252,10 @@ hipError_t launch_ss_f32_fl(const DecodeArgs &d, const int32_t *row_ptr, const u
         a.row_ptr = row_ptr;
         a.row_ent = row_ent;
         a.vc_ptr = d.c.vc_ptr;
+        a.W = weights;
+        a.Tw = weight_iters;
+        a.C = n_classes;
+        a.row_cls = row_cls;
         const size_t Fp = (size_t)a.Fp;
         a.ebytes = (uint32_t)((size_t)E * Fp * 4);
         uint8_t *p = d.ws;

@@ -33,7 +33,10 @@ EXPORTS = ("ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query",
            "ldpc_version",
            # include/ldpc_sim.h
            "ldpc_encoder_info", "ldpc_encode_batch", "ldpc_random_bits", "ldpc_channel_awgn",
-           "ldpc_count_errors")
+           "ldpc_count_errors",
+           # include/ldpc_learn.h
+           "ldpc_learn_classes", "ldpc_learn_workspace_size", "ldpc_learn_forward",
+           "ldpc_learn_backward")
 ENC_KIND = {0: "none", 1: "staircase", 2: "dense"}
 
 
@@ -47,7 +50,8 @@ class DecodeParams(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("alpha", ctypes.c_float),
                 ("beta", ctypes.c_float), ("early_stop", ctypes.c_int32),
                 ("msg", ctypes.c_int32), ("sched", ctypes.c_int32),
-                ("llr_step", ctypes.c_float), ("flags", ctypes.c_uint32)]
+                ("llr_step", ctypes.c_float), ("flags", ctypes.c_uint32),
+                ("weights", ctypes.c_void_p), ("weight_iters", ctypes.c_int32)]
 
 
 class CodeInfo(ctypes.Structure):
@@ -87,9 +91,15 @@ def lib():
         L.ldpc_random_bits.argtypes = [i32, i32, u32, u32, u32, u32, vp, vp]
         L.ldpc_channel_awgn.argtypes = [i32, i32, vp, vp, u32, u32, u32, u32, vp, vp, dbl, i32, vp]
         L.ldpc_count_errors.argtypes = [i32, i32, vp, vp, vp, vp]
+        L.ldpc_learn_classes.argtypes = [vp, ctypes.POINTER(i32), vp]
+        L.ldpc_learn_workspace_size.argtypes = [vp, i32, i32, i32, ctypes.POINTER(sz)]
+        L.ldpc_learn_forward.argtypes = [vp, i32, vp, vp, i32, vp, i32, vp, sz, vp, vp, vp]
+        L.ldpc_learn_backward.argtypes = [vp, i32, vp, i32, vp, i32, vp, sz, vp, vp]
         for f in ("ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query",
                   "ldpc_decode_workspace_size", "ldpc_decode_batch", "ldpc_encoder_info",
-                  "ldpc_encode_batch", "ldpc_random_bits", "ldpc_channel_awgn", "ldpc_count_errors"):
+                  "ldpc_encode_batch", "ldpc_random_bits", "ldpc_channel_awgn", "ldpc_count_errors",
+                  "ldpc_learn_classes", "ldpc_learn_workspace_size", "ldpc_learn_forward",
+                  "ldpc_learn_backward"):
             getattr(L, f).restype = ctypes.c_int
         L.ldpc_last_error.restype = ctypes.c_char_p
         L.ldpc_version.restype = ctypes.c_char_p
@@ -103,12 +113,17 @@ def _check(status: int):
 
 
 def make_params(max_iter=50, alpha=0.8, beta=0.0, early_stop=True, msg="int8",
-                sched="single_scan", llr_step=0.5, check_input=False, layout="auto") -> DecodeParams:
+                sched="single_scan", llr_step=0.5, check_input=False, layout="auto",
+                weights=None) -> DecodeParams:
+    """``weights``: None, or a float32 device tensor [T][C][2] of per-iteration,
+    per-class (a, b) pairs (FP32 single-scan); it must outlive the call."""
     flags = (F_CHECK_INPUT if check_input else 0) | (LAYOUT[layout] << LAYOUT_SHIFT)
+    wp = None if weights is None else weights.data_ptr()
+    wt = 0 if weights is None else int(weights.shape[0])
     return DecodeParams(int(max_iter), float(alpha), float(beta), 1 if early_stop else 0,
                         MSG[msg] if isinstance(msg, str) else int(msg),
                         SCHED[sched] if isinstance(sched, str) else int(sched),
-                        float(llr_step), int(flags))
+                        float(llr_step), int(flags), wp, wt)
 
 
 def _ptr(t):
@@ -144,6 +159,36 @@ class Code:
             self.close()
         except Exception:
             pass
+
+    def degree_classes(self) -> np.ndarray:
+        """Check-degree classes of the learned decoder (distinct row degrees)."""
+        n = ctypes.c_int32()
+        _check(lib().ldpc_learn_classes(self._h, ctypes.byref(n), None))
+        d = np.empty(n.value, dtype=np.int32)
+        _check(lib().ldpc_learn_classes(self._h, ctypes.byref(n), d.ctypes.data_as(ctypes.c_void_p)))
+        return d
+
+    def learn_workspace_size(self, n_frames: int, T: int, ckpt: int) -> int:
+        b = ctypes.c_size_t()
+        _check(lib().ldpc_learn_workspace_size(self._h, int(n_frames), int(T), int(ckpt), ctypes.byref(b)))
+        return b.value
+
+    def learn_forward(self, llr, target, weights, ckpt, workspace, post_out=None):
+        """Raw forward pass (include/ldpc_learn.h); returns the per-iteration loss [T]."""
+        T = int(weights.shape[0])
+        loss = torch.empty(T, dtype=torch.float32, device=llr.device)
+        _check(lib().ldpc_learn_forward(self._h, int(llr.shape[0]), _ptr(llr), _ptr(target), T, _ptr(weights),
+                                        int(ckpt), _ptr(workspace), workspace.numel(), _ptr(loss),
+                                        _ptr(post_out), _stream()))
+        return loss
+
+    def learn_backward(self, n_frames, target, weights, ckpt, workspace):
+        """Raw adjoint: d(sum of the forward's losses)/d(weights), [T][C][2]."""
+        grad = torch.empty_like(weights)
+        _check(lib().ldpc_learn_backward(self._h, int(n_frames), _ptr(target), int(weights.shape[0]),
+                                         _ptr(weights), int(ckpt), _ptr(workspace), workspace.numel(),
+                                         _ptr(grad), _stream()))
+        return grad
 
     def encoder_info(self) -> dict:
         """Systematic encoder of the code: kind, K and the column order
@@ -200,7 +245,7 @@ class Code:
 
     def decode(self, llr, max_iter=50, alpha=0.8, beta=0.0, early_stop=True, msg=None,
                sched="single_scan", llr_step=0.5, check_input=False, layout="auto",
-               with_llr=True, stream=None) -> dict:
+               with_llr=True, stream=None, weights=None) -> dict:
         """Decode a [F, N] device tensor (float32 or int8) and return device
         tensors ``hard``, ``llr``, ``iters``, ``ok``."""
         if not llr.is_cuda:
@@ -212,7 +257,7 @@ class Code:
         if llr.dtype != want:
             raise ValueError(f"msg={msg} needs a {want} tensor")
         p = make_params(max_iter, alpha, beta, early_stop, msg, sched, llr_step,
-                        check_input, layout)
+                        check_input, layout, weights)
         F = llr.shape[0]
         out = self.alloc_outputs(F, llr.device, with_llr)
         ws = self.alloc_workspace(F, p, llr.device)

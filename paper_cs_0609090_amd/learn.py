@@ -1,0 +1,152 @@
+"""Learned normalised/offset min-sum (include/ldpc_learn.h): training and
+evaluation on the GPU.
+
+``LearnedMinSum.apply(weights, code, llr, target, ckpt, workspace)`` is the
+summed BCE loss of the decoder unrolled over T = weights.shape[0] iterations
+with the per-iteration, per-class pairs ``weights`` [T][C][2]; its backward
+is the library's adjoint kernel.  ``train`` fits the pairs with Adam on
+frames drawn on the GPU (random codewords, BPSK/AWGN with Eb/N0 uniform per
+frame); ``evaluate`` decodes fresh frames with the trained pairs through
+``ldpc_decode_batch`` (per-frame early stop) next to plain NMS, on the same
+frames, and reports FER and average iterations.
+
+    python -m paper_cs_0609090_amd.learn --code peg1008 --T 20 --steps 1024
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import time
+
+import numpy as np
+import torch
+
+from . import fer as FER
+from . import ldpc
+
+
+class LearnedMinSum(torch.autograd.Function):
+    """Summed loss of the unrolled decoder; gradients only for the weights."""
+
+    @staticmethod
+    def forward(ctx, weights, gcode, llr, target, ckpt, workspace):
+        w = weights.detach().contiguous()
+        loss_t = gcode.learn_forward(llr, target, w, ckpt, workspace)
+        ctx.gcode, ctx.target, ctx.ckpt, ctx.workspace, ctx.n = gcode, target, ckpt, workspace, llr.shape[0]
+        ctx.save_for_backward(w)
+        return loss_t.sum()
+
+    @staticmethod
+    def backward(ctx, g):
+        (w,) = ctx.saved_tensors
+        grad = ctx.gcode.learn_backward(ctx.n, ctx.target, w, ctx.ckpt, ctx.workspace)
+        return grad * g, None, None, None, None, None
+
+
+def _frames(gcode, K, n, ebn0_lo, ebn0_hi, key, offset, rng):
+    """n random codewords and their binary32 channel LLRs (Eb/N0 uniform per frame)."""
+    info = ldpc.random_bits(n, K, key=key, stream_id=1, frame_offset=offset)
+    cw = gcode.encode(info)
+    eb = rng.uniform(ebn0_lo, ebn0_hi, size=n)
+    rate = K / gcode.N
+    sig = torch.tensor([FER.sigma_for(float(e), rate) for e in eb], dtype=torch.float64, device="cuda")
+    llr, _ = ldpc.channel_awgn(sig, gcode.N, codewords=cw, key=key, stream_id=0, frame_offset=offset)
+    return llr, cw
+
+
+def init_weights(n_classes: int, T: int, alpha: float = 0.8, beta: float = 0.0) -> torch.Tensor:
+    w = torch.empty((T, n_classes, 2), dtype=torch.float32, device="cuda")
+    w[:, :, 0] = alpha
+    w[:, :, 1] = beta
+    return w
+
+
+def train(gcode, T: int = 20, steps: int = 1024, batch: int = 1024, ebn0=(1.5, 2.5), lr: float = 0.01,
+          ckpt: int = 5, key=(0x7EA, 1), seed: int = 0, log_every: int = 64, init=(0.8, 0.0)):
+    """Adam on the [T][C][2] pairs; returns (weights, log)."""
+    C = len(gcode.degree_classes())
+    K = gcode.encoder_info()["K"]
+    w = init_weights(C, T, *init).requires_grad_(True)
+    opt = torch.optim.Adam([w], lr=lr)
+    ws = torch.empty(gcode.learn_workspace_size(batch, T, ckpt), dtype=torch.uint8, device="cuda")
+    rng = np.random.default_rng(seed)
+    log = []
+    scale = 1.0 / (batch * gcode.N * T)
+    t0 = time.time()
+    for step in range(steps):
+        llr, cw = _frames(gcode, K, batch, ebn0[0], ebn0[1], key, step * batch, rng)
+        loss = LearnedMinSum.apply(w, gcode, llr, cw, ckpt, ws) * scale
+        opt.zero_grad()
+        loss.backward()
+        opt.step()
+        with torch.no_grad():
+            w[:, :, 0].clamp_(0.05, 1.5)
+            w[:, :, 1].clamp_(0.0, 4.0)
+        if step % log_every == 0 or step == steps - 1:
+            log.append({"step": step, "loss": float(loss.detach()), "s": time.time() - t0})
+    return w.detach(), log
+
+
+def evaluate(gcode, weights, ebn0_db: float, frames: int, batch: int = 4096, nms_alpha: float = 0.8,
+             nms_iters: int = 50, key=(0x5EED, 9), offset: int = 1 << 24):
+    """FER / BER / average iterations of the learned decoder (T = weights
+    rows, early stop) and of plain NMS (nms_iters, early stop) on the same
+    random-codeword frames."""
+    K = gcode.encoder_info()["K"]
+    rate = K / gcode.N
+    sg = FER.sigma_for(ebn0_db, rate)
+    T = int(weights.shape[0])
+    pl = ldpc.make_params(max_iter=T, msg="fp32", early_stop=True, weights=weights)
+    pn = ldpc.make_params(max_iter=nms_iters, alpha=nms_alpha, msg="fp32", early_stop=True, layout="frames")
+    res = {"learned": np.zeros(4), "nms": np.zeros(4)}  # frame errors, bit errors, iterations, frames
+    done = 0
+    while done < frames:
+        n = min(batch, frames - done)
+        info = ldpc.random_bits(n, K, key=key, stream_id=1, frame_offset=offset + done)
+        cw = gcode.encode(info)
+        sig = torch.full((n,), sg, dtype=torch.float64, device="cuda")
+        llr, _ = ldpc.channel_awgn(sig, gcode.N, codewords=cw, key=key, stream_id=0, frame_offset=offset + done)
+        for name, p in (("learned", pl), ("nms", pn)):
+            out = gcode.alloc_outputs(n, "cuda", with_llr=False)
+            ws = gcode.alloc_workspace(n, p, "cuda")
+            gcode.decode_into(llr, p, out["hard"], None, out["iters"], out["ok"], ws)
+            errs = ldpc.count_errors(out["hard"], cw)
+            r = res[name]
+            r += np.array([int((errs > 0).sum()), int(errs.sum()), int(out["iters"].sum()), n])
+        done += n
+    out = {"ebn0_db": ebn0_db, "frames": frames, "T": T, "nms_alpha": nms_alpha, "nms_max_iter": nms_iters}
+    for name, r in res.items():
+        out[name] = {"fer": r[0] / r[3], "ber": r[1] / (r[3] * gcode.N), "avg_iters": r[2] / r[3],
+                     "frame_errors": int(r[0])}
+    out["iter_saving"] = 1.0 - out["learned"]["avg_iters"] / out["nms"]["avg_iters"]
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--code", default="peg1008", choices=sorted(FER.CODES))
+    ap.add_argument("--T", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=1024)
+    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--lr", type=float, default=0.01)
+    ap.add_argument("--ckpt", type=int, default=5)
+    ap.add_argument("--eval-ebn0", type=float, nargs="+", default=[1.5, 2.0, 2.5])
+    ap.add_argument("--eval-frames", type=int, default=100000)
+    ap.add_argument("--save", default=None, help="write the trained pairs (.npy)")
+    args = ap.parse_args(argv)
+    code = FER.CODES[args.code]()
+    gcode = ldpc.Code.from_parity_check(code)
+    w, log = train(gcode, T=args.T, steps=args.steps, batch=args.batch, lr=args.lr, ckpt=args.ckpt)
+    for r in log:
+        print(json.dumps({"train": r}), flush=True)
+    if args.save:
+        np.save(args.save, w.cpu().numpy())
+    print(json.dumps({"weights": w.cpu().numpy().round(4).tolist(),
+                      "classes": gcode.degree_classes().tolist()}), flush=True)
+    for e in args.eval_ebn0:
+        print(json.dumps(evaluate(gcode, w, e, args.eval_frames)), flush=True)
+    gcode.close()
+
+
+if __name__ == "__main__":
+    main()
