@@ -63,13 +63,16 @@ def init_weights(n_classes: int, T: int, alpha: float = 0.8, beta: float = 0.0) 
 
 def train(gcode, T: int = 20, steps: int = 1024, batch: int = 1024, ebn0=(1.5, 2.5), lr: float = 0.01,
           ckpt: int = 5, key=(0x7EA, 1), seed: int = 0, log_every: int = 64, init=(0.8, 0.0)):
-    """Adam on the [T][C][2] pairs; returns (weights, log)."""
+    """Adam on the [T][C][2] pairs; returns (weights, log).  The log holds
+    the training loss and the loss of one fixed validation batch (frames
+    outside the training stream), both per bit and iteration."""
     C = len(gcode.degree_classes())
     K = gcode.encoder_info()["K"]
     w = init_weights(C, T, *init).requires_grad_(True)
     opt = torch.optim.Adam([w], lr=lr)
     ws = torch.empty(gcode.learn_workspace_size(batch, T, ckpt), dtype=torch.uint8, device="cuda")
     rng = np.random.default_rng(seed)
+    vllr, vcw = _frames(gcode, K, batch, ebn0[0], ebn0[1], key, 1 << 28, np.random.default_rng(seed + 1))
     log = []
     scale = 1.0 / (batch * gcode.N * T)
     t0 = time.time()
@@ -83,20 +86,24 @@ def train(gcode, T: int = 20, steps: int = 1024, batch: int = 1024, ebn0=(1.5, 2
             w[:, :, 0].clamp_(0.05, 1.5)
             w[:, :, 1].clamp_(0.0, 4.0)
         if step % log_every == 0 or step == steps - 1:
-            log.append({"step": step, "loss": float(loss.detach()), "s": time.time() - t0})
+            with torch.no_grad():
+                vl = float(gcode.learn_forward(vllr, vcw, w.detach().contiguous(), ckpt, ws).sum()) * scale
+            log.append({"step": step, "loss": float(loss.detach()), "val_loss": vl, "s": time.time() - t0})
     return w.detach(), log
 
 
 def evaluate(gcode, weights, ebn0_db: float, frames: int, batch: int = 4096, nms_alpha: float = 0.8,
-             nms_iters: int = 50, key=(0x5EED, 9), offset: int = 1 << 24):
-    """FER / BER / average iterations of the learned decoder (T = weights
-    rows, early stop) and of plain NMS (nms_iters, early stop) on the same
-    random-codeword frames."""
+             nms_iters: int = 50, learned_iters: int | None = None, key=(0x5EED, 9), offset: int = 1 << 24):
+    """FER / BER / average iterations of the learned decoder (early stop; its
+    T = weights rows apply to the first T iterations and the last row to any
+    later one, up to learned_iters, default nms_iters) and of plain NMS
+    (nms_iters, early stop) on the same random-codeword frames."""
     K = gcode.encoder_info()["K"]
     rate = K / gcode.N
     sg = FER.sigma_for(ebn0_db, rate)
     T = int(weights.shape[0])
-    pl = ldpc.make_params(max_iter=T, msg="fp32", early_stop=True, weights=weights)
+    li = nms_iters if learned_iters is None else learned_iters
+    pl = ldpc.make_params(max_iter=li, msg="fp32", early_stop=True, weights=weights)
     pn = ldpc.make_params(max_iter=nms_iters, alpha=nms_alpha, msg="fp32", early_stop=True, layout="frames")
     res = {"learned": np.zeros(4), "nms": np.zeros(4)}  # frame errors, bit errors, iterations, frames
     done = 0
@@ -114,7 +121,8 @@ def evaluate(gcode, weights, ebn0_db: float, frames: int, batch: int = 4096, nms
             r = res[name]
             r += np.array([int((errs > 0).sum()), int(errs.sum()), int(out["iters"].sum()), n])
         done += n
-    out = {"ebn0_db": ebn0_db, "frames": frames, "T": T, "nms_alpha": nms_alpha, "nms_max_iter": nms_iters}
+    out = {"ebn0_db": ebn0_db, "frames": frames, "T": T, "learned_max_iter": li, "nms_alpha": nms_alpha,
+           "nms_max_iter": nms_iters}
     for name, r in res.items():
         out[name] = {"fer": r[0] / r[3], "ber": r[1] / (r[3] * gcode.N), "avg_iters": r[2] / r[3],
                      "frame_errors": int(r[0])}
@@ -133,10 +141,17 @@ def main(argv=None):
     ap.add_argument("--eval-ebn0", type=float, nargs="+", default=[1.5, 2.0, 2.5])
     ap.add_argument("--eval-frames", type=int, default=100000)
     ap.add_argument("--save", default=None, help="write the trained pairs (.npy)")
+    ap.add_argument("--init-alpha", type=float, default=0.8)
+    ap.add_argument("--init-beta", type=float, default=0.0)
+    ap.add_argument("--ebn0-lo", type=float, default=1.5)
+    ap.add_argument("--ebn0-hi", type=float, default=2.5)
+    ap.add_argument("--learned-iters", type=int, default=None,
+                    help="iteration cap of the learned decoder at evaluation (default: NMS's 50)")
     args = ap.parse_args(argv)
     code = FER.CODES[args.code]()
     gcode = ldpc.Code.from_parity_check(code)
-    w, log = train(gcode, T=args.T, steps=args.steps, batch=args.batch, lr=args.lr, ckpt=args.ckpt)
+    w, log = train(gcode, T=args.T, steps=args.steps, batch=args.batch, lr=args.lr, ckpt=args.ckpt,
+                   ebn0=(args.ebn0_lo, args.ebn0_hi), init=(args.init_alpha, args.init_beta))
     for r in log:
         print(json.dumps({"train": r}), flush=True)
     if args.save:
@@ -144,7 +159,7 @@ def main(argv=None):
     print(json.dumps({"weights": w.cpu().numpy().round(4).tolist(),
                       "classes": gcode.degree_classes().tolist()}), flush=True)
     for e in args.eval_ebn0:
-        print(json.dumps(evaluate(gcode, w, e, args.eval_frames)), flush=True)
+        print(json.dumps(evaluate(gcode, w, e, args.eval_frames, learned_iters=args.learned_iters)), flush=True)
     gcode.close()
 
 
