@@ -7,6 +7,8 @@
 #include <string>
 #include <vector>
 
+#include <hip/hip_runtime.h>
+
 #include "../../include/ldpc.h"
 
 struct ldpc_code {
@@ -50,9 +52,31 @@ struct ldpc_code {
     int32_t learn_classes = 0;
     std::vector<int32_t> learn_degrees;
     int32_t *d_row_cls = nullptr;  // [M] class of each row
+    // layout used by LDPC_LAYOUT_AUTO per (msg, sched), index msg * 2 + sched;
+    // 0 = the built-in policy (set by ldpc_autotune, read atomically)
+    int32_t tuned_layout[6] = {0, 0, 0, 0, 0, 0};
 };
 
 namespace ldpc {
+// Makes `dev` the current device for the guard's lifetime.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+// ldpc_decode_batch: every check, then (when `launch`) the kernels on `stream`
+ldpc_status decode_job(const ldpc_code *c, int32_t n_frames, const void *llr_in, const ldpc_decode_params *p,
+                       uint8_t *hard_out, float *llr_out, int32_t *iters_out, uint8_t *syndrome_ok,
+                       void *workspace, size_t workspace_bytes, void *stream, bool launch);
+
 // error state of the calling thread (ldpc_last_error), set by every entry point
 ldpc_status set_error(ldpc_status st, const std::string &msg);
 void clear_error();

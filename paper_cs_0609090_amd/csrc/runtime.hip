@@ -26,18 +26,7 @@ ldpc_status fail(ldpc_status st, const std::string &msg) {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = true;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
+using ldpc::DeviceGuard;
 
 // Per-call layout plan (which state lives in LDS, which in the workspace).
 struct Plan {
@@ -73,7 +62,11 @@ ldpc_status validate_params(const ldpc_decode_params *p) {
 ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl) {
     const int D = c->D, Mp = c->Mp;
     const size_t nz = (size_t)c->dummy + 1;
-    const uint32_t layout = (p->flags >> LDPC_F_LAYOUT_SHIFT) & 0xFu;
+    uint32_t layout = (p->flags >> LDPC_F_LAYOUT_SHIFT) & 0xFu;
+    if (layout == LDPC_LAYOUT_AUTO && !p->weights) {  // a layout chosen by ldpc_autotune
+        const int32_t t = __atomic_load_n(&c->tuned_layout[p->msg * 2 + p->sched], __ATOMIC_RELAXED);
+        if (t > 0) layout = (uint32_t)t;
+    }
     const size_t limit = (size_t)c->lds_limit;
     const size_t aux = 16;
     int dmax = D <= 8 ? 8 : (D <= 16 ? 16 : (D <= 32 ? 32 : 64));
@@ -622,6 +615,17 @@ ldpc_status ldpc_decode_batch(const ldpc_code *c, int32_t n_frames, const void *
                               const ldpc_decode_params *p, uint8_t *hard_out, float *llr_out,
                               int32_t *iters_out, uint8_t *syndrome_ok, void *workspace,
                               size_t workspace_bytes, void *stream) {
+    return ldpc::decode_job(c, n_frames, llr_in, p, hard_out, llr_out, iters_out, syndrome_ok, workspace,
+                            workspace_bytes, stream, true);
+}
+
+}  // extern "C"
+
+namespace ldpc {
+
+ldpc_status decode_job(const ldpc_code *c, int32_t n_frames, const void *llr_in, const ldpc_decode_params *p,
+                       uint8_t *hard_out, float *llr_out, int32_t *iters_out, uint8_t *syndrome_ok,
+                       void *workspace, size_t workspace_bytes, void *stream, bool launch) {
     if (!c) return fail(LDPC_EINVAL, "code is NULL");
     if (n_frames < 0) return fail(LDPC_EINVAL, "n_frames < 0");
     ldpc_status st = validate_params(p);
@@ -645,7 +649,7 @@ ldpc_status ldpc_decode_batch(const ldpc_code *c, int32_t n_frames, const void *
     if (workspace && (reinterpret_cast<uintptr_t>(workspace) & 255u))
         return fail(LDPC_EINVAL, "workspace must be 256-byte aligned");
     if (c->device < 0) return fail(LDPC_EINVAL, "host-only handle (device < 0) cannot decode");
-    if (n_frames == 0) return LDPC_OK;
+    if (n_frames == 0 || !launch) return LDPC_OK;
 
     DeviceGuard g(c->device);
     if (!g.ok) return fail(LDPC_EDEVICE, "hipSetDevice failed");
@@ -719,4 +723,4 @@ ldpc_status ldpc_decode_batch(const ldpc_code *c, int32_t n_frames, const void *
     return LDPC_OK;
 }
 
-}  // extern "C"
+}  // namespace ldpc

@@ -36,7 +36,10 @@ EXPORTS = ("ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query",
            "ldpc_count_errors",
            # include/ldpc_learn.h
            "ldpc_learn_classes", "ldpc_learn_workspace_size", "ldpc_learn_forward",
-           "ldpc_learn_backward")
+           "ldpc_learn_backward",
+           # include/ldpc_multi.h
+           "ldpc_multi_workspace_size", "ldpc_decode_multi", "ldpc_autotune")
+LAYOUT_NAME = {v: k for k, v in LAYOUT.items()}
 ENC_KIND = {0: "none", 1: "staircase", 2: "dense"}
 
 
@@ -64,6 +67,13 @@ class CodeInfo(ctypes.Structure):
                 ("lds_bytes_per_cu", ctypes.c_int32), ("reg_slots", ctypes.c_int32),
                 ("reg_rows_per_thread", ctypes.c_int32), ("reg_zpack", ctypes.c_int32),
                 ("pk_slots", ctypes.c_int32), ("pk_rows_per_thread", ctypes.c_int32)]
+
+
+class Job(ctypes.Structure):
+    """ldpc_job of include/ldpc_multi.h."""
+    _fields_ = [("code", ctypes.c_void_p), ("n_frames", ctypes.c_int32), ("llr_in", ctypes.c_void_p),
+                ("params", DecodeParams), ("hard_out", ctypes.c_void_p), ("llr_out", ctypes.c_void_p),
+                ("iters_out", ctypes.c_void_p), ("syndrome_ok", ctypes.c_void_p)]
 
 
 _lib = None
@@ -95,11 +105,16 @@ def lib():
         L.ldpc_learn_workspace_size.argtypes = [vp, i32, i32, i32, ctypes.POINTER(sz)]
         L.ldpc_learn_forward.argtypes = [vp, i32, vp, vp, i32, vp, i32, vp, sz, vp, vp, vp]
         L.ldpc_learn_backward.argtypes = [vp, i32, vp, i32, vp, i32, vp, sz, vp, vp]
+        L.ldpc_multi_workspace_size.argtypes = [ctypes.POINTER(Job), i32, ctypes.POINTER(sz)]
+        L.ldpc_decode_multi.argtypes = [ctypes.POINTER(Job), i32, vp, sz, vp]
+        L.ldpc_autotune.argtypes = [vp, i32, ctypes.POINTER(DecodeParams), ctypes.POINTER(i32),
+                                    ctypes.POINTER(ctypes.c_float), ctypes.POINTER(i32)]
         for f in ("ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query",
                   "ldpc_decode_workspace_size", "ldpc_decode_batch", "ldpc_encoder_info",
                   "ldpc_encode_batch", "ldpc_random_bits", "ldpc_channel_awgn", "ldpc_count_errors",
                   "ldpc_learn_classes", "ldpc_learn_workspace_size", "ldpc_learn_forward",
-                  "ldpc_learn_backward"):
+                  "ldpc_learn_backward", "ldpc_multi_workspace_size", "ldpc_decode_multi",
+                  "ldpc_autotune"):
             getattr(L, f).restype = ctypes.c_int
         L.ldpc_last_error.restype = ctypes.c_char_p
         L.ldpc_version.restype = ctypes.c_char_p
@@ -227,6 +242,14 @@ class Code:
                                        _ptr(hard), _ptr(llr_out), _ptr(iters), _ptr(ok),
                                        _ptr(workspace), ws_bytes, ctypes.c_void_p(s.cuda_stream)))
 
+    def autotune(self, n_frames: int, params: DecodeParams) -> dict:
+        """Time every layout that can run these parameters and make AUTO use
+        the fastest from now on (ldpc_autotune)."""
+        lay, ms, tried = ctypes.c_int32(), ctypes.c_float(), ctypes.c_int32()
+        _check(lib().ldpc_autotune(self._h, int(n_frames), ctypes.byref(params), ctypes.byref(lay),
+                                   ctypes.byref(ms), ctypes.byref(tried)))
+        return {"layout": LAYOUT_NAME[int(lay.value)], "ms": float(ms.value), "tried": int(tried.value)}
+
     def alloc_outputs(self, n_frames: int, device, with_llr: bool = True) -> dict:
         return {
             "hard": torch.empty((n_frames, self.N), dtype=torch.uint8, device=device),
@@ -267,6 +290,37 @@ class Code:
 
 def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class MultiBatch:
+    """Several (code, llr, params) jobs decoded together by ldpc_decode_multi
+    (include/ldpc_multi.h).  Outputs and the shared workspace are allocated
+    once here; ``run()`` only enqueues, so it can be captured into a graph
+    (after one eager ``run()``, which creates the library's stream pool)."""
+
+    def __init__(self, items, with_llr: bool = False):
+        self.items = list(items)  # (Code, llr device tensor, DecodeParams); kept alive here
+        n = len(self.items)
+        self._jobs = (Job * max(n, 1))()
+        self.outputs = []
+        for k, (code, llr, p) in enumerate(self.items):
+            F = int(llr.shape[0])
+            out = code.alloc_outputs(F, llr.device, with_llr)
+            self.outputs.append(out)
+            self._jobs[k] = Job(code._h.value, F, llr.data_ptr(), p, out["hard"].data_ptr(),
+                                None if out["llr"] is None else out["llr"].data_ptr(),
+                                out["iters"].data_ptr(), out["ok"].data_ptr())
+        b = ctypes.c_size_t()
+        _check(lib().ldpc_multi_workspace_size(self._jobs, n, ctypes.byref(b)))
+        self.workspace_bytes = int(b.value)
+        dev = self.items[0][1].device if n else "cuda"
+        self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=dev) \
+            if self.workspace_bytes else None
+
+    def run(self, stream=None) -> None:
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().ldpc_decode_multi(self._jobs, len(self.items), _ptr(self.workspace),
+                                       self.workspace_bytes, ctypes.c_void_p(s.cuda_stream)))
 
 
 def random_bits(n_frames: int, n_bits: int, key=(0x5EED, 0), stream_id: int = 0,

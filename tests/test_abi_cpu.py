@@ -45,8 +45,10 @@ def test_struct_layouts_match_header(L, tmp_path):
     C compiler's sizes and field offsets."""
     import subprocess
     fields = {"ldpc_decode_params": [f for f, _ in L.DecodeParams._fields_],
-              "ldpc_code_info": [f for f, _ in L.CodeInfo._fields_]}
-    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ldpc.h"', 'int main(void) {']
+              "ldpc_code_info": [f for f, _ in L.CodeInfo._fields_],
+              "ldpc_job": [f for f, _ in L.Job._fields_]}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ldpc.h"', '#include "ldpc_multi.h"',
+             'int main(void) {']
     for st, fs in fields.items():
         lines.append(f'printf("{st} %zu\\n", sizeof({st}));')
         for f in fs:
@@ -58,7 +60,7 @@ def test_struct_layouts_match_header(L, tmp_path):
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
     out = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
                                                        check=True).stdout.splitlines())
-    for st, cls in (("ldpc_decode_params", L.DecodeParams), ("ldpc_code_info", L.CodeInfo)):
+    for st, cls in (("ldpc_decode_params", L.DecodeParams), ("ldpc_code_info", L.CodeInfo), ("ldpc_job", L.Job)):
         assert int(out[st]) == ctypes.sizeof(cls), st
         for f in fields[st]:
             assert int(out[f"{st}.{f}"]) == getattr(cls, f).offset, f"{st}.{f}"
@@ -241,3 +243,84 @@ def test_encoder_description(L, name):
     rank = _gf2_rank(H)
     assert K == code.N - rank
     assert _gf2_rank(H[:, pos[K:]]) == rank
+
+
+# ---------------------------------------------------------------------------
+# mixed batches (include/ldpc_multi.h), host side
+def _host_code(L, code):
+    st, h = _create(L, code.M, code.N, code.row_ptr, code.col_idx)
+    assert st == L.LDPC_OK
+    return h
+
+
+def _job(L, h, F, p, fake=0x100000):
+    return L.Job(h.value, F, fake, p, fake, None, fake, fake)
+
+
+def test_multi_workspace_is_the_concatenation(L):
+    """ldpc_multi_workspace_size = the jobs' ldpc_decode_workspace_size,
+    each started on a 256-byte boundary, in job order."""
+    codes = [W.code_c0_peg1008(), W.code_ira16200(), W.random_small_code(40, 90, (3, 9), seed=31)]
+    hs = [_host_code(L, c) for c in codes]
+    plist = [L.make_params(msg="int8", layout="hbm"), L.make_params(msg="fp32", max_iter=20),
+             L.make_params(msg="fp32", sched="two_scan", layout="hbm"),
+             L.make_params(msg="int8", sched="two_scan", max_iter=7, layout="frames")]
+    sel = [(0, 0, 333), (1, 1, 65), (2, 2, 7), (1, 3, 129), (0, 1, 0)]
+    jobs = (L.Job * len(sel))()
+    want = 0
+    for k, (ci, pi, F) in enumerate(sel):
+        b = ctypes.c_size_t()
+        assert L.lib().ldpc_decode_workspace_size(hs[ci], F, ctypes.byref(plist[pi]), ctypes.byref(b)) == 0
+        want = (want + 255) // 256 * 256 + b.value
+        jobs[k] = _job(L, hs[ci], F, plist[pi])
+    got = ctypes.c_size_t()
+    assert L.lib().ldpc_multi_workspace_size(jobs, len(sel), ctypes.byref(got)) == L.LDPC_OK
+    assert got.value == want and want > 0
+    for h in hs:
+        L.lib().ldpc_code_destroy(h)
+
+
+def test_multi_argument_errors(L):
+    code = W.code_c0_peg1008()
+    h = _host_code(L, code)
+    p = L.make_params(msg="int8")
+    lib = L.lib()
+    sz = ctypes.c_size_t()
+    jobs = (L.Job * 2)(_job(L, h, 10, p), _job(L, h, 20, p))
+    assert lib.ldpc_multi_workspace_size(jobs, -1, ctypes.byref(sz)) == L.LDPC_EINVAL
+    assert lib.ldpc_multi_workspace_size(None, 2, ctypes.byref(sz)) == L.LDPC_EINVAL
+    assert lib.ldpc_multi_workspace_size(jobs, 0, ctypes.byref(sz)) == L.LDPC_OK and sz.value == 0
+    # a missing code names its job
+    jobs[1].code = None
+    assert lib.ldpc_multi_workspace_size(jobs, 2, ctypes.byref(sz)) == L.LDPC_EINVAL
+    assert lib.ldpc_last_error().startswith(b"job 1:")
+    jobs[1].code = h.value
+    # invalid parameters of one job reject the whole call
+    jobs[1].params.alpha = 1.5
+    assert lib.ldpc_decode_multi(jobs, 2, None, 0, None) == L.LDPC_EINVAL
+    assert b"job 1:" in lib.ldpc_last_error() and b"alpha" in lib.ldpc_last_error()
+    jobs[1].params.alpha = 0.8
+    # the synchronising input check is not allowed inside a mixed call
+    jobs[0].params.flags |= L.F_CHECK_INPUT
+    assert lib.ldpc_decode_multi(jobs, 2, None, 0, None) == L.LDPC_EINVAL
+    assert b"CHECK_INPUT" in lib.ldpc_last_error()
+    jobs[0].params.flags &= ~L.F_CHECK_INPUT
+    # a missing output pointer, and host-only handles, fail before any launch
+    jobs[0].iters_out = None
+    assert lib.ldpc_decode_multi(jobs, 2, None, 0, None) == L.LDPC_EINVAL
+    assert lib.ldpc_last_error().startswith(b"job 0:")
+    jobs[0].iters_out = 0x100000
+    assert lib.ldpc_decode_multi(jobs, 2, None, 0, None) == L.LDPC_EINVAL
+    assert b"host-only" in lib.ldpc_last_error()
+    # workspace checks of the whole call
+    jobs2 = (L.Job * 1)(_job(L, h, 10, L.make_params(msg="int8", layout="hbm")))
+    assert lib.ldpc_multi_workspace_size(jobs2, 1, ctypes.byref(sz)) == 0 and sz.value > 0
+    assert lib.ldpc_decode_multi(jobs2, 1, None, 0, None) == L.LDPC_EINVAL
+    assert lib.ldpc_decode_multi(jobs2, 1, ctypes.c_void_p(0x100000), sz.value - 1, None) == L.LDPC_EINVAL
+    assert lib.ldpc_decode_multi(jobs2, 1, ctypes.c_void_p(0x100010), sz.value, None) == L.LDPC_EINVAL
+    assert b"aligned" in lib.ldpc_last_error()
+    # autotuning needs a device handle and no per-iteration weights
+    lay = ctypes.c_int32()
+    assert lib.ldpc_autotune(h, 64, ctypes.byref(p), ctypes.byref(lay), None, None) == L.LDPC_EINVAL
+    assert lib.ldpc_autotune(h, 0, ctypes.byref(p), ctypes.byref(lay), None, None) == L.LDPC_EINVAL
+    lib.ldpc_code_destroy(h)
