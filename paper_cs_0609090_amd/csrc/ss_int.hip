@@ -78,7 +78,12 @@ __device__ void syndrome_pass(int tid, int T, int Mp, int D, const uint32_t *__r
     }
 }
 
-template <int DMAX, int MSG, bool MSG_LDS>
+// FUSED (early stop, hard decisions only): the syndrome of the hard
+// decisions of Z^(k-1) is formed from the Z_old gathers of iteration k; a
+// zero syndrome stops the frame with k-1 iterations, its decisions read from
+// Z_old (the saturated copy keeps the sign and zero of Z^(k-1)).  Otherwise a
+// separate check pass follows each iteration.
+template <int DMAX, int MSG, bool MSG_LDS, bool FUSED>
 __global__ void __launch_bounds__(launch_bound_for(DMAX)) ss_int_kernel(DecodeArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
     const int tid = threadIdx.x;
@@ -89,7 +94,7 @@ __global__ void __launch_bounds__(launch_bound_for(DMAX)) ss_int_kernel(DecodeAr
     const uint32_t *__restrict__ ell = a.c.ell;
     int8_t *zold = reinterpret_cast<int8_t *>(lds + a.off_zold);
     uint32_t *zacc = reinterpret_cast<uint32_t *>(lds + a.off_zacc);
-    int *flag = reinterpret_cast<int *>(lds + a.off_aux);
+    int *flag = reinterpret_cast<int *>(lds + a.off_aux);  // [0]: separate check, [1], [2]: fused
     uint8_t *st = MSG_LDS ? (lds + a.off_msg) : (a.ws + (size_t)f * a.ws_stride + a.ws_off_msg);
     const int8_t *__restrict__ z0 = static_cast<const int8_t *>(a.llr_in) + (size_t)f * N;
     const int P = a.zpack;
@@ -114,7 +119,11 @@ __global__ void __launch_bounds__(launch_bound_for(DMAX)) ss_int_kernel(DecodeAr
         uint32_t *s32 = reinterpret_cast<uint32_t *>(st);
         for (int i = tid; i < words; i += T) s32[i] = 0u;
     }
-    if (tid == 0) *flag = 0;
+    if (tid == 0) {
+        flag[0] = 0;
+        flag[1] = 0;
+        flag[2] = 0;
+    }
     __syncthreads();
 
     int8_t *L8 = reinterpret_cast<int8_t *>(st);
@@ -122,15 +131,21 @@ __global__ void __launch_bounds__(launch_bound_for(DMAX)) ss_int_kernel(DecodeAr
     uint16_t *cst = reinterpret_cast<uint16_t *>(st + (size_t)D * MpW * 8);
 
     int iters = 0;
-    bool converged = false;
+    bool converged = false;  // the decision of the last completed iteration is a codeword
+    bool conv_prev = false;  // FUSED: that of the iteration before the last one is
     for (int k = 1; k <= a.max_iter; ++k) {
+        // FUSED: the sign bit collects odd hard-decision parities of Z^(k-1)
+        // rows; flag[1 + (k & 1)] is set by this iteration and read after its
+        // first barrier, the other one (read last iteration) is cleared here
+        int zodd = 0;
+        if (FUSED && tid == 0) flag[1 + ((k + 1) & 1)] = 0;
         // ---- check pass (Eq. 3), one row per thread
         for (int m = tid; m < Mp; m += T) {
             uint32_t nid[DMAX];
             int tt[DMAX];
             int lo[DMAX];
             uint32_t min1 = 0xFFFFFFFFu, min2 = 0xFFFFFFFFu;
-            int par = 0;
+            int par = 0, hpar = 0;
             int Ao = 0, Bo = 0, Io = 0;
             if (MSG == MSG_1BIT) {
                 const uint32_t s = cst[m];
@@ -152,7 +167,9 @@ __global__ void __launch_bounds__(launch_bound_for(DMAX)) ss_int_kernel(DecodeAr
                         l = ((wbits >> (m & 63)) & 1ull) ? -fv : fv;
                     }
                     lo[j] = l;
-                    const int t = clamp_i((int)zold[n] - l, -kQmax, kQmax);
+                    const int zv = (int)zold[n];
+                    if (FUSED) hpar ^= zv - 1;  // sign bit: Z_old <= 0
+                    const int t = clamp_i(zv - l, -kQmax, kQmax);
                     tt[j] = t;
                     par ^= t;
                     const uint32_t key = ((uint32_t)(t < 0 ? -t : t) << 6) | (uint32_t)j;
@@ -160,6 +177,7 @@ __global__ void __launch_bounds__(launch_bound_for(DMAX)) ss_int_kernel(DecodeAr
                     min1 = min(min1, key);
                 }
             }
+            if (FUSED) zodd |= hpar;
             const int idx = (int)(min1 & 63u);
             const int A = norm_q((int)(min1 >> 6), a.a8, a.b_int);
             const int B = norm_q((int)(min2 >> 6), a.a8, a.b_int);
@@ -185,7 +203,12 @@ __global__ void __launch_bounds__(launch_bound_for(DMAX)) ss_int_kernel(DecodeAr
                 }
             }
         }
+        if (FUSED && k >= 2 && zodd < 0) flag[1 + (k & 1)] = 1;
         __syncthreads();
+        if (FUSED && k >= 2 && flag[1 + (k & 1)] == 0) {  // Z^(k-1) is a codeword
+            conv_prev = true;
+            break;
+        }
         // ---- variable pass: refresh the saturated gather copy
         if (tid == 0) *flag = 0;
         for (int w = tid; w < nwords; w += T) {
@@ -197,7 +220,7 @@ __global__ void __launch_bounds__(launch_bound_for(DMAX)) ss_int_kernel(DecodeAr
         }
         __syncthreads();
         iters = k;
-        if (a.early_stop) {
+        if (!FUSED && a.early_stop) {
             syndrome_pass(tid, T, Mp, D, ell, zold, flag);
             __syncthreads();
             if (*flag == 0) {
@@ -208,7 +231,7 @@ __global__ void __launch_bounds__(launch_bound_for(DMAX)) ss_int_kernel(DecodeAr
     }
 
     int ok = 1;
-    if (!converged) {
+    if (!converged && !conv_prev) {
         __syncthreads();
         if (tid == 0) *flag = 0;
         __syncthreads();
@@ -217,7 +240,9 @@ __global__ void __launch_bounds__(launch_bound_for(DMAX)) ss_int_kernel(DecodeAr
         ok = (*flag == 0);
     }
     // ---- outputs
-    for (int n = tid; n < N; n += T) {
+    if (FUSED && conv_prev) {  // decisions of Z^(iters) from its saturated copy
+        for (int n = tid; n < N; n += T) a.hard_out[(size_t)f * N + n] = zold[n] <= 0 ? 1 : 0;
+    } else for (int n = tid; n < N; n += T) {
         uint32_t w, sh;
         zloc((uint32_t)n, P, w, sh);
         const int z = zfield(zacc[w], sh, zp);
@@ -230,9 +255,9 @@ __global__ void __launch_bounds__(launch_bound_for(DMAX)) ss_int_kernel(DecodeAr
     }
 }
 
-template <int DMAX, int MSG, bool ML>
+template <int DMAX, int MSG, bool ML, bool FUSED>
 hipError_t launch_one(const DecodeArgs &a, const LaunchCfg &c, hipStream_t s) {
-    auto kern = ss_int_kernel<DMAX, MSG, ML>;
+    auto kern = ss_int_kernel<DMAX, MSG, ML, FUSED>;
     if (c.lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds);
@@ -244,7 +269,10 @@ hipError_t launch_one(const DecodeArgs &a, const LaunchCfg &c, hipStream_t s) {
 
 template <int DMAX, int MSG>
 hipError_t launch_msg(const DecodeArgs &a, const LaunchCfg &c, hipStream_t s) {
-    return c.msg_lds ? launch_one<DMAX, MSG, true>(a, c, s) : launch_one<DMAX, MSG, false>(a, c, s);
+    // the fused check needs at least one iteration and no posterior output
+    if (a.early_stop && a.llr_out == nullptr && a.max_iter >= 1)
+        return c.msg_lds ? launch_one<DMAX, MSG, true, true>(a, c, s) : launch_one<DMAX, MSG, false, true>(a, c, s);
+    return c.msg_lds ? launch_one<DMAX, MSG, true, false>(a, c, s) : launch_one<DMAX, MSG, false, false>(a, c, s);
 }
 
 template <int DMAX>

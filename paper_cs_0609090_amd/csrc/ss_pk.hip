@@ -30,6 +30,15 @@
 // the dummy slot (Z_old at its maximum, never the row minimum) and add into a
 // private word per lane.  Z_old is stored as Z + 64 (bytes), messages as
 // L + 64.
+//
+// Early stop (FUSED, for callers that want hard decisions only): the gather
+// of iteration k already reads every Z^(k-1) byte, so the syndrome of the
+// hard decisions of Z^(k-1) is formed there (one packed subtract and a share
+// of a three-input XOR per slot pair) instead of in a separate pass over the
+// rows.  When it is zero after iteration k, the frame stops with k-1
+// iterations and its decisions are read from Z_old, which saturation leaves
+// with the sign (and zero) of Z^(k-1).  The exact posteriors of Z^(k-1) are
+// gone by then, so a caller asking for them gets the separate check instead.
 #include "ldpc_internal.h"
 
 namespace ldpc {
@@ -63,7 +72,7 @@ __device__ __forceinline__ uint32_t pair_of(uint32_t w, int s) {
     return __builtin_amdgcn_perm(w, w, s == 0 ? 0x0c010c00u : 0x0c030c02u);
 }
 
-template <int D, int R, bool ONEBIT>
+template <int D, int R, bool ONEBIT, bool FUSED>
 __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
     static_assert(!ONEBIT || D <= 8, "1-bit state keeps 8 slots per 16-bit half");
     static_assert(R % 2 == 0, "rows are processed in pairs");
@@ -77,7 +86,7 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
     const uint32_t dummy = (uint32_t)a.c.dummy;
     uint8_t *zold = lds;  // Z_old + 64 at LDS offset 0 (the planner places it there)
     uint32_t *zacc = reinterpret_cast<uint32_t *>(lds + a.off_zacc);
-    int *flag = reinterpret_cast<int *>(lds + a.off_aux);
+    int *flag = reinterpret_cast<int *>(lds + a.off_aux);  // [0]: separate check, [1], [2]: fused
     const int8_t *__restrict__ z0 = static_cast<const int8_t *>(a.llr_in) + (size_t)f * N;
     const __amdgpu_buffer_rsrc_t rec = __builtin_amdgcn_make_buffer_rsrc(
         (void *)a.c.pk_idx, (short)0, RP * D * kT * 16, kRsrcWord3);
@@ -103,7 +112,11 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
         }
         zacc[w] = v;
     }
-    if (tid == 0) *flag = 0;
+    if (tid == 0) {
+        flag[0] = 0;
+        flag[1] = 0;
+        flag[2] = 0;
+    }
 
     // Message state of each row pair.
     //   int8:  Lw[p][i], bytes 2s / 2s+1: slot 2i+s of rows a / b, as L + 64.
@@ -125,14 +138,20 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
     const uint32_t a8x2 = (uint32_t)a.a8 * 0x00010001u;
     const uint32_t bx2 = (uint32_t)a.b_int * 0x00010001u;
     int iters = 0;
-    bool converged = false;
+    bool converged = false;  // the decision of the last completed iteration is a codeword
+    bool conv_prev = false;  // FUSED: that of the iteration before the last one is
     for (int it = 1; it <= a.max_iter; ++it) {
         uint32_t it0 = 0;  // opaque zero: keeps the index loads inside the iteration loop
         asm volatile("" : "+s"(it0));
+        // FUSED: bits 15 / 31 collect odd hard-decision parities of Z^(it-1)
+        // rows; flag[1 + (it & 1)] is set by this iteration and read after its
+        // first barrier, the other one (read last iteration) is cleared here
+        uint32_t zodd = 0;
+        if (FUSED && tid == 0) flag[1 + ((it + 1) & 1)] = 0;
 #pragma unroll
         for (int p = 0; p < RP; ++p) {
             __builtin_amdgcn_sched_barrier(0);
-            uint32_t acc_a[D], acc_b[D], t2[D], lo2[D], mg2[D];
+            uint32_t acc_a[D], acc_b[D], t2[D], lo2[D], mg2[D], h2[D];
             u16x2 min1 = {0xFFFF, 0xFFFF}, min2 = {0xFFFF, 0xFFFF};
             uint32_t Sp = 0, Aold = 0, Bold = 0;
             if (ONEBIT) {
@@ -149,6 +168,9 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
                 acc_b[j] = r4[3];
                 const u16x2 zv = {(unsigned short)lds_byte(na), (unsigned short)lds_byte(nb)};
                 const uint32_t z2 = bits(zv);
+                // FUSED: sign bit of each half set iff Z_old <= 0 (stored Z + 64 <= 64);
+                // a packed 16-bit subtract, so no borrow crosses the halves
+                if (FUSED) h2[j] = bits(as_i(z2) - (i16x2){65, 65});
                 uint32_t l2;
                 if (ONEBIT) {
                     // L_old = s * (slot held the minimum ? B : A), rebuilt per
@@ -176,6 +198,13 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
 #pragma unroll
             for (int j = 1; j + 1 < D; j += 2) par = __builtin_amdgcn_bitop3_b32(par, t2[j], t2[j + 1], 0x96);
             if (D % 2 == 0) par ^= t2[D - 1];
+            if (FUSED) {
+                uint32_t hp = h2[0];
+#pragma unroll
+                for (int j = 1; j + 1 < D; j += 2) hp = __builtin_amdgcn_bitop3_b32(hp, h2[j], h2[j + 1], 0x96);
+                if (D % 2 == 0) hp ^= h2[D - 1];
+                zodd |= hp;
+            }
             // per row pair: normalised magnitudes of the saturated minima, signed
             // once by the row parity (each message is then flipped only by its
             // own extrinsic's sign)
@@ -233,7 +262,12 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
                 }
             }
         }
+        if (FUSED && it >= 2 && (zodd & 0x80008000u)) flag[1 + (it & 1)] = 1;
         __syncthreads();
+        if (FUSED && it >= 2 && flag[1 + (it & 1)] == 0) {  // Z^(it-1) is a codeword
+            conv_prev = true;
+            break;
+        }
         if (tid == 0) *flag = 0;
         if (P == 3) {
             // four accumulator words (twelve slots) per step: one 16-byte LDS
@@ -280,7 +314,7 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
         }
         __syncthreads();
         iters = it;
-        if (a.early_stop) {
+        if (!FUSED && a.early_stop) {
             for (int p = 0; p < RP; ++p) {
                 int pa = 0, pb = 0;
                 for (int j = 0; j < D; ++j) {
@@ -299,7 +333,7 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
         }
     }
     int ok = 1;
-    if (!converged) {
+    if (!converged && !conv_prev) {
         __syncthreads();
         if (tid == 0) *flag = 0;
         __syncthreads();
@@ -316,7 +350,9 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
         __syncthreads();
         ok = (*flag == 0);
     }
-    for (int n = tid; n < N; n += kT) {
+    if (FUSED && conv_prev) {  // decisions of Z^(iters) from its saturated copy
+        for (int n = tid; n < N; n += kT) a.hard_out[(size_t)f * N + n] = zold[slot_of[n]] <= 64 ? 1 : 0;
+    } else for (int n = tid; n < N; n += kT) {
         const uint32_t sl = slot_of[n];
         const uint32_t w = (P == 1) ? sl : (P == 2 ? sl >> 1 : sl / 3u);
         const int i = (int)(sl - w * (uint32_t)P);
@@ -331,9 +367,9 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
     }
 }
 
-template <int D, int R, bool ONEBIT>
+template <int D, int R, bool ONEBIT, bool FUSED>
 hipError_t launch_one(const DecodeArgs &a, size_t lds, hipStream_t s) {
-    auto kern = ss_pk_kernel<D, R, ONEBIT>;
+    auto kern = ss_pk_kernel<D, R, ONEBIT, FUSED>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -370,8 +406,14 @@ void pk_shapes(int *out, int cap, int *count) {
 }
 
 hipError_t launch_ss_pk(const DecodeArgs &a, int D, int R, bool onebit, size_t lds, hipStream_t s) {
-#define X(d, r) \
-    if (D == d && R == r) return onebit ? launch_one<d, r, true>(a, lds, s) : launch_one<d, r, false>(a, lds, s);
+    // the fused check needs at least one iteration and no posterior output
+    const bool fused = a.early_stop && a.llr_out == nullptr && a.max_iter >= 1;
+#define X(d, r)                                                                                         \
+    if (D == d && R == r) {                                                                             \
+        if (fused)                                                                                      \
+            return onebit ? launch_one<d, r, true, true>(a, lds, s) : launch_one<d, r, false, true>(a, lds, s); \
+        return onebit ? launch_one<d, r, true, false>(a, lds, s) : launch_one<d, r, false, false>(a, lds, s);   \
+    }
     LDPC_PK_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;

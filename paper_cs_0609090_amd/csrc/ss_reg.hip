@@ -14,6 +14,10 @@
 //   min1/argmin/min2 keyed as |t| << 5 | j.  Padding slots point at a
 //   variable whose accumulator word holds nothing else, so their updates
 //   need no test.
+// Early stop with hard decisions only (FUSED) forms the syndrome of the
+// hard decisions of Z^(k-1) from the Z_old gathers of iteration k, as in
+// ss_pk.hip; with posterior output a separate check pass follows each
+// iteration.
 #include "ldpc_internal.h"
 
 namespace ldpc {
@@ -79,7 +83,7 @@ __device__ __forceinline__ uint32_t ld_idx(__amdgpu_buffer_rsrc_t r, uint32_t vo
     return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
 }
 
-template <int D, int R, int P, int MSG>
+template <int D, int R, int P, int MSG, bool FUSED>
 __global__ void __launch_bounds__(kT) ss_reg_kernel(DecodeArgs a) {
     static_assert(D >= 2 && D <= 32, "slots per row");
     static_assert(MSG == MSG_INT8 || D + 15 <= 32, "1-bit state must fit one register");
@@ -93,7 +97,7 @@ __global__ void __launch_bounds__(kT) ss_reg_kernel(DecodeArgs a) {
     int8_t *zold = reinterpret_cast<int8_t *>(lds + a.off_zold);  // Z_old saturated to +-62
     uint8_t *zacc_b = lds + a.off_zacc;
     uint32_t *zacc = reinterpret_cast<uint32_t *>(zacc_b);
-    int *flag = reinterpret_cast<int *>(lds + a.off_aux);
+    int *flag = reinterpret_cast<int *>(lds + a.off_aux);  // [0]: separate check, [1], [2]: fused
     const int8_t *__restrict__ z0 = static_cast<const int8_t *>(a.llr_in) + (size_t)f * N;
     const __amdgpu_buffer_rsrc_t ellr =
         __builtin_amdgcn_make_buffer_rsrc((void *)a.c.ell_reg, (short)0, D * Mr * 4, kRsrcWord3);
@@ -112,7 +116,11 @@ __global__ void __launch_bounds__(kT) ss_reg_kernel(DecodeArgs a) {
     }
     for (int n = tid; n <= (int)dummy; n += kT)
         zold[n] = (int8_t)(n < N ? min(max((int)z0[n], -kQmax), kQmax) : (n == (int)dummy ? kZoldMax : 0));
-    if (tid == 0) *flag = 0;
+    if (tid == 0) {
+        flag[0] = 0;
+        flag[1] = 0;
+        flag[2] = 0;
+    }
 
     uint32_t Lw[R][W];  // INT8: int8 messages; 1BIT: Lw[k][0] = state word
 #pragma unroll
@@ -125,8 +133,14 @@ __global__ void __launch_bounds__(kT) ss_reg_kernel(DecodeArgs a) {
     const uint32_t a8 = (uint32_t)a.a8;
     const int bq = a.b_int;
     int iters = 0;
-    bool converged = false;
+    bool converged = false;  // the decision of the last completed iteration is a codeword
+    bool conv_prev = false;  // FUSED: that of the iteration before the last one is
     for (int it = 1; it <= a.max_iter; ++it) {
+        // FUSED: the sign bit collects odd hard-decision parities of Z^(it-1)
+        // rows; flag[1 + (it & 1)] is set by this iteration and read after its
+        // first barrier, the other one (read last iteration) is cleared here
+        int zodd = 0;
+        if (FUSED && tid == 0) flag[1 + ((it + 1) & 1)] = 0;
         // indices of the next row are loaded one row ahead; the scheduling
         // barriers keep the unrolled rows from hoisting every load to the top
         // The index stream is the same every iteration; an opaque zero added to
@@ -168,15 +182,21 @@ __global__ void __launch_bounds__(kT) ss_reg_kernel(DecodeArgs a) {
                 }
             }
             uint32_t min1 = 0xFFFFFFFFu, min2 = 0xFFFFFFFFu;
-            int par = 0;
+            int par = 0, hpar = 0;
 #pragma unroll
             for (int j = 0; j < D; ++j) {
-                const int tr = (int)zold[n[j]] - lo[j];  // Z_old - L_old
+                const int zv = (int)zold[n[j]];
+                const int tr = zv - lo[j];  // Z_old - L_old
                 traw[j] = tr;
                 par ^= tr;
+                if (FUSED) hpar ^= zv - 1;  // sign bit: Z_old <= 0
                 const uint32_t key = ((uint32_t)(tr < 0 ? -tr : tr) << 5) | (uint32_t)j;
                 min2 = min(min2, max(min1, key));
                 min1 = min(min1, key);
+            }
+            if (FUSED) {  // opaque: otherwise the XOR chain is deferred and every gathered value stays live
+                asm volatile("" : "+v"(hpar));
+                zodd |= hpar;
             }
             const int idx = (int)(min1 & 31u);
             int A = norm_q(min1 >> 5, a8, bq);
@@ -215,7 +235,12 @@ __global__ void __launch_bounds__(kT) ss_reg_kernel(DecodeArgs a) {
             for (int i = 0; i < W; ++i) asm volatile("" : "+v"(Lw[k][i]));
             __builtin_amdgcn_sched_barrier(0);
         }
+        if (FUSED && it >= 2 && zodd < 0) flag[1 + (it & 1)] = 1;
         __syncthreads();
+        if (FUSED && it >= 2 && flag[1 + (it & 1)] == 0) {  // Z^(it-1) is a codeword
+            conv_prev = true;
+            break;
+        }
         if (tid == 0) *flag = 0;
         for (int w = tid; w < nwords; w += kT) {
             const uint32_t v = zacc[w];
@@ -227,7 +252,7 @@ __global__ void __launch_bounds__(kT) ss_reg_kernel(DecodeArgs a) {
         }
         __syncthreads();
         iters = it;
-        if (a.early_stop) {
+        if (!FUSED && a.early_stop) {
             for (int k = 0; k < R; ++k) {
                 const uint32_t voff = (uint32_t)(k * kT + tid) * 4u;
                 int p = 0;
@@ -242,7 +267,7 @@ __global__ void __launch_bounds__(kT) ss_reg_kernel(DecodeArgs a) {
         }
     }
     int ok = 1;
-    if (!converged) {
+    if (!converged && !conv_prev) {
         __syncthreads();
         if (tid == 0) *flag = 0;
         __syncthreads();
@@ -255,7 +280,9 @@ __global__ void __launch_bounds__(kT) ss_reg_kernel(DecodeArgs a) {
         __syncthreads();
         ok = (*flag == 0);
     }
-    for (int n = tid; n < N; n += kT) {
+    if (FUSED && conv_prev) {  // decisions of Z^(iters) from its saturated copy
+        for (int n = tid; n < N; n += kT) a.hard_out[(size_t)f * N + n] = zold[n] <= 0 ? 1 : 0;
+    } else for (int n = tid; n < N; n += kT) {
         uint32_t addr, sh;
         ZP<P>::loc((uint32_t)n, addr, sh);
         const uint32_t v = *reinterpret_cast<const uint32_t *>(zacc_b + addr);
@@ -269,9 +296,9 @@ __global__ void __launch_bounds__(kT) ss_reg_kernel(DecodeArgs a) {
     }
 }
 
-template <int D, int R, int P, int MSG>
+template <int D, int R, int P, int MSG, bool FUSED>
 hipError_t launch_one(const DecodeArgs &a, size_t lds, hipStream_t s) {
-    auto kern = ss_reg_kernel<D, R, P, MSG>;
+    auto kern = ss_reg_kernel<D, R, P, MSG, FUSED>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -279,6 +306,13 @@ hipError_t launch_one(const DecodeArgs &a, size_t lds, hipStream_t s) {
     }
     hipLaunchKernelGGL(kern, dim3((unsigned)a.n_frames), dim3(kT), lds, s, a);
     return hipGetLastError();
+}
+
+template <int D, int R, int P, int MSG>
+hipError_t launch_es(const DecodeArgs &a, size_t lds, hipStream_t s) {
+    // the fused check needs at least one iteration and no posterior output
+    if (a.early_stop && a.llr_out == nullptr && a.max_iter >= 1) return launch_one<D, R, P, MSG, true>(a, lds, s);
+    return launch_one<D, R, P, MSG, false>(a, lds, s);
 }
 
 }  // namespace
@@ -326,8 +360,8 @@ void reg_shapes(int *out, int cap, int *count) {
 hipError_t launch_ss_reg(const DecodeArgs &a, int msg, int D, int R, int P, size_t lds, hipStream_t s) {
 #define X(d, r, p)                                                                         \
     if (D == d && R == r && P == p) {                                                      \
-        if (msg == MSG_INT8) return launch_one<d, r, p, MSG_INT8>(a, lds, s);              \
-        if (d + 15 <= 32) return launch_one<d, r, p, (d + 15 <= 32 ? MSG_1BIT : MSG_INT8)>(a, lds, s); \
+        if (msg == MSG_INT8) return launch_es<d, r, p, MSG_INT8>(a, lds, s);               \
+        if (d + 15 <= 32) return launch_es<d, r, p, (d + 15 <= 32 ? MSG_1BIT : MSG_INT8)>(a, lds, s); \
         return hipErrorInvalidValue;                                                       \
     }
     LDPC_REG_SHAPES(X)

@@ -309,3 +309,66 @@ def test_workspace_too_small_rejected(torch_dev, L):
         gc.decode_into(x, p, o["hard"], o["llr"], o["iters"], o["ok"], ws)
     assert ei.value.status == L.LDPC_EINVAL
     gc.close()
+
+
+# ---------------------------------------------------------------------------
+# Early stop with hard decisions only: the integer kernels fold the syndrome
+# of iteration k-1 into the gathers of iteration k.  Same decisions, iteration
+# counts and flags as the oracle and as the path that also returns posteriors.
+ES_CODES = {"peg1008": W.code_c0_peg1008, "ira16200": W.code_ira16200, "qc7493": W.code_c1_qc7493,
+            "ira64800": W.code_c2_ira64800}
+ES_CASES = [("peg1008", "int8", "auto"), ("peg1008", "1bit", "auto"), ("peg1008", "int8", "hbm"),
+            ("peg1008", "int8", "reg1"), ("peg1008", "1bit", "reg1"), ("ira16200", "int8", "reg"),
+            ("ira16200", "1bit", "reg"), ("ira16200", "int8", "reg1"), ("qc7493", "int8", "auto"),
+            ("qc7493", "1bit", "auto")]
+
+
+def _spread_inputs(code, F, seed, lo=0.5, hi=3.5):
+    eb = np.random.default_rng(seed).uniform(lo, hi, size=F)
+    return W.quantize_llr(W.awgn_llr(code.N, F, eb, code.design_rate, key=(0xE5, seed)))
+
+
+@pytest.mark.parametrize("max_iter", [1, 2, 9, 30])
+@pytest.mark.parametrize("name,msg,layout", ES_CASES)
+def test_early_stop_hard_only(torch_dev, L, orc, name, msg, layout, max_iter):
+    torch = torch_dev
+    code = ES_CODES[name]()
+    F = 96 if code.N < 10000 else 40
+    x = _spread_inputs(code, F, 11)
+    gcode = L.Code.from_parity_check(code)
+    t = torch.from_numpy(x).cuda()
+    kw = dict(max_iter=max_iter, early_stop=True, msg=msg, layout=layout)
+    fused = {k: (v.cpu().numpy() if v is not None else None)
+             for k, v in gcode.decode(t, with_llr=False, **kw).items()}
+    full = {k: v.cpu().numpy() for k, v in gcode.decode(t, with_llr=True, **kw).items()}
+    gcode.close()
+    for k in ("hard", "iters", "ok"):
+        np.testing.assert_array_equal(fused[k], full[k], err_msg=f"{k} fused vs full {name} {msg} {layout}")
+    algo = "one_bit" if msg == "1bit" else "single_scan"
+    r = orc.decode(code, x, algo=algo, arith="int", max_iter=max_iter, early_stop=True, step=0.5)
+    np.testing.assert_array_equal(fused["iters"], r["iters"])
+    np.testing.assert_array_equal(fused["ok"], r["ok"])
+    np.testing.assert_array_equal(fused["hard"], r["hard"])
+    if max_iter >= 9 and name != "qc7493":  # the spread reaches frames that stop early and frames that do not
+        assert len(set(fused["iters"].tolist())) > 2
+
+
+@pytest.mark.parametrize("msg", ["int8", "1bit"])
+def test_early_stop_hard_only_ira64800_sampled(torch_dev, L, orc, msg):
+    """The packed kernel on the N=64800 code, 128 frames, hard decisions only."""
+    torch = torch_dev
+    code = W.code_c2_ira64800()
+    F = 128
+    x = _spread_inputs(code, F, 12, lo=0.8, hi=1.6)
+    gcode = L.Code.from_parity_check(code)
+    assert gcode.info()["pk_slots"] > 0
+    g = {k: (v.cpu().numpy() if v is not None else None)
+         for k, v in gcode.decode(torch.from_numpy(x).cuda(), max_iter=50, early_stop=True, msg=msg,
+                                  layout="reg", with_llr=False).items()}
+    gcode.close()
+    sel = np.array([0, 5, 77, F - 1])
+    algo = "one_bit" if msg == "1bit" else "single_scan"
+    r = orc.decode(code, x[sel], algo=algo, arith="int", max_iter=50, early_stop=True, step=0.5)
+    np.testing.assert_array_equal(g["iters"][sel], r["iters"])
+    np.testing.assert_array_equal(g["ok"][sel], r["ok"])
+    np.testing.assert_array_equal(g["hard"][sel], r["hard"])
