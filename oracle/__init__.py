@@ -4,9 +4,11 @@ Only the test-suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  The decoder library does not use it.
 
 ``decode(code, llr, algo=..., arith=...)`` runs one of the three decoders of
-the paper (two-scan Sec. III, single-scan Sec. IV, 1-bit Sec. V) in 6-bit
-fixed point (``arith='int'``, int8 input), binary32 or binary64 and returns
-numpy arrays.
+the paper (two-scan Sec. III, single-scan Sec. IV, 1-bit Sec. V) in b-bit
+fixed point (``arith='int'``, int8 input; b = 6, or 6-8 with ``qbits`` for
+single-scan and 1-bit), binary32 or binary64 and returns numpy arrays.
+``sched`` (fixed point, single-scan and 1-bit) is a [T][2] array of
+per-iteration (alpha_k, beta_k) pairs; iteration k uses row min(k, T) - 1.
 """
 from __future__ import annotations
 
@@ -52,7 +54,8 @@ def _p(a):
 
 def decode(code, llr, algo: str = "single_scan", arith: str = "int", max_iter: int = 50,
            alpha: float = 0.8, beta: float = 0.0, early_stop: bool = True,
-           step: float = 0.5, trace: bool = False, state: bool = False) -> dict:
+           step: float = 0.5, trace: bool = False, state: bool = False, sched=None,
+           qbits: int = 6) -> dict:
     """Decode a batch [F, N].  Returns dict with ``post`` (float32 for int and
     f32, float64 for f64), ``hard`` (uint8), ``iters`` (int32), ``ok`` (uint8)
     and, with ``trace``, per-iteration ``L`` [F, max_iter, E], ``Z``
@@ -80,9 +83,18 @@ def decode(code, llr, algo: str = "single_scan", arith: str = "int", max_iter: i
     tz = np.zeros((F, T, N), dtype=real) if trace else None
     tzmn = np.zeros((F, T, E), dtype=real) if (trace and algo == "two_scan") else None
     out = {}
+    ex = sched is not None or qbits != 6
+    if ex and (arith != "int" or algo == "two_scan"):
+        raise ValueError("schedules and message widths: fixed-point single-scan and 1-bit only")
+    sch = None if sched is None else np.ascontiguousarray(sched, dtype=np.float64).reshape(-1, 2)
     common = [ctypes.c_int(M), ctypes.c_int(N), _p(rp), _p(ci), ctypes.c_int(F), _p(x),
-              ctypes.c_int(max_iter), ctypes.c_double(alpha), ctypes.c_double(beta),
-              ctypes.c_int(1 if early_stop else 0)]
+              ctypes.c_int(max_iter)]
+    if ex:
+        common += [_p(sch), ctypes.c_int(0 if sch is None else sch.shape[0])]
+    common += [ctypes.c_double(alpha), ctypes.c_double(beta)]
+    if ex:
+        common.append(ctypes.c_int(qbits))
+    common.append(ctypes.c_int(1 if early_stop else 0))
     if arith == "int":
         common.append(ctypes.c_double(step))
     tail = [_p(post), _p(hard), _p(iters), _p(ok), _p(tl), _p(tz)]
@@ -93,7 +105,7 @@ def decode(code, llr, algo: str = "single_scan", arith: str = "int", max_iter: i
         st = np.zeros((F, M, 3), dtype=np.int32) if state else None
         sg = np.zeros((F, E), dtype=np.uint8) if state else None
         tail += [_p(st), _p(sg)]
-    fn = getattr(L, f"oracle_{algo}_int" if arith == "int" else f"oracle_{algo}_{arith}")
+    fn = getattr(L, (f"oracle_{algo}_int" + ("_ex" if ex else "")) if arith == "int" else f"oracle_{algo}_{arith}")
     rc = fn(*common, *tail)
     if rc != 0:
         raise ValueError(f"oracle rejected the arguments (rc={rc})")

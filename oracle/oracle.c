@@ -26,11 +26,16 @@
  * rely on the observation it is used to test.
  *
  * Arithmetic variants
- *   _int : 6-bit fixed point (the paper's b-bit messages, Sec. V).  Inputs are
- *          int8 in [-31,31]; every variable-to-check value (two-scan Z_mn,
- *          single-scan Z_n - L_mn) is saturated to +-31; accumulators are not.
+ *   _int : b-bit fixed point (the paper's b = 6..8 bit messages, Sec. V; the
+ *          plain entry points are 6-bit, the _ex ones take b = 6, 7 or 8).
+ *          With Q = 2^(b-1) - 1 (31, 63, 127): inputs are int8 in [-Q, Q];
+ *          every variable-to-check value (two-scan Z_mn, single-scan
+ *          Z_n - L_mn) is saturated to +-Q; accumulators are not.
  *          Normalisation/offset: |L| = max(((m*a8 + 128) >> 8) - b, 0) with
  *          a8 = round(256*alpha), b = round(beta/step) (round half away).
+ *          The _ex entry points also take a schedule of one (alpha_k, beta_k)
+ *          pair per iteration k (Sec. III indexes both by the iteration):
+ *          iteration k uses row min(k, n_sched) - 1, each converted as above.
  *   _f32, _f64 : IEEE binary32 / binary64, no saturation; |L| =
  *          max(alpha*m - beta, 0) with the product rounded before the
  *          subtraction (build with -ffp-contract=off).
@@ -54,7 +59,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define ORC_QMAX 31
+#define ORC_QMAX6 31 /* Q of the 6-bit entry points */
 
 /* ------------------------------------------------------------------------ */
 /* shared helpers of the oracle itself                                       */
@@ -114,7 +119,7 @@ static int orc_syndrome_ok(int M, const int *row_ptr, const int *col_idx, const 
 /* 6-bit fixed point                                                         */
 /* ------------------------------------------------------------------------ */
 
-static int sat_q(int v) { return v > ORC_QMAX ? ORC_QMAX : (v < -ORC_QMAX ? -ORC_QMAX : v); }
+static int sat_q(int v, int Q) { return v > Q ? Q : (v < -Q ? -Q : v); }
 static int iabs_(int v) { return v < 0 ? -v : v; }
 
 /* Normalised/offset magnitude (Sec. III NMS and OMS in fixed point). */
@@ -147,10 +152,26 @@ static int params_q(double alpha, double beta, double step, int *a8, int *b)
     return 0;
 }
 
-static int input_q_ok(long n, const int8_t *llr)
+/* Fixed-point pairs of iterations 1..max_iter: the constant (alpha, beta)
+ * when sched is NULL, else row min(k, n_sched) - 1 of sched [n_sched][2]. */
+static int schedule_q(int max_iter, const double *sched, int n_sched, double alpha, double beta,
+                      double step, int *a8k, int *bk)
+{
+    for (int k = 1; k <= max_iter; ++k) {
+        const int r = (k < n_sched ? k : n_sched) - 1;
+        if (sched ? params_q(sched[2 * r], sched[2 * r + 1], step, &a8k[k], &bk[k])
+                  : params_q(alpha, beta, step, &a8k[k], &bk[k]))
+            return -1;
+    }
+    return 0;
+}
+
+static int qmax_of(int qbits) { return qbits >= 6 && qbits <= 8 ? (1 << (qbits - 1)) - 1 : -1; }
+
+static int input_q_ok(long n, const int8_t *llr, int Q)
 {
     for (long i = 0; i < n; ++i)
-        if (llr[i] < -ORC_QMAX || llr[i] > ORC_QMAX) return 0;
+        if (llr[i] < -Q || llr[i] > Q) return 0;
     return 1;
 }
 
@@ -170,7 +191,7 @@ int oracle_two_scan_int(int M, int N, const int *row_ptr, const int *col_idx,
 {
     int a8, b;
     if (orc_check_code(M, N, row_ptr, col_idx) || n_frames < 0 || max_iter < 0 ||
-        params_q(alpha, beta, step, &a8, &b) || !input_q_ok((long)n_frames * N, llr))
+        params_q(alpha, beta, step, &a8, &b) || !input_q_ok((long)n_frames * N, llr, ORC_QMAX6))
         return -1;
     const int E = row_ptr[M];
     orc_cols cols;
@@ -208,7 +229,7 @@ int oracle_two_scan_int(int M, int N, const int *row_ptr, const int *col_idx,
                     int v = Z0[n];
                     for (int i2 = cols.ptr[n]; i2 < cols.ptr[n + 1]; ++i2)
                         if (i2 != i) v += L[cols.edge[i2]];
-                    Zmn[cols.edge[i]] = sat_q(v);
+                    Zmn[cols.edge[i]] = sat_q(v, ORC_QMAX6);
                 }
             }
             decide_q(N, Zn, x);
@@ -230,16 +251,23 @@ int oracle_two_scan_int(int M, int N, const int *row_ptr, const int *col_idx,
     return 0;
 }
 
-int oracle_single_scan_int(int M, int N, const int *row_ptr, const int *col_idx,
-                           int n_frames, const int8_t *llr, int max_iter,
-                           double alpha, double beta, int early_stop, double step,
-                           float *post_out, uint8_t *hard_out, int32_t *iters_out,
-                           uint8_t *ok_out, int32_t *trace_L, int32_t *trace_Z)
+int oracle_single_scan_int_ex(int M, int N, const int *row_ptr, const int *col_idx,
+                              int n_frames, const int8_t *llr, int max_iter,
+                              const double *sched, int n_sched, double alpha, double beta,
+                              int qbits, int early_stop, double step,
+                              float *post_out, uint8_t *hard_out, int32_t *iters_out,
+                              uint8_t *ok_out, int32_t *trace_L, int32_t *trace_Z)
 {
-    int a8, b;
-    if (orc_check_code(M, N, row_ptr, col_idx) || n_frames < 0 || max_iter < 0 ||
-        params_q(alpha, beta, step, &a8, &b) || !input_q_ok((long)n_frames * N, llr))
+    const int Q = qmax_of(qbits);
+    if (orc_check_code(M, N, row_ptr, col_idx) || n_frames < 0 || max_iter < 0 || Q < 0 ||
+        (sched && n_sched < 1) || !input_q_ok((long)n_frames * N, llr, Q))
         return -1;
+    int *a8k = (int *)malloc(sizeof(int) * ((size_t)max_iter + 1));
+    int *bk = (int *)malloc(sizeof(int) * ((size_t)max_iter + 1));
+    if (schedule_q(max_iter, sched, n_sched, alpha, beta, step, a8k, bk)) {
+        free(a8k); free(bk);
+        return -1;
+    }
     const int E = row_ptr[M];
     int *Z0 = (int *)malloc(sizeof(int) * ((size_t)N + 1));
     int *Zold = (int *)malloc(sizeof(int) * ((size_t)N + 1));
@@ -262,8 +290,8 @@ int oracle_single_scan_int(int M, int N, const int *row_ptr, const int *col_idx,
                 int d = row_ptr[m + 1] - row_ptr[m];
                 const int *cn = col_idx + row_ptr[m];
                 for (int j = 0; j < d; ++j)                          /* Z^(k-1)_n' - L^(k-1)_mn' */
-                    t[j] = sat_q(Zold[cn[j]] - L[row_ptr[m] + j]);
-                row_update_q(d, t, a8, b, Lr);                       /* Eq.(3) */
+                    t[j] = sat_q(Zold[cn[j]] - L[row_ptr[m] + j], Q);
+                row_update_q(d, t, a8k[k], bk[k], Lr);               /* Eq.(3) */
                 for (int j = 0; j < d; ++j) {
                     L[row_ptr[m] + j] = Lr[j];
                     Znew[cn[j]] += Lr[j];                            /* Z^(k)_n += L^(k)_mn */
@@ -283,8 +311,18 @@ int oracle_single_scan_int(int M, int N, const int *row_ptr, const int *col_idx,
         if (iters_out) iters_out[f] = k;
         if (ok_out) ok_out[f] = (uint8_t)orc_syndrome_ok(M, row_ptr, col_idx, x);
     }
-    free(Z0); free(Zold); free(Znew); free(L); free(t); free(Lr); free(x);
+    free(Z0); free(Zold); free(Znew); free(L); free(t); free(Lr); free(x); free(a8k); free(bk);
     return 0;
+}
+
+int oracle_single_scan_int(int M, int N, const int *row_ptr, const int *col_idx,
+                           int n_frames, const int8_t *llr, int max_iter,
+                           double alpha, double beta, int early_stop, double step,
+                           float *post_out, uint8_t *hard_out, int32_t *iters_out,
+                           uint8_t *ok_out, int32_t *trace_L, int32_t *trace_Z)
+{
+    return oracle_single_scan_int_ex(M, N, row_ptr, col_idx, n_frames, llr, max_iter, NULL, 0, alpha, beta, 6,
+                                     early_stop, step, post_out, hard_out, iters_out, ok_out, trace_L, trace_Z);
 }
 
 /* Sec. V compression of one row's messages L[0..d-1]:
@@ -322,18 +360,25 @@ void oracle_row_update_int(int d, const int32_t *t, double alpha, double beta,
     row_update_q(d, t, a8, b, L);
 }
 
-int oracle_one_bit_int(int M, int N, const int *row_ptr, const int *col_idx,
-                       int n_frames, const int8_t *llr, int max_iter,
-                       double alpha, double beta, int early_stop, double step,
-                       float *post_out, uint8_t *hard_out, int32_t *iters_out,
-                       uint8_t *ok_out, int32_t *trace_L, int32_t *trace_Z,
-                       int32_t *state_out /* [F][M][3] = A, B, n~ after the last iteration; nullable */,
-                       uint8_t *sign_out /* [F][E]; nullable */)
+int oracle_one_bit_int_ex(int M, int N, const int *row_ptr, const int *col_idx,
+                          int n_frames, const int8_t *llr, int max_iter,
+                          const double *sched, int n_sched, double alpha, double beta,
+                          int qbits, int early_stop, double step,
+                          float *post_out, uint8_t *hard_out, int32_t *iters_out,
+                          uint8_t *ok_out, int32_t *trace_L, int32_t *trace_Z,
+                          int32_t *state_out /* [F][M][3] = A, B, n~ after the last iteration; nullable */,
+                          uint8_t *sign_out /* [F][E]; nullable */)
 {
-    int a8, b;
-    if (orc_check_code(M, N, row_ptr, col_idx) || n_frames < 0 || max_iter < 0 ||
-        params_q(alpha, beta, step, &a8, &b) || !input_q_ok((long)n_frames * N, llr))
+    const int Q = qmax_of(qbits);
+    if (orc_check_code(M, N, row_ptr, col_idx) || n_frames < 0 || max_iter < 0 || Q < 0 ||
+        (sched && n_sched < 1) || !input_q_ok((long)n_frames * N, llr, Q))
         return -1;
+    int *a8k = (int *)malloc(sizeof(int) * ((size_t)max_iter + 1));
+    int *bk = (int *)malloc(sizeof(int) * ((size_t)max_iter + 1));
+    if (schedule_q(max_iter, sched, n_sched, alpha, beta, step, a8k, bk)) {
+        free(a8k); free(bk);
+        return -1;
+    }
     const int E = row_ptr[M];
     int *Z0 = (int *)malloc(sizeof(int) * ((size_t)N + 1));
     int *Zold = (int *)malloc(sizeof(int) * ((size_t)N + 1));
@@ -362,8 +407,8 @@ int oracle_one_bit_int(int M, int N, const int *row_ptr, const int *col_idx,
                 int d = row_ptr[m + 1] - row_ptr[m];
                 const int *cn = col_idx + row_ptr[m];
                 oracle_expand_row_int(d, A[m], B[m], nt[m], s + row_ptr[m], Lold);  /* L^(k-1) */
-                for (int j = 0; j < d; ++j) t[j] = sat_q(Zold[cn[j]] - Lold[j]);
-                row_update_q(d, t, a8, b, Lnew);                                    /* L^(k), normalised */
+                for (int j = 0; j < d; ++j) t[j] = sat_q(Zold[cn[j]] - Lold[j], Q);
+                row_update_q(d, t, a8k[k], bk[k], Lnew);                            /* L^(k), normalised */
                 for (int j = 0; j < d; ++j) Znew[cn[j]] += Lnew[j];                 /* Z += L */
                 oracle_compress_row_int(d, Lnew, &A[m], &B[m], &nt[m], s + row_ptr[m]); /* Eqs.(4),(5) */
                 if (Lall) for (int j = 0; j < d; ++j) Lall[row_ptr[m] + j] = Lnew[j];
@@ -390,8 +435,20 @@ int oracle_one_bit_int(int M, int N, const int *row_ptr, const int *col_idx,
         if (sign_out) memcpy(sign_out + (size_t)f * E, s, (size_t)E);
     }
     free(Z0); free(Zold); free(Znew); free(A); free(B); free(nt); free(s);
-    free(Lold); free(Lnew); free(t); free(Lall); free(x);
+    free(Lold); free(Lnew); free(t); free(Lall); free(x); free(a8k); free(bk);
     return 0;
+}
+
+int oracle_one_bit_int(int M, int N, const int *row_ptr, const int *col_idx,
+                       int n_frames, const int8_t *llr, int max_iter,
+                       double alpha, double beta, int early_stop, double step,
+                       float *post_out, uint8_t *hard_out, int32_t *iters_out,
+                       uint8_t *ok_out, int32_t *trace_L, int32_t *trace_Z,
+                       int32_t *state_out, uint8_t *sign_out)
+{
+    return oracle_one_bit_int_ex(M, N, row_ptr, col_idx, n_frames, llr, max_iter, NULL, 0, alpha, beta, 6,
+                                 early_stop, step, post_out, hard_out, iters_out, ok_out, trace_L, trace_Z,
+                                 state_out, sign_out);
 }
 
 /* ------------------------------------------------------------------------ */
