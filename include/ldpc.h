@@ -45,7 +45,8 @@ typedef enum {
 /* Message representation (Sec. V uses b = 6..8 bit fixed point). */
 typedef enum {
     LDPC_MSG_FP32 = 0, /* binary32 messages and posteriors */
-    LDPC_MSG_INT8 = 1, /* 6-bit fixed point held in int8, extrinsics saturated to +-31 */
+    LDPC_MSG_INT8 = 1, /* b-bit fixed point held in int8 (b = msg_bits, default 6: extrinsics
+                          saturated to +-31) */
     LDPC_MSG_1BIT = 2  /* Sec. V: per-edge sign bit + per-check (A, B, n~), 6-bit values */
 } ldpc_msg;
 
@@ -90,11 +91,26 @@ typedef enum {
  *  early_stop nonzero: stop a frame after the first iteration k >= 1 whose
  *             hard decision satisfies H x^T = 0 (Sec. III decoding step).
  *  weights    NULL, or device float32 [weight_iters][C][2]: per iteration k
- *             (row min(k, weight_iters) - 1) and check-degree class c (the
- *             distinct row degrees ascending, see ldpc_learn.h) the pair
- *             (a, b) replacing (alpha, beta).  FP32 single-scan only (it runs
- *             frames across lanes); other paths return LDPC_EUNSUPPORTED.
+ *             (row min(k, weight_iters) - 1) and check-degree class c the
+ *             pair (a, b) replacing (alpha, beta) (Sec. III indexes lambda
+ *             and beta by the iteration).  C is set by weight_classes.
+ *             FP32 single-scan takes either form (it then runs frames across
+ *             lanes); fixed-point single-scan (INT8, 1BIT, every layout but
+ *             FRAMES) takes one pair per iteration, converted per iteration
+ *             like alpha and beta: a8 = round(256 a), b = round(b / llr_step),
+ *             clamped to [0, 256] and [0, 255] (pairs are device data and are
+ *             not validated; keep 0 < a <= 1, b >= 0 for the method's
+ *             meaning).  Two-scan returns LDPC_EUNSUPPORTED.
  *  weight_iters rows of `weights` (>= 1 when weights is set).
+ *  weight_classes 0: C = the code's check-degree classes (the distinct row
+ *             degrees ascending, see ldpc_learn.h; FP32 only unless the code
+ *             has one class); 1: C = 1, one pair per iteration for all rows.
+ *  msg_bits   fixed-point message width b of Sec. V: 0 or 6 (default), 7 or 8.
+ *             Extrinsics saturate to Q = 2^(b-1) - 1 (31, 63, 127) and INT8
+ *             inputs range over [-Q, Q] in units of llr_step.  7 and 8 bits:
+ *             INT8 single-scan on the LDS/HBM kernel only (AUTO picks it;
+ *             REG, REG1 and FRAMES return LDPC_EUNSUPPORTED); 1BIT and
+ *             two-scan are 6-bit only.  Ignored for FP32 when 0 or 6.
  */
 typedef struct {
     int32_t max_iter;
@@ -107,6 +123,8 @@ typedef struct {
     uint32_t flags;
     const float *weights;
     int32_t weight_iters;
+    int32_t weight_classes;
+    int32_t msg_bits;
 } ldpc_decode_params;
 
 /* Facts about a code handle and its planned device layouts. */
@@ -162,8 +180,9 @@ ldpc_status ldpc_decode_workspace_size(const ldpc_code *code, int32_t n_frames,
 /*
  * Decode n_frames frames (one parity-check matrix, Sec. III-V).
  *  llr_in      device [F][N]: float32 channel LLRs Z^(0) for LDPC_MSG_FP32;
- *              int8 fixed-point LLRs in [-31, 31] (units of llr_step) for INT8
- *              and 1BIT (values outside are saturated).
+ *              int8 fixed-point LLRs in [-Q, Q] (units of llr_step; Q = 31 for
+ *              the default 6-bit messages) for INT8 and 1BIT (values outside
+ *              are saturated).
  *  hard_out    device [F][N] uint8: x_n = 0 if Z_n > 0 else 1.
  *  llr_out     device [F][N] float32 posterior Z_n (fixed point: Z * llr_step,
  *              exact); may be NULL.
@@ -177,9 +196,12 @@ ldpc_status ldpc_decode_workspace_size(const ldpc_code *code, int32_t n_frames,
  * synchronises (except with LDPC_F_CHECK_INPUT).  Each frame's result depends
  * only on its own input.  max_iter = 0 returns the channel decisions.
  * Errors: LDPC_EINVAL for n_frames < 0, max_iter < 0, alpha outside (0, 1],
- * beta < 0, llr_step <= 0, a required NULL pointer or a small workspace;
- * LDPC_EUNSUPPORTED for LDPC_TWO_SCAN with LDPC_MSG_1BIT or a forced layout
- * that does not fit; LDPC_EDEVICE for a failed launch.
+ * beta < 0, llr_step <= 0, a required NULL pointer, a small workspace,
+ * weight_iters < 1 with weights, weight_classes outside {0, 1} or msg_bits
+ * outside {0, 6, 7, 8}; LDPC_EUNSUPPORTED for LDPC_TWO_SCAN with
+ * LDPC_MSG_1BIT, a forced layout that does not fit, weights or message
+ * widths on a path that has no kernel for them (see above); LDPC_EDEVICE
+ * for a failed launch.
  */
 ldpc_status ldpc_decode_batch(const ldpc_code *code, int32_t n_frames, const void *llr_in,
                               const ldpc_decode_params *p, uint8_t *hard_out, float *llr_out,

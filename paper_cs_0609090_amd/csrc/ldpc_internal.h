@@ -10,6 +10,8 @@ namespace ldpc {
 constexpr int kWave = 64;     // CDNA wavefront width
 constexpr int kQmax = 31;     // 6-bit message range: extrinsics saturate to +-31
 constexpr int kZoldMax = 62;  // stored Z_{n} saturates to +-62 (see ss_int.hip)
+// b-bit messages (Sec. V, b = 6..8): extrinsics saturate to Q = 2^(b-1) - 1 and
+// the stored Z_old to 2Q, which keeps sat_Q(sat_2Q(Z) - L) = sat_Q(Z - L) for |L| <= Q
 
 enum Msg : int { MSG_FP32 = 0, MSG_INT8 = 1, MSG_1BIT = 2 };
 
@@ -55,7 +57,25 @@ struct DecodeArgs {
     uint32_t off_aux;
     uint64_t ws_off_msg;     // workspace byte offsets inside one frame's stride
     uint64_t ws_off_z;
+    // fixed point: per-iteration (a, b) pairs [wsched_T][2] replacing a8/b_int
+    // (null: the constant pair), and the message width
+    const float *wsched;
+    int32_t wsched_T;
+    int32_t qmax;            // Q: extrinsic bound (31, 63, 127)
+    int32_t zmax;            // 2Q: bound of the stored Z_old
 };
+
+// Fixed-point pair of iteration `it` from the schedule: row min(it, T) - 1,
+// a8 = round(256 a), b = round(b / step) (half away from zero, binary64 as
+// for the constant pair), clamped to [0, 256] and [0, 255].
+__device__ __forceinline__ void sched_pair(const DecodeArgs &a, int it, int &a8, int &b) {
+    const int r = min(it, a.wsched_T) - 1;
+    const double xa = (double)a.wsched[2 * r] * 256.0;
+    const double xb = (double)a.wsched[2 * r + 1] / a.step;
+    // clamped in binary64 first (NaN goes to 0), so the conversions are in range
+    a8 = __builtin_amdgcn_readfirstlane((int)fmin(fmax(round(xa), 0.0), 256.0));
+    b = __builtin_amdgcn_readfirstlane((int)fmin(fmax(round(xb), 0.0), 255.0));
+}
 
 struct LaunchCfg {
     int dmax;        // register-array bucket: 8, 16, 32 or 64 slots
@@ -87,7 +107,7 @@ void pk_shapes(int *out, int cap, int *count);   // (D, R) pairs
 bool reg_shape_available(int D, int R, int P);
 void reg_shapes(int *out, int cap, int *count);  // (D, R, P) triples
 constexpr int kRegThreads = 1024;
-hipError_t launch_check_input(const void *llr, int64_t count, int msg, int32_t *bad,
+hipError_t launch_check_input(const void *llr, int64_t count, int msg, int qmax, int32_t *bad,
                               hipStream_t s);
 
 // Launch bound (threads) of each register-array bucket.

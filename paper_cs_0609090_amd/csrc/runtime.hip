@@ -18,6 +18,7 @@ thread_local std::string g_err;
 
 // LDS per workgroup assumed for host-only handles: one gfx950 CU (160 KiB).
 constexpr int kHostOnlyLds = 160 * 1024;
+constexpr int kQmax6 = 31;  // Q of the default 6-bit messages
 
 ldpc_status fail(ldpc_status st, const std::string &msg) {
     g_err = msg;
@@ -54,10 +55,18 @@ ldpc_status validate_params(const ldpc_decode_params *p) {
     const uint32_t layout = (p->flags >> LDPC_F_LAYOUT_SHIFT) & 0xFu;
     if (layout > LDPC_LAYOUT_FRAMES) return fail(LDPC_EINVAL, "unknown layout override");
     if (p->weights && p->weight_iters < 1) return fail(LDPC_EINVAL, "weight_iters must be >= 1 with weights");
-    if (p->weights && (p->msg != LDPC_MSG_FP32 || p->sched != LDPC_SINGLE_SCAN))
-        return fail(LDPC_EUNSUPPORTED, "per-iteration weights: FP32 single-scan only");
+    if (p->weight_classes != 0 && p->weight_classes != 1) return fail(LDPC_EINVAL, "weight_classes must be 0 or 1");
+    if (p->msg_bits != 0 && (p->msg_bits < 6 || p->msg_bits > 8))
+        return fail(LDPC_EINVAL, "msg_bits must be 0, 6, 7 or 8");
+    if (p->msg_bits > 6 && (p->msg != LDPC_MSG_INT8 || p->sched != LDPC_SINGLE_SCAN))
+        return fail(LDPC_EUNSUPPORTED, "7-8 bit messages: INT8 single-scan only");
+    if (p->weights && p->sched != LDPC_SINGLE_SCAN)
+        return fail(LDPC_EUNSUPPORTED, "per-iteration weights: single-scan only");
     return LDPC_OK;
 }
+
+// Q of the call's fixed-point messages: 2^(b-1) - 1 for b = msg_bits (6 by default).
+int qmax_of(const ldpc_decode_params *p) { return (1 << ((p->msg_bits ? p->msg_bits : 6) - 1)) - 1; }
 
 ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl) {
     const int D = c->D, Mp = c->Mp;
@@ -76,13 +85,19 @@ ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl)
     const bool allow_hbm = layout == LDPC_LAYOUT_AUTO || layout == LDPC_LAYOUT_HBM;
 
     const bool reg_layout = layout == LDPC_LAYOUT_REG || layout == LDPC_LAYOUT_REG1;
+    const int qmax = qmax_of(p);
+    if (p->weights && p->msg != LDPC_MSG_FP32 && p->weight_classes == 0 && c->learn_classes > 1)
+        return fail(LDPC_EUNSUPPORTED,
+                    "per-class pairs are FP32 only; fixed point takes one pair per iteration (weight_classes = 1)");
+    if (qmax != kQmax6 && reg_layout)
+        return fail(LDPC_EUNSUPPORTED, "7-8 bit messages run on the LDS/HBM kernel only");
     // AUTO for fixed point (measured on MI355X, 50 iterations): the packed
     // two-rows-per-lane kernel pays off from 16 rows per thread (M > 8192);
     // below that the one-row register kernel is faster, and codes of at most
     // 1024 checks run best LDS-resident with one thread per row (the register
     // kernels give every frame 1024 threads).
     const bool small_auto = layout == LDPC_LAYOUT_AUTO && c->M <= 1024;
-    if (p->sched == LDPC_SINGLE_SCAN && p->msg != LDPC_MSG_FP32 && !small_auto &&
+    if (p->sched == LDPC_SINGLE_SCAN && p->msg != LDPC_MSG_FP32 && !small_auto && qmax == kQmax6 &&
         (layout == LDPC_LAYOUT_AUTO || reg_layout)) {
         const bool packed = c->pkD > 0 && layout != LDPC_LAYOUT_REG1 &&
                             (layout == LDPC_LAYOUT_REG || c->pkR >= 16);  // int8 and 1-bit
@@ -105,7 +120,7 @@ ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl)
             return fail(LDPC_EUNSUPPORTED, "no register-resident shape for this code and message type");
     }
     if (reg_layout) return fail(LDPC_EUNSUPPORTED, "register layout is single-scan INT8/1BIT only");
-    if (p->weights) {  // the weighted decoder runs frames across lanes
+    if (p->weights && p->msg == LDPC_MSG_FP32) {  // the weighted binary32 decoder runs frames across lanes
         if (layout != LDPC_LAYOUT_AUTO && layout != LDPC_LAYOUT_FRAMES)
             return fail(LDPC_EUNSUPPORTED, "per-iteration weights need the frames-across-lanes layout");
         if (ldpc::fl_chunk_frames(c->N, c->E) <= 0)
@@ -130,11 +145,11 @@ ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl)
 
     if (p->sched == LDPC_SINGLE_SCAN && p->msg != LDPC_MSG_FP32) {
         pl->family = 0;
-        const size_t zold = align_up(nz, 16);
+        const size_t zold = align_up(nz * (qmax > 63 ? 2 : 1), 16);  // int16 Z_old for 8-bit messages
         const size_t msg = align_up(p->msg == LDPC_MSG_INT8 ? (size_t)D * Mp
                                                              : (size_t)D * (Mp / 64) * 8 + 2 * (size_t)Mp,
                                     16);
-        const int span = 31 * (c->max_col_deg + 1);  // bound on |partial Z| (Eq. 3 sums)
+        const int span = qmax * (c->max_col_deg + 1);  // bound on |partial Z| (Eq. 3 sums)
         for (int pass = 0; pass < 2; ++pass) {
             const bool msg_lds = pass == 0;
             if ((msg_lds && !allow_lds) || (!msg_lds && !allow_hbm)) continue;
@@ -202,7 +217,7 @@ ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl)
     return fail(LDPC_EUNSUPPORTED, "no layout fits the requested override");
 }
 
-__global__ void check_input_kernel(const void *llr, int64_t count, int msg, int32_t *bad) {
+__global__ void check_input_kernel(const void *llr, int64_t count, int msg, int qmax, int32_t *bad) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
         bool b;
@@ -210,7 +225,7 @@ __global__ void check_input_kernel(const void *llr, int64_t count, int msg, int3
             b = !isfinite(static_cast<const float *>(llr)[i]);
         } else {
             const int v = static_cast<const int8_t *>(llr)[i];
-            b = v < -ldpc::kQmax || v > ldpc::kQmax;
+            b = v < -qmax || v > qmax;
         }
         if (b) atomicOr(bad, 1);
     }
@@ -300,11 +315,11 @@ void clear_error() { g_err.clear(); }
 }  // namespace ldpc
 
 namespace ldpc {
-hipError_t launch_check_input(const void *llr, int64_t count, int msg, int32_t *bad, hipStream_t s) {
+hipError_t launch_check_input(const void *llr, int64_t count, int msg, int qmax, int32_t *bad, hipStream_t s) {
     hipLaunchKernelGGL(zero_word_kernel, dim3(1), dim3(1), 0, s, bad);
     if (count > 0) {
         const int64_t blocks = std::min<int64_t>((count + 255) / 256, 4096);
-        hipLaunchKernelGGL(check_input_kernel, dim3((unsigned)blocks), dim3(256), 0, s, llr, count, msg, bad);
+        hipLaunchKernelGGL(check_input_kernel, dim3((unsigned)blocks), dim3(256), 0, s, llr, count, msg, qmax, bad);
     }
     return hipGetLastError();
 }
@@ -657,7 +672,7 @@ ldpc_status decode_job(const ldpc_code *c, int32_t n_frames, const void *llr_in,
 
     if (p->flags & LDPC_F_CHECK_INPUT) {
         int32_t *bad = reinterpret_cast<int32_t *>(static_cast<uint8_t *>(workspace) + check_off);
-        hipError_t e = ldpc::launch_check_input(llr_in, (int64_t)n_frames * c->N, p->msg, bad, s);
+        hipError_t e = ldpc::launch_check_input(llr_in, (int64_t)n_frames * c->N, p->msg, qmax_of(p), bad, s);
         int32_t hbad = 0;
         if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -701,6 +716,10 @@ ldpc_status decode_job(const ldpc_code *c, int32_t n_frames, const void *llr_in,
     a.off_aux = pl.off_aux;
     a.ws_off_msg = pl.ws_off_msg;
     a.ws_off_z = pl.ws_off_z;
+    a.wsched = p->msg == LDPC_MSG_FP32 ? nullptr : p->weights;  // binary32 takes its pairs below
+    a.wsched_T = p->weight_iters;
+    a.qmax = qmax_of(p);
+    a.zmax = 2 * a.qmax;
 
     hipError_t e;
     if (pl.family == 0)
@@ -716,7 +735,7 @@ ldpc_status decode_job(const ldpc_code *c, int32_t n_frames, const void *llr_in,
                                      c->D, c->cu_count, s);
     else if (pl.family == 5)
         e = ldpc::launch_ss_f32_fl(a, c->d_row_ptr, c->d_row_ent, c->E, c->D, c->cu_count, p->weights,
-                                   p->weight_iters, c->d_row_cls, c->learn_classes, s);
+                                   p->weight_iters, c->d_row_cls, p->weight_classes == 1 ? 1 : c->learn_classes, s);
     else
         e = ldpc::launch_two_scan(a, p->msg, pl.cfg, s);
     if (e != hipSuccess) return fail(LDPC_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));

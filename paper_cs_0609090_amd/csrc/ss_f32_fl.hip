@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(kBlock) fl_check(FlArgs a, const float *__rest
             float wa = a.alpha, wb = a.beta;
             if (a.W) {  // per-iteration, per-class pair
                 const auto *Wt = cptr(a.W) + (size_t)(min(it, a.Tw) - 1) * a.C * 2;
-                const int c = cptr(a.row_cls)[m];
+                const int c = a.C > 1 ? cptr(a.row_cls)[m] : 0;  // one column: a pair per iteration
                 wa = Wt[2 * c];
                 wb = Wt[2 * c + 1];
             }

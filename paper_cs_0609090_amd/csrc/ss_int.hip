@@ -1,5 +1,8 @@
-// Single-scan min-sum in 6-bit fixed point: int8 messages (Sec. IV, Eq. 3) and
-// the compressed 1-bit form (Sec. V), one workgroup per frame.
+// Single-scan min-sum in b-bit fixed point: int8 messages (Sec. IV, Eq. 3;
+// b = 6, 7 or 8) and the compressed 1-bit form (Sec. V, 6-bit values), one
+// workgroup per frame.  Below, 31 and 62 are the 6-bit Q and 2Q; b-bit
+// messages use Q = 2^(b-1) - 1 and 2Q in their place, with Z_old in int16
+// for b = 8.
 //
 // Per frame and iteration k the workgroup makes one pass over the
 // check-to-variable addressing (slot-major ELL, a thread per check row):
@@ -69,8 +72,9 @@ __device__ __forceinline__ int norm_q(int mag, int a8, int b) {
 }
 
 // Row parity of hard decisions; sets *flag when a check fails.
+template <typename ZT>
 __device__ void syndrome_pass(int tid, int T, int Mp, int D, const uint32_t *__restrict__ ell,
-                              const int8_t *zold, int *flag) {
+                              const ZT *zold, int *flag) {
     for (int m = tid; m < Mp; m += T) {
         int p = 0;
         for (int j = 0; j < D; ++j) p ^= (zold[ell[j * Mp + m]] <= 0) ? 1 : 0;
@@ -83,7 +87,9 @@ __device__ void syndrome_pass(int tid, int T, int Mp, int D, const uint32_t *__r
 // zero syndrome stops the frame with k-1 iterations, its decisions read from
 // Z_old (the saturated copy keeps the sign and zero of Z^(k-1)).  Otherwise a
 // separate check pass follows each iteration.
-template <int DMAX, int MSG, bool MSG_LDS, bool FUSED>
+// b-bit messages: extrinsics saturate to Q = a.qmax, the stored Z_old to
+// 2Q = a.zmax, held in ZT (int8 up to 7 bits, int16 for 8).
+template <int DMAX, int MSG, bool MSG_LDS, bool FUSED, typename ZT>
 __global__ void __launch_bounds__(launch_bound_for(DMAX)) ss_int_kernel(DecodeArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
     const int tid = threadIdx.x;
@@ -92,7 +98,8 @@ __global__ void __launch_bounds__(launch_bound_for(DMAX)) ss_int_kernel(DecodeAr
     const int N = a.c.N, Mp = a.c.Mp, D = a.c.D;
     const uint32_t dummy = (uint32_t)a.c.dummy;
     const uint32_t *__restrict__ ell = a.c.ell;
-    int8_t *zold = reinterpret_cast<int8_t *>(lds + a.off_zold);
+    ZT *zold = reinterpret_cast<ZT *>(lds + a.off_zold);
+    const int Q = a.qmax, Z2 = a.zmax;
     uint32_t *zacc = reinterpret_cast<uint32_t *>(lds + a.off_zacc);
     int *flag = reinterpret_cast<int *>(lds + a.off_aux);  // [0]: separate check, [1], [2]: fused
     uint8_t *st = MSG_LDS ? (lds + a.off_msg) : (a.ws + (size_t)f * a.ws_stride + a.ws_off_msg);
@@ -107,13 +114,13 @@ __global__ void __launch_bounds__(launch_bound_for(DMAX)) ss_int_kernel(DecodeAr
         uint32_t v = 0;
         for (int i = 0; i < P; ++i) {
             const int n = w * P + i;
-            const int z = n < N ? clamp_i(z0[n], -kQmax, kQmax) : 0;
+            const int z = n < N ? clamp_i(z0[n], -Q, Q) : 0;
             v |= (uint32_t)(z + zp.bias) << (i * zp.bits);
         }
         zacc[w] = v;
     }
     for (int n = tid; n <= (int)dummy; n += T)
-        zold[n] = (int8_t)(n < N ? clamp_i(z0[n], -kQmax, kQmax) : (n == (int)dummy ? kZoldMax : 0));
+        zold[n] = (ZT)(n < N ? clamp_i(z0[n], -Q, Q) : (n == (int)dummy ? Z2 : 0));
     {
         const int words = (MSG == MSG_INT8) ? (D * Mp) / 4 : (D * MpW * 8 + 2 * Mp) / 4;
         uint32_t *s32 = reinterpret_cast<uint32_t *>(st);
@@ -130,6 +137,7 @@ __global__ void __launch_bounds__(launch_bound_for(DMAX)) ss_int_kernel(DecodeAr
     unsigned long long *sgn = reinterpret_cast<unsigned long long *>(st);
     uint16_t *cst = reinterpret_cast<uint16_t *>(st + (size_t)D * MpW * 8);
 
+    int a8 = a.a8, bq = a.b_int;  // normalisation pair
     int iters = 0;
     bool converged = false;  // the decision of the last completed iteration is a codeword
     bool conv_prev = false;  // FUSED: that of the iteration before the last one is
@@ -139,6 +147,7 @@ __global__ void __launch_bounds__(launch_bound_for(DMAX)) ss_int_kernel(DecodeAr
         // first barrier, the other one (read last iteration) is cleared here
         int zodd = 0;
         if (FUSED && tid == 0) flag[1 + ((k + 1) & 1)] = 0;
+        if (a.wsched) sched_pair(a, k, a8, bq);  // per-iteration pair (Sec. III's lambda_k, beta_k)
         // ---- check pass (Eq. 3), one row per thread
         for (int m = tid; m < Mp; m += T) {
             uint32_t nid[DMAX];
@@ -169,7 +178,7 @@ __global__ void __launch_bounds__(launch_bound_for(DMAX)) ss_int_kernel(DecodeAr
                     lo[j] = l;
                     const int zv = (int)zold[n];
                     if (FUSED) hpar ^= zv - 1;  // sign bit: Z_old <= 0
-                    const int t = clamp_i(zv - l, -kQmax, kQmax);
+                    const int t = clamp_i(zv - l, -Q, Q);
                     tt[j] = t;
                     par ^= t;
                     const uint32_t key = ((uint32_t)(t < 0 ? -t : t) << 6) | (uint32_t)j;
@@ -179,8 +188,8 @@ __global__ void __launch_bounds__(launch_bound_for(DMAX)) ss_int_kernel(DecodeAr
             }
             if (FUSED) zodd |= hpar;
             const int idx = (int)(min1 & 63u);
-            const int A = norm_q((int)(min1 >> 6), a.a8, a.b_int);
-            const int B = norm_q((int)(min2 >> 6), a.a8, a.b_int);
+            const int A = norm_q((int)(min1 >> 6), a8, bq);
+            const int B = norm_q((int)(min2 >> 6), a8, bq);
             if (MSG == MSG_1BIT) cst[m] = (uint16_t)(A | (B << 5) | (idx << 10));
 #pragma unroll
             for (int j = 0; j < DMAX; ++j) {
@@ -215,7 +224,7 @@ __global__ void __launch_bounds__(launch_bound_for(DMAX)) ss_int_kernel(DecodeAr
             const uint32_t v = zacc[w];
             for (int i = 0; i < P; ++i) {
                 const int n = w * P + i;
-                if (n < N) zold[n] = (int8_t)clamp_i(zfield(v, (uint32_t)(i * zp.bits), zp), -kZoldMax, kZoldMax);
+                if (n < N) zold[n] = (ZT)clamp_i(zfield(v, (uint32_t)(i * zp.bits), zp), -Z2, Z2);
             }
         }
         __syncthreads();
@@ -255,9 +264,9 @@ __global__ void __launch_bounds__(launch_bound_for(DMAX)) ss_int_kernel(DecodeAr
     }
 }
 
-template <int DMAX, int MSG, bool ML, bool FUSED>
+template <int DMAX, int MSG, bool ML, bool FUSED, typename ZT>
 hipError_t launch_one(const DecodeArgs &a, const LaunchCfg &c, hipStream_t s) {
-    auto kern = ss_int_kernel<DMAX, MSG, ML, FUSED>;
+    auto kern = ss_int_kernel<DMAX, MSG, ML, FUSED, ZT>;
     if (c.lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds);
@@ -267,17 +276,20 @@ hipError_t launch_one(const DecodeArgs &a, const LaunchCfg &c, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int DMAX, int MSG>
+template <int DMAX, int MSG, typename ZT>
 hipError_t launch_msg(const DecodeArgs &a, const LaunchCfg &c, hipStream_t s) {
     // the fused check needs at least one iteration and no posterior output
     if (a.early_stop && a.llr_out == nullptr && a.max_iter >= 1)
-        return c.msg_lds ? launch_one<DMAX, MSG, true, true>(a, c, s) : launch_one<DMAX, MSG, false, true>(a, c, s);
-    return c.msg_lds ? launch_one<DMAX, MSG, true, false>(a, c, s) : launch_one<DMAX, MSG, false, false>(a, c, s);
+        return c.msg_lds ? launch_one<DMAX, MSG, true, true, ZT>(a, c, s)
+                         : launch_one<DMAX, MSG, false, true, ZT>(a, c, s);
+    return c.msg_lds ? launch_one<DMAX, MSG, true, false, ZT>(a, c, s)
+                     : launch_one<DMAX, MSG, false, false, ZT>(a, c, s);
 }
 
 template <int DMAX>
 hipError_t launch_dmax(const DecodeArgs &a, int msg, const LaunchCfg &c, hipStream_t s) {
-    return msg == MSG_INT8 ? launch_msg<DMAX, MSG_INT8>(a, c, s) : launch_msg<DMAX, MSG_1BIT>(a, c, s);
+    if (msg != MSG_INT8) return launch_msg<DMAX, MSG_1BIT, int8_t>(a, c, s);  // 1-bit state: 6-bit values
+    return a.zmax > 127 ? launch_msg<DMAX, MSG_INT8, int16_t>(a, c, s) : launch_msg<DMAX, MSG_INT8, int8_t>(a, c, s);
 }
 
 }  // namespace

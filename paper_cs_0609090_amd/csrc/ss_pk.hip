@@ -135,8 +135,8 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
     __syncthreads();
 
     const uint32_t tid16 = (uint32_t)tid * 16u;
-    const uint32_t a8x2 = (uint32_t)a.a8 * 0x00010001u;
-    const uint32_t bx2 = (uint32_t)a.b_int * 0x00010001u;
+    uint32_t a8x2 = (uint32_t)a.a8 * 0x00010001u;  // normalisation pair, both 16-bit halves
+    uint32_t bx2 = (uint32_t)a.b_int * 0x00010001u;
     int iters = 0;
     bool converged = false;  // the decision of the last completed iteration is a codeword
     bool conv_prev = false;  // FUSED: that of the iteration before the last one is
@@ -148,6 +148,12 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
         // first barrier, the other one (read last iteration) is cleared here
         uint32_t zodd = 0;
         if (FUSED && tid == 0) flag[1 + ((it + 1) & 1)] = 0;
+        if (a.wsched) {  // per-iteration pair (Sec. III's lambda_k, beta_k)
+            int a8i, bi;
+            sched_pair(a, it, a8i, bi);
+            a8x2 = (uint32_t)a8i * 0x00010001u;
+            bx2 = (uint32_t)bi * 0x00010001u;
+        }
 #pragma unroll
         for (int p = 0; p < RP; ++p) {
             __builtin_amdgcn_sched_barrier(0);

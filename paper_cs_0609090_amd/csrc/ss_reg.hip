@@ -130,8 +130,8 @@ __global__ void __launch_bounds__(kT) ss_reg_kernel(DecodeArgs a) {
     __syncthreads();
 
     const uint32_t tid4 = (uint32_t)tid * 4u;
-    const uint32_t a8 = (uint32_t)a.a8;
-    const int bq = a.b_int;
+    uint32_t a8 = (uint32_t)a.a8;  // normalisation pair
+    int bq = a.b_int;
     int iters = 0;
     bool converged = false;  // the decision of the last completed iteration is a codeword
     bool conv_prev = false;  // FUSED: that of the iteration before the last one is
@@ -141,6 +141,11 @@ __global__ void __launch_bounds__(kT) ss_reg_kernel(DecodeArgs a) {
         // first barrier, the other one (read last iteration) is cleared here
         int zodd = 0;
         if (FUSED && tid == 0) flag[1 + ((it + 1) & 1)] = 0;
+        if (a.wsched) {  // per-iteration pair (Sec. III's lambda_k, beta_k)
+            int a8i;
+            sched_pair(a, it, a8i, bq);
+            a8 = (uint32_t)a8i;
+        }
         // indices of the next row are loaded one row ahead; the scheduling
         // barriers keep the unrolled rows from hoisting every load to the top
         // The index stream is the same every iteration; an opaque zero added to

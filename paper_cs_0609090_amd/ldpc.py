@@ -54,7 +54,8 @@ class DecodeParams(ctypes.Structure):
                 ("beta", ctypes.c_float), ("early_stop", ctypes.c_int32),
                 ("msg", ctypes.c_int32), ("sched", ctypes.c_int32),
                 ("llr_step", ctypes.c_float), ("flags", ctypes.c_uint32),
-                ("weights", ctypes.c_void_p), ("weight_iters", ctypes.c_int32)]
+                ("weights", ctypes.c_void_p), ("weight_iters", ctypes.c_int32),
+                ("weight_classes", ctypes.c_int32), ("msg_bits", ctypes.c_int32)]
 
 
 class CodeInfo(ctypes.Structure):
@@ -129,16 +130,19 @@ def _check(status: int):
 
 def make_params(max_iter=50, alpha=0.8, beta=0.0, early_stop=True, msg="int8",
                 sched="single_scan", llr_step=0.5, check_input=False, layout="auto",
-                weights=None) -> DecodeParams:
-    """``weights``: None, or a float32 device tensor [T][C][2] of per-iteration,
-    per-class (a, b) pairs (FP32 single-scan); it must outlive the call."""
+                weights=None, weight_classes=0, msg_bits=0) -> DecodeParams:
+    """``weights``: None, or a float32 device tensor [T][C][2] of per-iteration
+    (a, b) pairs; it must outlive the call.  C = the code's degree classes
+    (``weight_classes=0``, binary32) or 1 (``weight_classes=1``: one pair per
+    iteration, binary32 and fixed point).  ``msg_bits``: fixed-point message
+    width 6 (default), 7 or 8 (INT8 single-scan)."""
     flags = (F_CHECK_INPUT if check_input else 0) | (LAYOUT[layout] << LAYOUT_SHIFT)
     wp = None if weights is None else weights.data_ptr()
     wt = 0 if weights is None else int(weights.shape[0])
     return DecodeParams(int(max_iter), float(alpha), float(beta), 1 if early_stop else 0,
                         MSG[msg] if isinstance(msg, str) else int(msg),
                         SCHED[sched] if isinstance(sched, str) else int(sched),
-                        float(llr_step), int(flags), wp, wt)
+                        float(llr_step), int(flags), wp, wt, int(weight_classes), int(msg_bits))
 
 
 def _ptr(t):
@@ -268,7 +272,7 @@ class Code:
 
     def decode(self, llr, max_iter=50, alpha=0.8, beta=0.0, early_stop=True, msg=None,
                sched="single_scan", llr_step=0.5, check_input=False, layout="auto",
-               with_llr=True, stream=None, weights=None) -> dict:
+               with_llr=True, stream=None, weights=None, weight_classes=0, msg_bits=0) -> dict:
         """Decode a [F, N] device tensor (float32 or int8) and return device
         tensors ``hard``, ``llr``, ``iters``, ``ok``."""
         if not llr.is_cuda:
@@ -280,7 +284,7 @@ class Code:
         if llr.dtype != want:
             raise ValueError(f"msg={msg} needs a {want} tensor")
         p = make_params(max_iter, alpha, beta, early_stop, msg, sched, llr_step,
-                        check_input, layout, weights)
+                        check_input, layout, weights, weight_classes, msg_bits)
         F = llr.shape[0]
         out = self.alloc_outputs(F, llr.device, with_llr)
         ws = self.alloc_workspace(F, p, llr.device)

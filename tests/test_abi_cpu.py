@@ -324,3 +324,62 @@ def test_multi_argument_errors(L):
     assert lib.ldpc_autotune(h, 64, ctypes.byref(p), ctypes.byref(lay), None, None) == L.LDPC_EINVAL
     assert lib.ldpc_autotune(h, 0, ctypes.byref(p), ctypes.byref(lay), None, None) == L.LDPC_EINVAL
     lib.ldpc_code_destroy(h)
+
+
+# ---------------------------------------------------------------------------
+# per-iteration schedules and 7-8 bit messages: validation and planning
+def test_schedule_and_width_validation(L):
+    import torch
+    small = L.Code.from_parity_check(W.code_c0_peg1008(), device=-1)        # one degree class
+    irr = L.Code.from_parity_check(W.random_small_code(40, 90, (3, 9), seed=31), device=-1)
+    big = L.Code.from_parity_check(W.code_ira16200(), device=-1)            # two classes
+    huge = L.Code.from_parity_check(W.code_c2_ira64800(), device=-1)
+    w = torch.zeros((4, 1, 2), dtype=torch.float32)                           # host stand-in: planning only
+
+    def status(code, **kw):
+        try:
+            code.workspace_size(8, L.make_params(**kw))
+            return L.LDPC_OK
+        except L.LdpcError as e:
+            return e.status
+
+    # widths: 0/6 default, 7 and 8 for INT8 single-scan on the LDS/HBM kernel
+    for bits in (0, 6, 7, 8):
+        assert status(small, msg="int8", msg_bits=bits) == L.LDPC_OK
+        assert status(big, msg="int8", msg_bits=bits, layout="hbm") == L.LDPC_OK
+    for bits in (5, 9, -1):
+        assert status(small, msg="int8", msg_bits=bits) == L.LDPC_EINVAL
+    for kw in (dict(msg="1bit", msg_bits=7), dict(msg="int8", sched="two_scan", msg_bits=7),
+               dict(msg="fp32", msg_bits=8), dict(msg="int8", msg_bits=7, layout="reg"),
+               dict(msg="int8", msg_bits=8, layout="reg1"), dict(msg="int8", msg_bits=7, layout="frames")):
+        assert status(big, **kw) == L.LDPC_EUNSUPPORTED, kw
+    # wider messages widen the posterior accumulator (|Z| <= Q (d_v + 1)): for
+    # the 64800-bit code (d_v = 8) 7 bits need 16-bit fields, which with Z_old
+    # no longer fit in LDS
+    assert status(huge, msg="int8", msg_bits=6, layout="hbm") == L.LDPC_OK
+    for bits in (7, 8):
+        assert status(huge, msg="int8", msg_bits=bits) == L.LDPC_EUNSUPPORTED
+    # AUTO with 7-8 bit messages leaves the register kernels for the LDS
+    # kernel (the 16200-bit code's messages still fit on chip at 7 bits)
+    assert big.workspace_size(4, L.make_params(msg="int8", msg_bits=7)) == \
+        big.workspace_size(4, L.make_params(msg="int8", msg_bits=7, layout="lds")) == 0
+    # schedules: one pair per iteration on every single-scan path; per-class
+    # pairs on fixed point only when the code has a single class
+    for msg in ("int8", "1bit"):
+        for lay in ("auto", "reg", "reg1", "lds", "hbm"):
+            st = status(big, msg=msg, layout=lay, weights=w, weight_classes=1)
+            assert st in (L.LDPC_OK, L.LDPC_EUNSUPPORTED)  # LDS may not fit the big code
+            assert status(big, msg=msg, layout=lay, weights=w, weight_classes=1) == \
+                status(big, msg=msg, layout=lay)
+        assert status(small, msg=msg, weights=w, weight_classes=0) == L.LDPC_OK
+        assert status(irr, msg=msg, weights=w, weight_classes=0) == L.LDPC_EUNSUPPORTED
+        assert status(irr, msg=msg, weights=w, weight_classes=1) == L.LDPC_OK
+    assert status(irr, msg="fp32", weights=w, weight_classes=0) == L.LDPC_OK
+    assert status(irr, msg="fp32", weights=w, weight_classes=1) == L.LDPC_OK
+    assert status(small, msg="int8", weights=w, weight_classes=2) == L.LDPC_EINVAL
+    assert status(small, msg="int8", sched="two_scan", weights=w, weight_classes=1) == L.LDPC_EUNSUPPORTED
+    # the width changes only the on-chip posterior copy: HBM message bytes stay one per edge
+    assert big.workspace_size(1, L.make_params(msg="int8", msg_bits=8, layout="hbm")) == \
+        big.workspace_size(1, L.make_params(msg="int8", layout="hbm"))
+    for c in (small, irr, big, huge):
+        c.close()

@@ -1,0 +1,119 @@
+"""Per-iteration normalisation/offset schedules and 7-8 bit messages on the
+GPU against the oracle (include/ldpc.h: weights with weight_classes = 1,
+msg_bits).
+
+Bar: bit-exact in posteriors, hard decisions, iteration counts and syndrome
+flags, as for the constant-pair decoders.  The schedule has fewer rows than
+the iteration cap, so later iterations repeat its last row.
+"""
+import numpy as np
+import pytest
+
+from paper_cs_0609090_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+CODES = {"peg1008": W.code_c0_peg1008, "ira16200": W.code_ira16200, "qc7493": W.code_c1_qc7493}
+SCHED = np.array([[0.7, 0.0], [0.75, 0.5], [0.8, 0.25], [0.875, 0.0], [0.9, 1.0]], dtype=np.float32)
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def L(torch_dev):
+    from paper_cs_0609090_amd import ldpc
+    ldpc.lib()
+    return ldpc
+
+
+def _inputs(code, F, step, qmax, seed):
+    eb = np.random.default_rng(seed).uniform(0.8, 3.2, size=F)
+    x = W.awgn_llr(code.N, F, eb, code.design_rate, key=(0x5C4, seed))
+    return W.quantize_llr(x, step=step, qmax=qmax)
+
+
+def _run(torch, L, orc, code, x, msg, layout, early_stop, with_llr, step, sched=None, bits=6, max_iter=12):
+    gcode = L.Code.from_parity_check(code)
+    w = None if sched is None else torch.from_numpy(np.ascontiguousarray(sched.reshape(-1, 1, 2))).cuda()
+    out = gcode.decode(torch.from_numpy(x).cuda(), max_iter=max_iter, early_stop=early_stop, msg=msg,
+                       layout=layout, llr_step=step, with_llr=with_llr, weights=w,
+                       weight_classes=1 if sched is not None else 0, msg_bits=bits)
+    g = {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+    gcode.close()
+    algo = "one_bit" if msg == "1bit" else "single_scan"
+    r = orc.decode(code, x, algo=algo, arith="int", max_iter=max_iter, early_stop=early_stop, step=step,
+                   sched=None if sched is None else sched.astype(np.float64), qbits=bits)
+    where = f"{code.name} {msg} {layout} es={early_stop} llr={with_llr} bits={bits} sched={sched is not None}"
+    np.testing.assert_array_equal(g["iters"], r["iters"], err_msg=f"iters {where}")
+    np.testing.assert_array_equal(g["ok"], r["ok"], err_msg=f"ok {where}")
+    np.testing.assert_array_equal(g["hard"], r["hard"], err_msg=f"hard {where}")
+    if with_llr:
+        np.testing.assert_array_equal(g["llr"], r["post"], err_msg=f"llr {where}")
+    return g
+
+
+SCHED_CASES = [("peg1008", "int8", "auto"), ("peg1008", "1bit", "auto"), ("peg1008", "int8", "hbm"),
+               ("peg1008", "int8", "reg1"), ("peg1008", "1bit", "reg1"), ("ira16200", "int8", "reg"),
+               ("ira16200", "1bit", "reg"), ("ira16200", "int8", "reg1"), ("ira16200", "1bit", "reg1"),
+               ("qc7493", "int8", "auto")]
+
+
+@pytest.mark.parametrize("early_stop,with_llr", [(False, True), (True, True), (True, False)])
+@pytest.mark.parametrize("name,msg,layout", SCHED_CASES)
+def test_schedule(torch_dev, L, orc, name, msg, layout, early_stop, with_llr):
+    code = CODES[name]()
+    F = 96 if code.N < 10000 else 40
+    x = _inputs(code, F, 0.5, 31, seed=1)
+    g = _run(torch_dev, L, orc, code, x, msg, layout, early_stop, with_llr, 0.5, sched=SCHED)
+    # the rows are really used: the constant pair of the first row decodes differently
+    if name == "peg1008" and not early_stop:
+        c = _run(torch_dev, L, orc, code, x, msg, layout, early_stop, with_llr, 0.5, sched=SCHED[:1])
+        assert not np.array_equal(g["llr"], c["llr"])
+
+
+WIDTH_CASES = [("peg1008", 7, "auto", 0.25), ("peg1008", 8, "auto", 0.125), ("peg1008", 7, "hbm", 0.5),
+               ("peg1008", 8, "hbm", 0.25), ("ira16200", 7, "auto", 0.25), ("ira16200", 8, "hbm", 0.125),
+               ("qc7493", 8, "auto", 0.125)]
+
+
+@pytest.mark.parametrize("early_stop,with_llr", [(False, True), (True, True), (True, False)])
+@pytest.mark.parametrize("name,bits,layout,step", WIDTH_CASES)
+def test_message_width(torch_dev, L, orc, name, bits, layout, step, early_stop, with_llr):
+    code = CODES[name]()
+    F = 96 if code.N < 10000 else 40
+    Q = (1 << (bits - 1)) - 1
+    x = _inputs(code, F, step, Q, seed=2)
+    if step < 0.5:  # finer steps: the inputs themselves use the wider range
+        assert np.abs(x).max() > 31
+    _run(torch_dev, L, orc, code, x, "int8", layout, early_stop, with_llr, step, bits=bits, max_iter=20)
+
+
+@pytest.mark.parametrize("bits", [7, 8])
+def test_width_with_schedule(torch_dev, L, orc, bits):
+    code = CODES["peg1008"]()
+    Q = (1 << (bits - 1)) - 1
+    x = _inputs(code, 130, 0.25, Q, seed=3)
+    _run(torch_dev, L, orc, code, x, "int8", "auto", True, True, 0.25, sched=SCHED, bits=bits, max_iter=15)
+
+
+def test_fp32_one_pair_per_iteration_equals_broadcast_classes(torch_dev, L):
+    """binary32: weight_classes = 1 equals the per-class form with every
+    class given the same pair (a code with several degree classes)."""
+    torch = torch_dev
+    code = W.random_small_code(40, 90, (3, 9), seed=31)
+    gcode = L.Code.from_parity_check(code)
+    C = len(gcode.degree_classes())
+    assert C > 1
+    x = torch.from_numpy(W.awgn_llr(code.N, 70, 2.0, code.design_rate, key=(0x5C4, 9))).cuda()
+    w1 = torch.from_numpy(np.ascontiguousarray(SCHED.reshape(-1, 1, 2))).cuda()
+    wc = torch.from_numpy(np.ascontiguousarray(np.repeat(SCHED[:, None, :], C, axis=1))).cuda()
+    a = gcode.decode(x, msg="fp32", max_iter=12, weights=w1, weight_classes=1)
+    b = gcode.decode(x, msg="fp32", max_iter=12, weights=wc)
+    gcode.close()
+    for k in ("hard", "llr", "iters", "ok"):
+        np.testing.assert_array_equal(a[k].cpu().numpy(), b[k].cpu().numpy(), err_msg=k)
