@@ -65,9 +65,11 @@ typedef enum {
                                    frame (single-scan INT8/1BIT; codes with an instantiated
                                    shape, see ldpc_code_info.reg_* / pk_*); INT8 and 1BIT
                                    use the packed two-rows-per-lane kernel when it has a
-                                   shape.  AUTO picks, for fixed point: the packed kernel
-                                   from 16 rows per thread (M > 8192), the one-row register
-                                   kernel below that, LDS-resident kernels for M <= 1024.
+                                   shape (1BIT up to 8 slots per row).  AUTO picks, for
+                                   fixed point: the packed kernel from 16 rows per thread
+                                   (M > 8192) or for rows wider than 8 slots (INT8), the
+                                   one-row register kernel otherwise, LDS-resident kernels
+                                   for M <= 1024.
                                    AUTO prefers this layout */
 #define LDPC_LAYOUT_REG1 4      /* as LDPC_LAYOUT_REG, one row at a time (no packing) */
 #define LDPC_LAYOUT_FRAMES 5    /* single-scan FP32 and the two-scan baseline (INT8, FP32):
@@ -143,8 +145,10 @@ typedef struct {
     int32_t reg_slots;          /* register-resident shape: slots per row (0 = none) */
     int32_t reg_rows_per_thread;
     int32_t reg_zpack;          /* posterior accumulator fields per 32-bit LDS word */
-    int32_t pk_slots;           /* packed (two rows per lane) INT8 shape: slots per row (0 = none) */
+    int32_t pk_slots;           /* packed (two rows per lane) shape: slots per row (0 = none);
+                                   1BIT only when pk_slots <= 8 */
     int32_t pk_rows_per_thread;
+    int32_t pk_threads;         /* threads per workgroup (one frame) of the packed kernel */
 } ldpc_code_info;
 
 /*

@@ -92,15 +92,17 @@ ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl)
     if (qmax != kQmax6 && reg_layout)
         return fail(LDPC_EUNSUPPORTED, "7-8 bit messages run on the LDS/HBM kernel only");
     // AUTO for fixed point (measured on MI355X, 50 iterations): the packed
-    // two-rows-per-lane kernel pays off from 16 rows per thread (M > 8192);
-    // below that the one-row register kernel is faster, and codes of at most
-    // 1024 checks run best LDS-resident with one thread per row (the register
-    // kernels give every frame 1024 threads).
+    // two-rows-per-lane kernel pays off from 16 rows per thread (M > 8192) and
+    // for rows wider than 8 slots (int8 only); otherwise the one-row register
+    // kernel is faster, and codes of at most 1024 checks run best LDS-resident
+    // with one thread per row (the register kernels give every frame 1024
+    // threads).
     const bool small_auto = layout == LDPC_LAYOUT_AUTO && c->M <= 1024;
     if (p->sched == LDPC_SINGLE_SCAN && p->msg != LDPC_MSG_FP32 && !small_auto && qmax == kQmax6 &&
         (layout == LDPC_LAYOUT_AUTO || reg_layout)) {
         const bool packed = c->pkD > 0 && layout != LDPC_LAYOUT_REG1 &&
-                            (layout == LDPC_LAYOUT_REG || c->pkR >= 16);  // int8 and 1-bit
+                            (p->msg == LDPC_MSG_INT8 || c->pkD <= 8) &&  // 1-bit: 8 slots per half
+                            (layout == LDPC_LAYOUT_REG || c->pkR >= 16 || c->pkD > 8);
         const bool ok = packed || (c->regD > 0 && (p->msg == LDPC_MSG_INT8 || c->regD + 15 <= 32));
         if (ok) {
             pl->family = packed ? 4 : 3;
@@ -112,7 +114,7 @@ ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl)
             pl->off_zacc = (uint32_t)zold;
             pl->off_aux = (uint32_t)(zold + zacc);
             pl->cfg.lds = zold + zacc + aux;
-            pl->cfg.threads = ldpc::kRegThreads;
+            pl->cfg.threads = packed ? c->pkT : ldpc::kRegThreads;
             pl->ws_stride = 0;
             return LDPC_OK;
         }
@@ -242,8 +244,8 @@ __global__ void zero_word_kernel(int32_t *p) { *p = 0; }
 // are least used by the half-wavefronts that will touch it, so each half's 32
 // gathers and 32 atomics spread over the banks.
 std::vector<uint32_t> pk_slot_assignment(int M, int N, const int32_t *row_ptr, const int32_t *col_idx,
-                                         int pkD, int pkR, int P, uint32_t zacc_off) {
-    const int T = ldpc::kRegThreads, RP = pkR / 2, nwave = T / 32;  // half-wavefront groups
+                                         int pkD, int pkR, int T, int P, uint32_t zacc_off) {
+    const int RP = pkR / 2, nwave = T / 32;  // half-wavefront groups
     const int ngroups = RP * 2 * pkD * nwave;
     std::vector<int32_t> gptr((size_t)N + 1, 0);
     auto each_edge = [&](auto &&fn) {
@@ -438,18 +440,19 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
             c->regP = bestP;
             // packed kernel: any instantiated (slots, even rows/thread) covering the
             // code; its accumulator addressing comes from the per-edge records
-            int pks[2 * 64], pcnt = 0;
+            int pks[3 * 64], pcnt = 0;
             ldpc::pk_shapes(pks, 64, &pcnt);
-            int pD = 1 << 30, pR = 1 << 30;
+            int pD = 1 << 30, pR = 1 << 30, pT = 0;
             // it also keeps 64 private accumulator words for padding slots
             const size_t need_pk = align_up((size_t)c->dummy + 1, 16) +
                                    align_up(4 * ((size_t)c->dummy / bestP + 1 + 64), 16) + 16;
             for (int i = 0; i < pcnt && i < 64 && need_pk <= (size_t)lds_dev; ++i) {
-                const int d = pks[2 * i], r = pks[2 * i + 1];
-                if (d < D || (int64_t)r * ldpc::kRegThreads < M) continue;
+                const int d = pks[3 * i], r = pks[3 * i + 1], t = pks[3 * i + 2];
+                if (d < D || (int64_t)r * t < M) continue;
                 if (d < pD || (d == pD && r < pR)) {
                     pD = d;
                     pR = r;
+                    pT = t;
                 }
             }
             // 10-bit fields are biased by 320 or 576 (both 64 mod 256: the low
@@ -458,6 +461,7 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
             if (pD < (1 << 30) && pbias >= 0) {
                 c->pkD = pD;
                 c->pkR = pR;
+                c->pkT = pT;
                 c->pkBias = pbias;
             }
         }
@@ -498,14 +502,14 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
     std::vector<uint32_t> pk_idx, pk_slot;
     hipError_t e5 = hipSuccess, e6 = hipSuccess;
     if (c->pkD > 0) {
-        // record {zold_a, zold_b, acc_a, acc_b} of slot j of rows a = p*1024 + t,
-        // b = (p + R/2)*1024 + t: LDS byte address of the saturated posterior and
-        // (LDS byte address of the accumulator word << 5) | field shift
-        const int T = ldpc::kRegThreads, RP = c->pkR / 2, Dk = c->pkD, Pk = c->regP;
+        // record {zold_a, zold_b, acc_a, acc_b} of slot j of rows a = p*T + t,
+        // b = (p + R/2)*T + t (T threads): LDS byte address of the saturated
+        // posterior and (LDS byte address of the accumulator word << 5) | field shift
+        const int T = c->pkT, RP = c->pkR / 2, Dk = c->pkD, Pk = c->regP;
         const int fbits = Pk == 1 ? 32 : (Pk == 2 ? 16 : 10);
         const uint32_t zacc_off = (uint32_t)align_up((size_t)c->dummy + 1, 16);
         const uint32_t nwords = (uint32_t)c->dummy / (uint32_t)Pk + 1;
-        pk_slot = pk_slot_assignment(M, N, row_ptr, col_idx, Dk, c->pkR, Pk, zacc_off);
+        pk_slot = pk_slot_assignment(M, N, row_ptr, col_idx, Dk, c->pkR, T, Pk, zacc_off);
         pk_idx.assign((size_t)RP * Dk * T * 4, 0u);
         auto acc_of_slot = [&](uint32_t sl) -> uint32_t {
             const uint32_t w = sl / (uint32_t)Pk, fld = sl % (uint32_t)Pk;
@@ -605,6 +609,7 @@ ldpc_status ldpc_code_query(const ldpc_code *c, ldpc_code_info *o) {
     o->reg_zpack = c->regP;
     o->pk_slots = c->pkD;
     o->pk_rows_per_thread = c->pkR;
+    o->pk_threads = c->pkT;
     return LDPC_OK;
 }
 
@@ -727,7 +732,7 @@ ldpc_status decode_job(const ldpc_code *c, int32_t n_frames, const void *llr_in,
     else if (pl.family == 3)
         e = ldpc::launch_ss_reg(a, p->msg, c->regD, c->regR, c->regP, pl.cfg.lds, s);
     else if (pl.family == 4)
-        e = ldpc::launch_ss_pk(a, c->pkD, c->pkR, p->msg == LDPC_MSG_1BIT, pl.cfg.lds, s);
+        e = ldpc::launch_ss_pk(a, c->pkD, c->pkR, c->pkT, p->msg == LDPC_MSG_1BIT, pl.cfg.lds, s);
     else if (pl.family == 1)
         e = ldpc::launch_ss_f32(a, pl.cfg, s);
     else if (pl.family == 6)

@@ -44,7 +44,6 @@
 namespace ldpc {
 namespace {
 
-constexpr int kT = kRegThreads;
 constexpr uint32_t kRsrcWord3 = 0x00020000u;  // raw buffer, gfx9 family
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
@@ -72,9 +71,10 @@ __device__ __forceinline__ uint32_t pair_of(uint32_t w, int s) {
     return __builtin_amdgcn_perm(w, w, s == 0 ? 0x0c010c00u : 0x0c030c02u);
 }
 
-template <int D, int R, bool ONEBIT, bool FUSED>
-__global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
+template <int D, int R, bool ONEBIT, bool FUSED, int T>
+__global__ void __launch_bounds__(T) ss_pk_kernel(DecodeArgs a) {
     static_assert(!ONEBIT || D <= 8, "1-bit state keeps 8 slots per 16-bit half");
+    constexpr int kT = T;  // threads per workgroup (one frame)
     static_assert(R % 2 == 0, "rows are processed in pairs");
     constexpr int RP = R / 2;        // row pairs per thread
     constexpr int W = (D + 1) / 2;   // registers per row pair: two slots (4 bytes) each
@@ -373,37 +373,43 @@ __global__ void __launch_bounds__(kT) ss_pk_kernel(DecodeArgs a) {
     }
 }
 
-template <int D, int R, bool ONEBIT, bool FUSED>
+template <int D, int R, bool ONEBIT, bool FUSED, int T>
 hipError_t launch_one(const DecodeArgs &a, size_t lds, hipStream_t s) {
-    auto kern = ss_pk_kernel<D, R, ONEBIT, FUSED>;
+    auto kern = ss_pk_kernel<D, R, ONEBIT, FUSED, T>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kern, dim3((unsigned)a.n_frames), dim3(kT), lds, s, a);
+    hipLaunchKernelGGL(kern, dim3((unsigned)a.n_frames), dim3(T), lds, s, a);
     return hipGetLastError();
 }
 
 }  // namespace
 
-// Instantiated (slots per row, rows per thread) shapes of the packed kernel.
+// Instantiated (slots per row, rows per thread, threads) shapes of the packed
+// kernel.  Rows of up to 8 slots run 1024 threads (int8 and 1-bit); wider rows
+// (int8 only: the 1-bit state keeps 8 slots per half) keep 6 D registers per
+// row pair live, so they run 768 threads, whose 3 waves per SIMD leave each
+// wave up to 168 VGPRs.
 #define LDPC_PK_SHAPES(X) \
-    X(6, 2)               \
-    X(6, 4)               \
-    X(7, 8)               \
-    X(7, 16)              \
-    X(7, 32)              \
-    X(8, 8)               \
-    X(8, 16)              \
-    X(8, 32)
+    X(6, 2, 1024)         \
+    X(6, 4, 1024)         \
+    X(7, 8, 1024)         \
+    X(7, 16, 1024)        \
+    X(7, 32, 1024)        \
+    X(8, 8, 1024)         \
+    X(8, 16, 1024)        \
+    X(8, 32, 1024)        \
+    X(21, 4, 768)
 
 void pk_shapes(int *out, int cap, int *count) {
     int i = 0;
-#define X(d, r)              \
+#define X(d, r, t)           \
     if (i < cap) {           \
-        out[2 * i] = d;      \
-        out[2 * i + 1] = r;  \
+        out[3 * i] = d;      \
+        out[3 * i + 1] = r;  \
+        out[3 * i + 2] = t;  \
     }                        \
     ++i;
     LDPC_PK_SHAPES(X)
@@ -411,15 +417,24 @@ void pk_shapes(int *out, int cap, int *count) {
     *count = i;
 }
 
-hipError_t launch_ss_pk(const DecodeArgs &a, int D, int R, bool onebit, size_t lds, hipStream_t s) {
+namespace {
+template <int D, int R, int T>
+hipError_t launch_shape(const DecodeArgs &a, bool onebit, size_t lds, hipStream_t s) {
     // the fused check needs at least one iteration and no posterior output
     const bool fused = a.early_stop && a.llr_out == nullptr && a.max_iter >= 1;
-#define X(d, r)                                                                                         \
-    if (D == d && R == r) {                                                                             \
-        if (fused)                                                                                      \
-            return onebit ? launch_one<d, r, true, true>(a, lds, s) : launch_one<d, r, false, true>(a, lds, s); \
-        return onebit ? launch_one<d, r, true, false>(a, lds, s) : launch_one<d, r, false, false>(a, lds, s);   \
+    if constexpr (D <= 8) {
+        if (onebit)
+            return fused ? launch_one<D, R, true, true, T>(a, lds, s) : launch_one<D, R, true, false, T>(a, lds, s);
+    } else {
+        if (onebit) return hipErrorInvalidValue;
     }
+    return fused ? launch_one<D, R, false, true, T>(a, lds, s) : launch_one<D, R, false, false, T>(a, lds, s);
+}
+}  // namespace
+
+hipError_t launch_ss_pk(const DecodeArgs &a, int D, int R, int T, bool onebit, size_t lds, hipStream_t s) {
+#define X(d, r, t) \
+    if (D == d && R == r && T == t) return launch_shape<d, r, t>(a, onebit, lds, s);
     LDPC_PK_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;

@@ -67,7 +67,8 @@ class CodeInfo(ctypes.Structure):
                 ("msg_bits_int8", ctypes.c_int64), ("msg_bits_1bit", ctypes.c_int64),
                 ("lds_bytes_per_cu", ctypes.c_int32), ("reg_slots", ctypes.c_int32),
                 ("reg_rows_per_thread", ctypes.c_int32), ("reg_zpack", ctypes.c_int32),
-                ("pk_slots", ctypes.c_int32), ("pk_rows_per_thread", ctypes.c_int32)]
+                ("pk_slots", ctypes.c_int32), ("pk_rows_per_thread", ctypes.c_int32),
+                ("pk_threads", ctypes.c_int32)]
 
 
 class Job(ctypes.Structure):

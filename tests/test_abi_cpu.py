@@ -151,7 +151,10 @@ def test_workspace_plans(L):
     big = L.Code.from_parity_check(W.code_c2_ira64800(), device=-1)
     info = big.info()
     assert (info["reg_slots"], info["reg_rows_per_thread"], info["reg_zpack"]) == (7, 32, 3)
-    assert (info["pk_slots"], info["pk_rows_per_thread"]) == (7, 32)
+    assert (info["pk_slots"], info["pk_rows_per_thread"], info["pk_threads"]) == (7, 32, 1024)
+    # rows of up to 21 slots: the wide packed shape (int8 only), 768 threads
+    qc = L.Code.from_parity_check(W.code_c1_qc7493(), device=-1).info()
+    assert (qc["pk_slots"], qc["pk_rows_per_thread"], qc["pk_threads"]) == (21, 4, 768)
     for msg in ("int8", "1bit"):
         assert big.workspace_size(4, L.make_params(msg=msg)) == 0
         assert big.workspace_size(4, L.make_params(msg=msg, layout="reg")) == 0

@@ -157,7 +157,7 @@ def test_ira16200(torch_dev, L, orc, variant, layout):
               layout=layout)
 
 
-@pytest.mark.parametrize("variant,layout", [(VARIANTS[0], "auto"), (VARIANTS[0], "lds"),
+@pytest.mark.parametrize("variant,layout", [(VARIANTS[0], "auto"), (VARIANTS[0], "reg1"), (VARIANTS[0], "lds"),
                                             (VARIANTS[0], "hbm"), (VARIANTS[1], "lds"),
                                             (VARIANTS[3], "auto"), (VARIANTS[2], "auto")],
                          ids=lambda v: v if isinstance(v, str) else f"{v[0]}-{v[1]}")
@@ -217,15 +217,16 @@ def test_frames_layout(torch_dev, L, orc, case, fp):
 def test_register_path_selected(torch_dev, L):
     """The fixed-point single-scan path of every workload code runs on a
     register-resident kernel (shapes chosen at create time); int8 on the
-    packed two-rows-per-lane kernel where it has a shape."""
-    for code, shape, pk in ((W.code_c0_peg1008(), (6, 1, 1), (6, 2)),
-                            (W.code_ira16200(), (7, 8, 1), (7, 8)),
-                            (W.code_c1_qc7493(), (21, 3, 1), (0, 0)),
-                            (W.code_c2_ira64800(), (7, 32, 3), (7, 32))):
+    packed two-rows-per-lane kernel where it has a shape (768 threads for
+    the QC code's rows of up to 21 slots)."""
+    for code, shape, pk in ((W.code_c0_peg1008(), (6, 1, 1), (6, 2, 1024)),
+                            (W.code_ira16200(), (7, 8, 1), (7, 8, 1024)),
+                            (W.code_c1_qc7493(), (21, 3, 1), (21, 4, 768)),
+                            (W.code_c2_ira64800(), (7, 32, 3), (7, 32, 1024))):
         gc = L.Code.from_parity_check(code)
         i = gc.info()
         assert (i["reg_slots"], i["reg_rows_per_thread"], i["reg_zpack"]) == shape, code.name
-        assert (i["pk_slots"], i["pk_rows_per_thread"]) == pk, code.name
+        assert (i["pk_slots"], i["pk_rows_per_thread"], i["pk_threads"]) == pk, code.name
         gc.close()
 
 
