@@ -92,17 +92,19 @@ ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl)
     if (qmax != kQmax6 && reg_layout)
         return fail(LDPC_EUNSUPPORTED, "7-8 bit messages run on the LDS/HBM kernel only");
     // AUTO for fixed point (measured on MI355X, 50 iterations): the packed
-    // two-rows-per-lane kernel pays off from 16 rows per thread (M > 8192) and
-    // for rows wider than 8 slots (int8 only); otherwise the one-row register
-    // kernel is faster, and codes of at most 1024 checks run best LDS-resident
-    // with one thread per row (the register kernels give every frame 1024
-    // threads).
-    const bool small_auto = layout == LDPC_LAYOUT_AUTO && c->M <= 1024;
+    // two-rows-per-lane kernel pays off from 16 rows per thread (M > 8192),
+    // for rows wider than 8 slots (int8 only) and with its 256-thread shapes
+    // for small codes; otherwise the one-row register kernel is faster, and
+    // other codes of at most 1024 checks run best LDS-resident with one thread
+    // per row (the register kernels give every frame 1024 threads).
+    const bool small_pk = c->pkD > 0 && c->pkT <= 256;  // packed shape with small workgroups
+    const bool wide_pk = c->pkD > 8 && 5 * c->D >= 4 * c->pkD;  // wide rows filling >= 80% of the slots
+    const bool small_auto = layout == LDPC_LAYOUT_AUTO && c->M <= 1024 && !small_pk;
     if (p->sched == LDPC_SINGLE_SCAN && p->msg != LDPC_MSG_FP32 && !small_auto && qmax == kQmax6 &&
         (layout == LDPC_LAYOUT_AUTO || reg_layout)) {
         const bool packed = c->pkD > 0 && layout != LDPC_LAYOUT_REG1 &&
                             (p->msg == LDPC_MSG_INT8 || c->pkD <= 8) &&  // 1-bit: 8 slots per half
-                            (layout == LDPC_LAYOUT_REG || c->pkR >= 16 || c->pkD > 8);
+                            (layout == LDPC_LAYOUT_REG || c->pkR >= 16 || wide_pk || small_pk);
         const bool ok = packed || (c->regD > 0 && (p->msg == LDPC_MSG_INT8 || c->regD + 15 <= 32));
         if (ok) {
             pl->family = packed ? 4 : 3;
@@ -449,7 +451,9 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
             for (int i = 0; i < pcnt && i < 64 && need_pk <= (size_t)lds_dev; ++i) {
                 const int d = pks[3 * i], r = pks[3 * i + 1], t = pks[3 * i + 2];
                 if (d < D || (int64_t)r * t < M) continue;
-                if (d < pD || (d == pD && r < pR)) {
+                // fewest slots, then fewest padded rows, then fewest rows per thread
+                if (d < pD || (d == pD && (int64_t)r * t < (int64_t)pR * pT) ||
+                    (d == pD && (int64_t)r * t == (int64_t)pR * pT && r < pR)) {
                     pD = d;
                     pR = r;
                     pT = t;

@@ -388,11 +388,15 @@ hipError_t launch_one(const DecodeArgs &a, size_t lds, hipStream_t s) {
 }  // namespace
 
 // Instantiated (slots per row, rows per thread, threads) shapes of the packed
-// kernel.  Rows of up to 8 slots run 1024 threads (int8 and 1-bit); wider rows
-// (int8 only: the 1-bit state keeps 8 slots per half) keep 6 D registers per
-// row pair live, so they run 768 threads, whose 3 waves per SIMD leave each
-// wave up to 168 VGPRs.
+// kernel.  Rows of up to 8 slots run 1024 threads (int8 and 1-bit), or 256 for
+// codes of at most 512 / 1024 checks, so that a CU holds several frames; wider
+// rows (int8 only: the 1-bit state keeps 8 slots per half) keep 6 D registers
+// per row pair live, so they run 768 threads, whose 3 waves per SIMD leave
+// each wave up to 168 VGPRs.
 #define LDPC_PK_SHAPES(X) \
+    X(6, 2, 256)          \
+    X(8, 2, 256)          \
+    X(8, 4, 256)          \
     X(6, 2, 1024)         \
     X(6, 4, 1024)         \
     X(7, 8, 1024)         \

@@ -217,9 +217,10 @@ def test_frames_layout(torch_dev, L, orc, case, fp):
 def test_register_path_selected(torch_dev, L):
     """The fixed-point single-scan path of every workload code runs on a
     register-resident kernel (shapes chosen at create time); int8 on the
-    packed two-rows-per-lane kernel where it has a shape (768 threads for
-    the QC code's rows of up to 21 slots)."""
-    for code, shape, pk in ((W.code_c0_peg1008(), (6, 1, 1), (6, 2, 1024)),
+    packed two-rows-per-lane kernel where it has a shape (256 threads for
+    the 504 rows of the PEG code, 768 for the QC code's rows of up to 21
+    slots)."""
+    for code, shape, pk in ((W.code_c0_peg1008(), (6, 1, 1), (6, 2, 256)),
                             (W.code_ira16200(), (7, 8, 1), (7, 8, 1024)),
                             (W.code_c1_qc7493(), (21, 3, 1), (21, 4, 768)),
                             (W.code_c2_ira64800(), (7, 32, 3), (7, 32, 1024))):
