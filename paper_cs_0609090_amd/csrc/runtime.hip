@@ -105,7 +105,7 @@ ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl)
         const bool packed = c->pkD > 0 && layout != LDPC_LAYOUT_REG1 &&
                             (p->msg == LDPC_MSG_INT8 || c->pkD <= 8) &&  // 1-bit: 8 slots per half
                             (layout == LDPC_LAYOUT_REG || c->pkR >= 16 || wide_pk || small_pk);
-        const bool ok = packed || (c->regD > 0 && (p->msg == LDPC_MSG_INT8 || c->regD + 15 <= 32));
+        const bool ok = packed || c->regD > 0;
         if (ok) {
             pl->family = packed ? 4 : 3;
             const size_t zold = align_up(nz, 16);

@@ -4,7 +4,8 @@
 // their messages in VGPRs:
 //   INT8  D int8 messages per row, four to a register;
 //   1BIT  one register per row: D sign bits, then A, B (5 bits each) and the
-//         argmin position n~ (5 bits): the compressed state of Sec. V.
+//         argmin position n~ (5 bits): the compressed state of Sec. V (rows of
+//         more than 17 slots: the signs in one register, A | B | n~ in another).
 // The only per-edge memory traffic is the shared check-to-variable index
 // (buffer loads from L2) plus two LDS operations: the gather of the saturated
 // posterior and, when the message changed, the atomic add of L_new - L_old
@@ -86,8 +87,8 @@ __device__ __forceinline__ uint32_t ld_idx(__amdgpu_buffer_rsrc_t r, uint32_t vo
 template <int D, int R, int P, int MSG, bool FUSED>
 __global__ void __launch_bounds__(kT) ss_reg_kernel(DecodeArgs a) {
     static_assert(D >= 2 && D <= 32, "slots per row");
-    static_assert(MSG == MSG_INT8 || D + 15 <= 32, "1-bit state must fit one register");
-    constexpr int W = (D + 3) / 4;
+    constexpr bool kWide1 = MSG == MSG_1BIT && D + 15 > 32;  // 1-bit state in two registers
+    constexpr int W = MSG == MSG_INT8 ? (D + 3) / 4 : (kWide1 ? 2 : 1);
     constexpr int Mr = R * kT;
     extern __shared__ __align__(16) uint8_t lds[];
     const int tid = threadIdx.x;
@@ -173,13 +174,18 @@ __global__ void __launch_bounds__(kT) ss_reg_kernel(DecodeArgs a) {
                 for (int j = 0; j < D; ++j) nn[j] = ld_idx(ellr, tid4, it0 + (uint32_t)((j * Mr + (k + 1) * kT) * 4));
             }
             __builtin_amdgcn_sched_barrier(0);
-            if (MSG == MSG_INT8) {
+            if constexpr (MSG == MSG_INT8) {
 #pragma unroll
                 for (int j = 0; j < D; ++j) lo[j] = (int)(int8_t)(Lw[k][j >> 2] >> (8 * (j & 3)));
             } else {
                 const uint32_t s = Lw[k][0];
-                const int Ao = (int)((s >> D) & 31u), Bo = (int)((s >> (D + 5)) & 31u);
-                const int Io = (int)((s >> (D + 10)) & 31u);
+                uint32_t fs;  // A | B << 5 | n~ << 10
+                if constexpr (kWide1)
+                    fs = Lw[k][1];
+                else
+                    fs = s >> D;
+                const int Ao = (int)(fs & 31u), Bo = (int)((fs >> 5) & 31u);
+                const int Io = (int)((fs >> 10) & 31u);
 #pragma unroll
                 for (int j = 0; j < D; ++j) {
                     const int fv = (j == Io) ? Bo : Ao;
@@ -223,13 +229,16 @@ __global__ void __launch_bounds__(kT) ss_reg_kernel(DecodeArgs a) {
                     atomicAdd(reinterpret_cast<uint32_t *>(zacc_b + addr), (uint32_t)delta << sh);
                 }
             }
-            if (MSG == MSG_INT8) {
+            if constexpr (MSG == MSG_INT8) {
 #pragma unroll
                 for (int i = 0; i < W; ++i) {
                     const int j = 4 * i;
                     Lw[k][i] = pack4(ln[j], j + 1 < D ? ln[j + 1] : 0, j + 2 < D ? ln[j + 2] : 0,
                                      j + 3 < D ? ln[j + 3] : 0);
                 }
+            } else if constexpr (kWide1) {
+                Lw[k][0] = sbits;
+                Lw[k][1] = (uint32_t)A | ((uint32_t)B << 5) | ((uint32_t)idx << 10);
             } else {
                 Lw[k][0] = sbits | ((uint32_t)A << D) | ((uint32_t)B << (D + 5)) | ((uint32_t)idx << (D + 10));
             }
@@ -366,8 +375,7 @@ hipError_t launch_ss_reg(const DecodeArgs &a, int msg, int D, int R, int P, size
 #define X(d, r, p)                                                                         \
     if (D == d && R == r && P == p) {                                                      \
         if (msg == MSG_INT8) return launch_es<d, r, p, MSG_INT8>(a, lds, s);               \
-        if (d + 15 <= 32) return launch_es<d, r, p, (d + 15 <= 32 ? MSG_1BIT : MSG_INT8)>(a, lds, s); \
-        return hipErrorInvalidValue;                                                       \
+        return launch_es<d, r, p, MSG_1BIT>(a, lds, s);                                    \
     }
     LDPC_REG_SHAPES(X)
 #undef X

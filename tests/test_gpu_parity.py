@@ -158,7 +158,7 @@ def test_ira16200(torch_dev, L, orc, variant, layout):
 
 
 @pytest.mark.parametrize("variant,layout", [(VARIANTS[0], "auto"), (VARIANTS[0], "reg1"), (VARIANTS[0], "lds"),
-                                            (VARIANTS[0], "hbm"), (VARIANTS[1], "lds"),
+                                            (VARIANTS[0], "hbm"), (VARIANTS[1], "lds"), (VARIANTS[1], "auto"),
                                             (VARIANTS[3], "auto"), (VARIANTS[2], "auto")],
                          ids=lambda v: v if isinstance(v, str) else f"{v[0]}-{v[1]}")
 def test_qc7493_batch_sampled(torch_dev, L, orc, variant, layout):

@@ -60,7 +60,7 @@ def _run(torch, L, orc, code, x, msg, layout, early_stop, with_llr, step, sched=
 SCHED_CASES = [("peg1008", "int8", "auto"), ("peg1008", "1bit", "auto"), ("peg1008", "int8", "hbm"),
                ("peg1008", "int8", "reg1"), ("peg1008", "1bit", "reg1"), ("ira16200", "int8", "reg"),
                ("ira16200", "1bit", "reg"), ("ira16200", "int8", "reg1"), ("ira16200", "1bit", "reg1"),
-               ("qc7493", "int8", "auto")]
+               ("qc7493", "int8", "auto"), ("qc7493", "1bit", "auto")]
 
 
 @pytest.mark.parametrize("early_stop,with_llr", [(False, True), (True, True), (True, False)])
