@@ -46,7 +46,7 @@ ALG_OPS_PER_ROW = 10
 # reports traffic as null.
 MEASURED_TRAFFIC = {
     "ss_pk.hip": {
-        "e23557d44a6158ef": {"bytes": 235.7e6, "workload": ("int8", 512, 50),
+        "2a1efeec3fb0d520": {"bytes": 235.7e6, "workload": ("int8", 512, 50),
                              "profile": "profiles/ss_pk_int8_ira64800_512f.md"},
     },
     "ss_reg.hip": {
