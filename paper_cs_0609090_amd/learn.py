@@ -11,6 +11,8 @@ frame); ``evaluate`` decodes fresh frames with the trained pairs through
 frames, and reports FER and average iterations.
 
     python -m paper_cs_0609090_amd.learn --code peg1008 --T 20 --steps 1024
+    python -m paper_cs_0609090_amd.learn --code qc7493 --ebn0-lo 2.75 --ebn0-hi 3.75 --init-alpha 0.6 \
+        --lr 0.02 --eval-ebn0 3.0 3.25 3.5 --eval-frames 20000 --nms-alpha 0.8 0.5
 """
 from __future__ import annotations
 
@@ -147,6 +149,8 @@ def main(argv=None):
     ap.add_argument("--ebn0-hi", type=float, default=2.5)
     ap.add_argument("--learned-iters", type=int, default=None,
                     help="iteration cap of the learned decoder at evaluation (default: NMS's 50)")
+    ap.add_argument("--nms-alpha", type=float, nargs="+", default=[0.8],
+                    help="constant normalisations the learned decoder is compared with")
     args = ap.parse_args(argv)
     code = FER.CODES[args.code]()
     gcode = ldpc.Code.from_parity_check(code)
@@ -159,7 +163,9 @@ def main(argv=None):
     print(json.dumps({"weights": w.cpu().numpy().round(4).tolist(),
                       "classes": gcode.degree_classes().tolist()}), flush=True)
     for e in args.eval_ebn0:
-        print(json.dumps(evaluate(gcode, w, e, args.eval_frames, learned_iters=args.learned_iters)), flush=True)
+        for na in args.nms_alpha:
+            print(json.dumps(evaluate(gcode, w, e, args.eval_frames, nms_alpha=na, learned_iters=args.learned_iters)),
+                  flush=True)
     gcode.close()
 
 
