@@ -120,9 +120,13 @@ __global__ void __launch_bounds__(T) ss_pk_kernel(DecodeArgs a) {
 
     // Message state of each row pair.
     //   int8:  Lw[p][i], bytes 2s / 2s+1: slot 2i+s of rows a / b, as L + 64.
-    //   1-bit (Sec. V): St[p] bit j / 16+j: sign of slot j's message in row
-    //          a / b; bit 8+j / 24+j: slot j held the row minimum, so its
-    //          magnitude is B (A elsewhere); Ab[p] bytes: A_a, B_a, A_b, B_b.
+    //   1-bit (Sec. V): St[p] bit j / 16+j: sign of slot j's own extrinsic
+    //          t in row a / b; bit 8+j / 24+j: slot j held the row minimum, so
+    //          its magnitude is B (A elsewhere); Ab[p] bytes: A_a, B_a, A_b,
+    //          B_b, signed by the row's sign parity.  A message is then the
+    //          stored sign times the signed A or B, exactly the Sec. V message
+    //          s_mn f(A, B): the row parity moves from every per-edge sign bit
+    //          into the per-row A and B (s_mn = own sign XOR parity).
     uint32_t Lw[RP][ONEBIT ? 1 : W];
     uint32_t St[RP], Ab[RP];
 #pragma unroll
@@ -160,10 +164,10 @@ __global__ void __launch_bounds__(T) ss_pk_kernel(DecodeArgs a) {
             uint32_t acc_a[D], acc_b[D], t2[D], lo2[D], mg2[D], h2[D];
             u16x2 min1 = {0xFFFF, 0xFFFF}, min2 = {0xFFFF, 0xFFFF};
             uint32_t Sp = 0, Aold = 0, Bold = 0;
-            if (ONEBIT) {
+            if (ONEBIT) {  // signed bytes to 16-bit halves
                 Sp = St[p];
-                Aold = Ab[p] & 0x00FF00FFu;
-                Bold = (Ab[p] >> 8) & 0x00FF00FFu;
+                Aold = bits(as_i(bits(as_u(Ab[p]) << (u16x2){8, 8})) >> (i16x2){8, 8});
+                Bold = bits(as_i(Ab[p] & 0xFF00FF00u) >> (i16x2){8, 8});
             }
 #pragma unroll
             for (int j = 0; j < D; ++j) {
@@ -237,15 +241,11 @@ __global__ void __launch_bounds__(T) ss_pk_kernel(DecodeArgs a) {
                 // own sign +-1, then L_new + 64 in one multiply-add
                 const i16x2 sg = (as_i(t2[j]) >> (i16x2){15, 15}) | (i16x2){1, 1};
                 i16x2 lb;
-                if (ONEBIT) {
-                    // keep the sign bit and the minimum flag of the new message
-                    const i16x2 lnew = as_i(mag) * sg;
-                    lb = lnew + (i16x2){64, 64};
-                    const uint32_t sneg = bits(lnew >> (i16x2){15, 15});
+                lb = as_i(mag) * sg + (i16x2){64, 64};
+                if (ONEBIT) {  // keep the own-extrinsic sign and the minimum flag
+                    const uint32_t sneg = bits(as_i(t2[j]) >> (i16x2){15, 15});
                     Sn = __builtin_amdgcn_bitop3_b32(sneg, 0x00010001u << j, Sn, 0xEA);  // (a & b) | c
                     Sn = __builtin_amdgcn_bitop3_b32(nsel, 0x01000100u << j, Sn, 0xAE);  // (~a & b) | c
-                } else {
-                    lb = as_i(mag) * sg + (i16x2){64, 64};
                 }
                 nl[j] = bits(lb);
                 const uint32_t d = bits(lb - as_i(lo2[j]));
@@ -256,7 +256,7 @@ __global__ void __launch_bounds__(T) ss_pk_kernel(DecodeArgs a) {
             }
             if (ONEBIT) {
                 St[p] = Sn;
-                Ab[p] = __builtin_amdgcn_perm(bits(Bm), bits(Am), 0x06020400u);
+                Ab[p] = __builtin_amdgcn_perm(B2, A2, 0x06020400u);  // low bytes of the signed halves
                 asm volatile("" : "+v"(St[p]), "+v"(Ab[p]));
             } else {
 #pragma unroll
