@@ -61,16 +61,16 @@ typedef enum {
 #define LDPC_LAYOUT_AUTO 0
 #define LDPC_LAYOUT_LDS 1       /* messages in LDS (must fit) */
 #define LDPC_LAYOUT_HBM 2       /* messages in the caller's workspace (device memory) */
-#define LDPC_LAYOUT_REG 3       /* messages in registers, one workgroup of 1024 threads per
-                                   frame (single-scan INT8/1BIT; codes with an instantiated
-                                   shape, see ldpc_code_info.reg_* / pk_*); INT8 and 1BIT
-                                   use the packed two-rows-per-lane kernel when it has a
-                                   shape (1BIT up to 8 slots per row).  AUTO picks, for
-                                   fixed point: the packed kernel from 16 rows per thread
-                                   (M > 8192) or for rows wider than 8 slots (INT8), the
-                                   one-row register kernel otherwise, LDS-resident kernels
-                                   for M <= 1024.
-                                   AUTO prefers this layout */
+#define LDPC_LAYOUT_REG 3       /* messages in registers, one workgroup per frame (single-scan
+                                   INT8/1BIT; codes with an instantiated shape, see
+                                   ldpc_code_info.reg_* / pk_*); INT8 and 1BIT use the packed
+                                   two-rows-per-lane kernel (pk_threads per workgroup) when it
+                                   has a shape (1BIT up to 8 slots per row), else the one-row
+                                   kernel (1024 threads).  AUTO picks, for fixed point: the
+                                   packed kernel from 16 rows per thread (M > 8192), for rows
+                                   wider than 8 slots (INT8) and with 256-thread shapes for
+                                   small codes; the one-row register kernel otherwise; the
+                                   LDS-resident kernels for the remaining codes with M <= 1024 */
 #define LDPC_LAYOUT_REG1 4      /* as LDPC_LAYOUT_REG, one row at a time (no packing) */
 #define LDPC_LAYOUT_FRAMES 5    /* single-scan FP32 and the two-scan baseline (INT8, FP32):
                                    one frame per lane, 64 frames per wavefront, messages and

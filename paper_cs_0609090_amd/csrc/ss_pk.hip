@@ -4,7 +4,7 @@
 // as ss_reg.hip (Sec. IV, Eq. 3, 6-bit fixed point); only the instruction
 // mapping differs:
 //
-//   thread t owns the rows a = p*1024 + t and b = (p + R/2)*1024 + t for
+//   thread t of T owns the rows a = p*T + t and b = (p + R/2)*T + t for
 //   p < R/2; for every slot j the pair (row a, row b) is one 16-bit lane pair:
 //     t2   = Zold2 - Lold2                  (v_pk_sub_i16; both stored +64)
 //     m2   = |t2|
