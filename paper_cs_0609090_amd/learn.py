@@ -64,14 +64,20 @@ def init_weights(n_classes: int, T: int, alpha: float = 0.8, beta: float = 0.0) 
 
 
 def train(gcode, T: int = 20, steps: int = 1024, batch: int = 1024, ebn0=(1.5, 2.5), lr: float = 0.01,
-          ckpt: int = 5, key=(0x7EA, 1), seed: int = 0, log_every: int = 64, init=(0.8, 0.0)):
-    """Adam on the [T][C][2] pairs; returns (weights, log).  The log holds
-    the training loss and the loss of one fixed validation batch (frames
-    outside the training stream), both per bit and iteration."""
+          ckpt: int = 5, key=(0x7EA, 1), seed: int = 0, log_every: int = 64, init=(0.8, 0.0),
+          tie_classes: bool = False):
+    """Adam on the [T][C][2] pairs; returns (weights [T][C][2], log).  With
+    ``tie_classes`` one pair per iteration is shared by every class (its
+    gradient is the sum of the classes').  The log holds the training loss
+    and the loss of one fixed validation batch (frames outside the training
+    stream), both per bit and iteration."""
     C = len(gcode.degree_classes())
     K = gcode.encoder_info()["K"]
-    w = init_weights(C, T, *init).requires_grad_(True)
-    opt = torch.optim.Adam([w], lr=lr)
+    param = init_weights(1 if tie_classes else C, T, *init).requires_grad_(True)
+    opt = torch.optim.Adam([param], lr=lr)
+
+    def full():
+        return param.expand(T, C, 2) if tie_classes else param
     ws = torch.empty(gcode.learn_workspace_size(batch, T, ckpt), dtype=torch.uint8, device="cuda")
     rng = np.random.default_rng(seed)
     vllr, vcw = _frames(gcode, K, batch, ebn0[0], ebn0[1], key, 1 << 28, np.random.default_rng(seed + 1))
@@ -80,18 +86,18 @@ def train(gcode, T: int = 20, steps: int = 1024, batch: int = 1024, ebn0=(1.5, 2
     t0 = time.time()
     for step in range(steps):
         llr, cw = _frames(gcode, K, batch, ebn0[0], ebn0[1], key, step * batch, rng)
-        loss = LearnedMinSum.apply(w, gcode, llr, cw, ckpt, ws) * scale
+        loss = LearnedMinSum.apply(full(), gcode, llr, cw, ckpt, ws) * scale
         opt.zero_grad()
         loss.backward()
         opt.step()
         with torch.no_grad():
-            w[:, :, 0].clamp_(0.05, 1.5)
-            w[:, :, 1].clamp_(0.0, 4.0)
+            param[:, :, 0].clamp_(0.05, 1.5)
+            param[:, :, 1].clamp_(0.0, 4.0)
         if step % log_every == 0 or step == steps - 1:
             with torch.no_grad():
-                vl = float(gcode.learn_forward(vllr, vcw, w.detach().contiguous(), ckpt, ws).sum()) * scale
+                vl = float(gcode.learn_forward(vllr, vcw, full().detach().contiguous(), ckpt, ws).sum()) * scale
             log.append({"step": step, "loss": float(loss.detach()), "val_loss": vl, "s": time.time() - t0})
-    return w.detach(), log
+    return full().detach().contiguous(), log
 
 
 def evaluate(gcode, weights, ebn0_db: float, frames: int, batch: int = 4096, nms_alpha: float = 0.8,
@@ -151,11 +157,14 @@ def main(argv=None):
                     help="iteration cap of the learned decoder at evaluation (default: NMS's 50)")
     ap.add_argument("--nms-alpha", type=float, nargs="+", default=[0.8],
                     help="constant normalisations the learned decoder is compared with")
+    ap.add_argument("--tie-classes", action="store_true",
+                    help="one pair per iteration shared by all check-degree classes")
     args = ap.parse_args(argv)
     code = FER.CODES[args.code]()
     gcode = ldpc.Code.from_parity_check(code)
     w, log = train(gcode, T=args.T, steps=args.steps, batch=args.batch, lr=args.lr, ckpt=args.ckpt,
-                   ebn0=(args.ebn0_lo, args.ebn0_hi), init=(args.init_alpha, args.init_beta))
+                   ebn0=(args.ebn0_lo, args.ebn0_hi), init=(args.init_alpha, args.init_beta),
+                   tie_classes=args.tie_classes)
     for r in log:
         print(json.dumps({"train": r}), flush=True)
     if args.save:

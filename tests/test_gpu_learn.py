@@ -149,3 +149,19 @@ def test_training_lowers_the_loss(torch_dev, L):
     gc.close()
     assert log[-1]["loss"] < log[0]["loss"]
     assert w.shape == (5, 1, 2) and float(w[:, 0, 0].max()) < 1.0
+
+
+def test_training_with_tied_classes(torch_dev, L):
+    """One pair per iteration shared by every degree class: the returned
+    [T][C][2] pairs are equal across classes and training lowers the loss."""
+    from paper_cs_0609090_amd import learn
+    code = W.random_small_code(40, 90, (3, 9), seed=31)
+    gc = L.Code.from_parity_check(code)
+    C = len(gc.degree_classes())
+    assert C > 1
+    w, log = learn.train(gc, T=4, steps=40, batch=256, lr=0.05, ckpt=2, log_every=39, init=(1.0, 0.0),
+                         ebn0=(2.0, 3.0), tie_classes=True)
+    gc.close()
+    assert w.shape == (4, C, 2)
+    assert bool((w == w[:, :1, :]).all())
+    assert log[-1]["loss"] < log[0]["loss"]
