@@ -55,6 +55,35 @@ struct Buf {
     __device__ void stf_nt(float v, uint32_t lane_off, uint32_t elem_off) const {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, lane_off, elem_off, kNonTemporal);
     }
+    // V = 1 or 4 consecutive floats per lane (V frames); a 16-byte access
+    // moves four times the bytes of a 4-byte one for the same address work.
+    // AUX: cache policy (0, or kNonTemporal for streams).
+    template <int V, int AUX>
+    __device__ void ldv(float (&v)[V], uint32_t lane_off, uint32_t elem_off) const {
+        if constexpr (V == 4) {
+            const auto x = __builtin_amdgcn_raw_buffer_load_b128(r, lane_off, elem_off, AUX);
+            // each component through a scalar: a bit cast of a vector
+            // element expression itself reads element 0 with this compiler
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const uint32_t u = x[c];
+                v[c] = __builtin_bit_cast(float, u);
+            }
+        } else {
+            v[0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, lane_off, elem_off, AUX));
+        }
+    }
+    template <int V, int AUX>
+    __device__ void stv(const float (&v)[V], uint32_t lane_off, uint32_t elem_off) const {
+        if constexpr (V == 4) {
+            typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+            const u32x4 x = {__builtin_bit_cast(uint32_t, v[0]), __builtin_bit_cast(uint32_t, v[1]),
+                             __builtin_bit_cast(uint32_t, v[2]), __builtin_bit_cast(uint32_t, v[3])};
+            __builtin_amdgcn_raw_buffer_store_b128(x, r, lane_off, elem_off, AUX);
+        } else {
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v[0]), r, lane_off, elem_off, AUX);
+        }
+    }
     __device__ int ld8(uint32_t lane_off, uint32_t elem_off) const {  // signed byte
         return (int)(int8_t)__builtin_amdgcn_raw_buffer_load_b8(r, lane_off, elem_off, 0);
     }
