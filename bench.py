@@ -40,20 +40,33 @@ ALU16_PEAK_TOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 ALG_OPS_PER_EDGE = 10
 ALG_OPS_PER_ROW = 10
 
-# HBM bytes per dispatch of the benchmark workload measured with rocprofv3
-# (FETCH_SIZE x 2 + WRITE_SIZE, calibrated on a device copy), keyed by the
-# hash of the kernel source the counters were taken on; any other source
-# reports traffic as null.
-MEASURED_TRAFFIC = {
-    "ss_pk.hip": {
-        "2a1efeec3fb0d520": {"bytes": 235.7e6, "workload": ("int8", 512, 50),
-                             "profile": "profiles/ss_pk_int8_ira64800_512f.md"},
-    },
-    "ss_reg.hip": {
-        "2cb1e30dc64ed9f4": {"bytes": 221.3e6, "workload": ("int8", 512, 50),
-                             "profile": "profiles/ss_reg_int8_ira64800_512f.md"},
-    },
+# The decoding kernel of each plan (ldpc_decode_plan): its source files and
+# the resource that bounds it.  The fixed-point register kernels keep every
+# message on chip (VALU-issue bound); the binary32 and two-scan paths stream
+# their per-edge arrays through HBM every iteration.
+KERNELS = {
+    "packed": (("ss_pk.hip",), "alu"),
+    "reg1": (("ss_reg.hip",), "alu"),
+    "generic_int": (("ss_int.hip",), "alu"),
+    "generic_f32": (("ss_f32.hip",), "hbm"),
+    "two_scan": (("two_scan.hip",), "hbm"),
+    "f32_frames": (("ss_f32_fl.hip", "fl_common.h"), "hbm"),
+    "two_scan_frames": (("two_scan_fl.hip", "fl_common.h"), "hbm"),
 }
+
+# HBM bytes per decode call of the benchmark workload measured with rocprofv3
+# (FETCH_SIZE x 2 + WRITE_SIZE, calibrated on a device copy, summed over the
+# path's kernels), keyed by the hash of the kernel sources the counters were
+# taken on; any other source reports traffic as null.
+MEASURED_TRAFFIC = [
+    {"kernel": "packed", "hash": "7b9024f260a943b6", "workload": ("int8", "single_scan", 512, 50),
+     "bytes": 235.6e6, "profile": "profiles/ss_pk_int8_ira64800_512f.md"},
+    {"kernel": "packed", "hash": "7b9024f260a943b6", "workload": ("1bit", "single_scan", 512, 50),
+     "bytes": 235.9e6, "profile": "profiles/ss_pk_1bit_ira64800_512f.md"},
+    {"kernel": "f32_frames", "hash": "47448efbb91a1d62", "workload": ("fp32", "single_scan", 512, 50),
+     "bytes": 105150.6e6, "profile": "profiles/fl_f32_ira64800_512f.md"},
+]
+
 
 # Algorithmic bytes per frame and iteration of each path (E edges, N
 # variables, M checks): what a decoder that keeps nothing on chip between
@@ -68,10 +81,13 @@ def alg_bytes_per_frame_iter(msg: str, sched: str, E: int, N: int, M: int) -> in
     return 8 * E + 12 * N
 
 
-def source_hash(name: str) -> str:
+def source_hash(names) -> str:
+    """sha256 prefix of the kernel's source files, concatenated in order."""
     import hashlib
-    path = os.path.join(ROOT, "paper_cs_0609090_amd", "csrc", name)
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in names:
+        h.update(open(os.path.join(ROOT, "paper_cs_0609090_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def log(*a):
@@ -185,18 +201,16 @@ def main():
     achieved_hbm = r["alg_bytes"] / r["kernel_s"] / 1e9
     alg_ops = (ALG_OPS_PER_EDGE * E + ALG_OPS_PER_ROW * M) * r["iters"]
     achieved_alu = alg_ops / r["kernel_s"] / 1e12
-    info = gcode.info()
-    kernel_src = None
-    if args.msg in ("int8", "1bit") and args.sched == "single_scan":
-        if args.msg == "int8" and args.layout in ("auto", "reg") and info["pk_slots"] > 0:
-            kernel_src = "ss_pk.hip"
-        elif args.layout in ("auto", "reg", "reg1") and info["reg_slots"] > 0:
-            kernel_src = "ss_reg.hip"
-    traffic = None
-    if kernel_src:
-        t = MEASURED_TRAFFIC.get(kernel_src, {}).get(source_hash(kernel_src))
-        if t and t.get("workload") == (args.msg, F, max_iter):
-            traffic = t["bytes"]
+    plan = gcode.plan(F, ldpc.make_params(max_iter=max_iter, alpha=alpha, early_stop=False, msg=args.msg,
+                                          sched=args.sched, layout=args.layout))
+    srcs, bound = KERNELS[plan["kernel"]]
+    h = source_hash(srcs)
+    traffic = next((t["bytes"] for t in MEASURED_TRAFFIC if t["kernel"] == plan["kernel"] and t["hash"] == h
+                    and t["workload"] == (args.msg, args.sched, F, max_iter)), None)
+    kernel_desc = {"kernel": plan["kernel"], "sources": list(srcs), "threads": plan["threads"]}
+    if plan["frames_per_lane"]:
+        kernel_desc["frames_per_lane"] = plan["frames_per_lane"]
+        kernel_desc["launch"] = "one decode call: check and variable pass per iteration"
     res = {
         "metric": "coded Gbit/s + edge-updates/s at max 50 iters",
         "value": round(r["gbps"], 4),
@@ -216,19 +230,25 @@ def main():
                    "early_stop": False, "alpha": alpha, "ebn0_db": ebn0,
                    "msg": args.msg, "sched": args.sched, "layout": args.layout},
         "edge_updates_per_s": r["eups"],
-        "roofline": {"bound": "alu", "achieved": round(achieved_alu, 3),
-                     "peak": round(ALU16_PEAK_TOPS, 2), "unit": "TOP/s",
-                     "frac": round(achieved_alu / ALU16_PEAK_TOPS, 4),
-                     "traffic": traffic,
-                     "kernel_ms": round(r["kernel_s"] * 1e3, 4),
-                     "alg_ops_per_launch": alg_ops,
-                     "kernel": kernel_src or "generic"},
-        "hbm_equivalent": {"achieved": round(achieved_hbm, 2), "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": round(achieved_hbm / HBM_PEAK_GBS, 4),
-                           "alg_bytes_per_launch": r["alg_bytes"],
-                           "note": "bytes a decoder that streams messages and posteriors "
-                                   "through HBM every iteration would move"},
     }
+    if bound == "alu":
+        res["roofline"] = {"bound": "alu", "achieved": round(achieved_alu, 3),
+                           "peak": round(ALU16_PEAK_TOPS, 2), "unit": "TOP/s",
+                           "frac": round(achieved_alu / ALU16_PEAK_TOPS, 4),
+                           "traffic": traffic,
+                           "kernel_ms": round(r["kernel_s"] * 1e3, 4),
+                           "alg_ops_per_launch": alg_ops, **kernel_desc}
+        res["hbm_equivalent"] = {"achieved": round(achieved_hbm, 2), "peak": HBM_PEAK_GBS,
+                                 "unit": "GB/s", "frac": round(achieved_hbm / HBM_PEAK_GBS, 4),
+                                 "alg_bytes_per_launch": r["alg_bytes"],
+                                 "note": "bytes a decoder that streams messages and posteriors "
+                                         "through HBM every iteration would move"}
+    else:
+        res["roofline"] = {"bound": "hbm", "achieved": round(achieved_hbm, 2), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(achieved_hbm / HBM_PEAK_GBS, 4),
+                           "traffic": traffic,
+                           "kernel_ms": round(r["kernel_s"] * 1e3, 4),
+                           "alg_bytes_per_launch": r["alg_bytes"], **kernel_desc}
     if not args.no_variants:
         var = {}
         for msg, sched in (("1bit", "single_scan"), ("fp32", "single_scan"),

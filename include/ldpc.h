@@ -73,9 +73,12 @@ typedef enum {
                                    LDS-resident kernels for the remaining codes with M <= 1024 */
 #define LDPC_LAYOUT_REG1 4      /* as LDPC_LAYOUT_REG, one row at a time (no packing) */
 #define LDPC_LAYOUT_FRAMES 5    /* single-scan FP32 and the two-scan baseline (INT8, FP32):
-                                   one frame per lane, 64 frames per wavefront, messages and
+                                   frames across the lanes of a wavefront, messages and
                                    posteriors in the caller's workspace (frame-minor, so every
-                                   access is a whole-wavefront line).  AUTO takes it for these
+                                   access is a whole-wavefront line); single-scan FP32 gives
+                                   each lane four consecutive frames once a call chunk holds
+                                   256 frames and rows have at most 32 entries, otherwise one
+                                   frame per lane.  AUTO takes it for these
                                    paths when their per-edge arrays do not fit in LDS.  The
                                    workspace then covers the whole call and depends on
                                    max_iter: ask ldpc_decode_workspace_size() */
@@ -180,6 +183,40 @@ ldpc_status ldpc_code_query(const ldpc_code *code, ldpc_code_info *out);
  */
 ldpc_status ldpc_decode_workspace_size(const ldpc_code *code, int32_t n_frames,
                                        const ldpc_decode_params *p, size_t *bytes);
+
+/* The kernel a decode call runs (ldpc_plan_info.kernel). */
+typedef enum {
+    LDPC_KERNEL_GENERIC_INT = 0,    /* single-scan fixed point (Sec. IV-V), one workgroup per
+                                       frame, one thread per row, messages in LDS or workspace */
+    LDPC_KERNEL_GENERIC_F32 = 1,    /* single-scan binary32, one workgroup per frame */
+    LDPC_KERNEL_TWO_SCAN = 2,       /* two-scan baseline (Sec. III), one workgroup per frame */
+    LDPC_KERNEL_REG1 = 3,           /* single-scan fixed point, messages in registers, one row
+                                       per lane */
+    LDPC_KERNEL_PACKED = 4,         /* single-scan fixed point, messages in registers, two rows
+                                       per lane (16-bit halves) */
+    LDPC_KERNEL_F32_FRAMES = 5,     /* single-scan binary32, frames across lanes */
+    LDPC_KERNEL_TWO_SCAN_FRAMES = 6 /* two-scan baseline, frames across lanes */
+} ldpc_kernel;
+
+typedef struct {
+    int32_t kernel;          /* ldpc_kernel */
+    int32_t layout;          /* the LDPC_LAYOUT_* value that forces this same plan */
+    int32_t threads;         /* threads per workgroup of the decoding kernel */
+    int32_t lds_bytes;       /* LDS per workgroup of the decoding kernel (0: none) */
+    int32_t frames_per_lane; /* frames-across-lanes kernels: frames each lane decodes (1 or
+                                4); 0 for the kernels with one workgroup per frame */
+    int32_t reserved;        /* 0 */
+    size_t workspace_bytes;  /* what ldpc_decode_workspace_size() returns for the same call */
+} ldpc_plan_info;
+
+/*
+ * The plan ldpc_decode_batch would follow for n_frames frames with these
+ * parameters (after AUTO and any layout pinned by ldpc_autotune).  Host only;
+ * works with host-only handles.  Errors: as ldpc_decode_workspace_size (a
+ * request with no kernel returns LDPC_EUNSUPPORTED); out NULL: LDPC_EINVAL.
+ */
+ldpc_status ldpc_decode_plan(const ldpc_code *code, int32_t n_frames, const ldpc_decode_params *p,
+                             ldpc_plan_info *out);
 
 /*
  * Decode n_frames frames (one parity-check matrix, Sec. III-V).

@@ -11,8 +11,8 @@
 namespace ldpc {
 namespace fl {
 
-constexpr int kWaves = 4;  // wavefronts per workgroup
-constexpr int kBlock = 64 * kWaves;
+constexpr int kBlock = kFlThreads;
+constexpr int kWaves = kBlock / 64;  // wavefronts per workgroup
 constexpr int kNotConverged = INT_MAX;
 constexpr uint32_t kRsrcWord3 = 0x00020000u;  // raw buffer, gfx9 family
 // Byte offset of the unused slots of a short row or column: every array of a

@@ -92,6 +92,9 @@ hipError_t launch_ss_f32(const DecodeArgs &a, const LaunchCfg &cfg, hipStream_t 
 // batch runs in chunks of fl_chunk_frames frames, 0 = code too large)
 int fl_chunk_frames(int N, int64_t E);
 size_t fl_workspace_bytes(int N, int64_t E, int n_frames, int max_iter);
+// frames each lane of that decoder holds (1 or 4) for a call of n_frames
+int fl_frames_per_lane(int N, int64_t E, int n_frames, int max_row_deg);
+constexpr int kFlThreads = 256;  // threads per workgroup of the frames-across-lanes kernels
 // two-scan baseline (int8 or binary32), frames across lanes
 int ts_fl_chunk_frames(int N, int64_t E, bool int8);
 size_t ts_fl_workspace_bytes(int N, int64_t E, int n_frames, int max_iter, bool int8);

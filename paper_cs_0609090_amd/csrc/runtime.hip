@@ -310,6 +310,19 @@ std::vector<uint32_t> pk_slot_assignment(int M, int N, const int32_t *row_ptr, c
     return slot;
 }
 
+// Device workspace of the decode itself, then with the LDPC_F_CHECK_INPUT
+// word (256 bytes at the next 256-byte boundary) when that flag is set.
+size_t decode_workspace(const ldpc_code *c, const ldpc_decode_params *p, const Plan &pl, int32_t n_frames) {
+    return pl.family == 5   ? ldpc::fl_workspace_bytes(c->N, c->E, n_frames, p->max_iter)
+           : pl.family == 6 ? ldpc::ts_fl_workspace_bytes(c->N, c->E, n_frames, p->max_iter,
+                                                          p->msg == LDPC_MSG_INT8)
+                            : (size_t)pl.ws_stride * (size_t)n_frames;
+}
+size_t total_workspace(const ldpc_code *c, const ldpc_decode_params *p, const Plan &pl, int32_t n_frames) {
+    const size_t b = decode_workspace(c, p, pl, n_frames);
+    return (p->flags & LDPC_F_CHECK_INPUT) ? align_up(b, 256) + 256 : b;
+}
+
 }  // namespace
 
 namespace ldpc {
@@ -626,12 +639,34 @@ ldpc_status ldpc_decode_workspace_size(const ldpc_code *c, int32_t n_frames,
     Plan pl;
     st = make_plan(c, p, &pl);
     if (st != LDPC_OK) return st;
-    size_t b = pl.family == 5   ? ldpc::fl_workspace_bytes(c->N, c->E, n_frames, p->max_iter)
-               : pl.family == 6 ? ldpc::ts_fl_workspace_bytes(c->N, c->E, n_frames, p->max_iter,
-                                                              p->msg == LDPC_MSG_INT8)
-                                : (size_t)pl.ws_stride * (size_t)n_frames;
-    if (p->flags & LDPC_F_CHECK_INPUT) b = align_up(b, 256) + 256;
-    *bytes = b;
+    *bytes = total_workspace(c, p, pl, n_frames);
+    return LDPC_OK;
+}
+
+ldpc_status ldpc_decode_plan(const ldpc_code *c, int32_t n_frames, const ldpc_decode_params *p,
+                             ldpc_plan_info *out) {
+    if (!c || !out) return fail(LDPC_EINVAL, "NULL argument");
+    if (n_frames < 0) return fail(LDPC_EINVAL, "n_frames < 0");
+    ldpc_status st = validate_params(p);
+    if (st != LDPC_OK) return st;
+    Plan pl;
+    st = make_plan(c, p, &pl);
+    if (st != LDPC_OK) return st;
+    ldpc_plan_info o{};
+    o.kernel = pl.family;  // the ldpc_kernel values are the plan families
+    const bool frames = pl.family == 5 || pl.family == 6;
+    o.layout = pl.family == 4 ? LDPC_LAYOUT_REG
+               : pl.family == 3 ? LDPC_LAYOUT_REG1
+               : frames         ? LDPC_LAYOUT_FRAMES
+               : pl.cfg.msg_lds ? LDPC_LAYOUT_LDS
+                                : LDPC_LAYOUT_HBM;
+    o.threads = frames ? ldpc::kFlThreads : pl.cfg.threads;
+    o.lds_bytes = frames ? 0 : (int32_t)pl.cfg.lds;
+    o.frames_per_lane = pl.family == 5 ? ldpc::fl_frames_per_lane(c->N, c->E, n_frames, c->D)
+                        : pl.family == 6 ? 1
+                                         : 0;
+    o.workspace_bytes = total_workspace(c, p, pl, n_frames);
+    *out = o;
     return LDPC_OK;
 }
 
@@ -659,15 +694,8 @@ ldpc_status decode_job(const ldpc_code *c, int32_t n_frames, const void *llr_in,
     Plan pl;
     st = make_plan(c, p, &pl);
     if (st != LDPC_OK) return st;
-    size_t need = pl.family == 5   ? ldpc::fl_workspace_bytes(c->N, c->E, n_frames, p->max_iter)
-                  : pl.family == 6 ? ldpc::ts_fl_workspace_bytes(c->N, c->E, n_frames, p->max_iter,
-                                                                 p->msg == LDPC_MSG_INT8)
-                                   : (size_t)pl.ws_stride * (size_t)n_frames;
-    size_t check_off = 0;
-    if (p->flags & LDPC_F_CHECK_INPUT) {
-        check_off = align_up(need, 256);
-        need = check_off + 256;
-    }
+    const size_t check_off = align_up(decode_workspace(c, p, pl, n_frames), 256);
+    const size_t need = total_workspace(c, p, pl, n_frames);
     if (need > 0 && (!workspace || workspace_bytes < need))
         return fail(LDPC_EINVAL, "workspace missing or smaller than ldpc_decode_workspace_size()");
     if (workspace && (reinterpret_cast<uintptr_t>(workspace) & 255u))

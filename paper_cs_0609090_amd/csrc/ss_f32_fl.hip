@@ -261,6 +261,12 @@ FlPlan fl_plan(int N, int64_t E, int n_frames) {
 size_t round_frames(int F, int V) { return (size_t)((F + 64 * V - 1) / (64 * V)) * 64 * V; }
 }  // namespace
 
+// Rows above 32 entries keep one frame per lane (four would not fit the
+// registers); the frame padding of the plan stays.
+int fl_frames_per_lane(int N, int64_t E, int n_frames, int max_row_deg) {
+    return (fl_plan(N, E, n_frames).V == 4 && max_row_deg <= 32) ? 4 : 1;
+}
+
 size_t fl_workspace_bytes(int N, int64_t E, int n_frames, int max_iter) {
     const FlPlan pl = fl_plan(N, E, n_frames);
     const int fr = std::min(n_frames, std::max(pl.chunk, 1));
@@ -288,9 +294,7 @@ hipError_t launch_ss_f32_fl(const DecodeArgs &d, const int32_t *row_ptr, const u
         a.M = d.c.M;
         a.N = d.c.N;
         a.F = F;
-        // rows above 32 entries keep one frame per lane (four would not fit
-        // the registers); the frame padding of the plan stays
-        const int V = (pl.V == 4 && max_row_deg <= 32) ? 4 : 1;
+        const int V = fl_frames_per_lane(d.c.N, E, d.n_frames, max_row_deg);
         a.Fp = (int)round_frames(F, pl.V);
         a.G = a.Fp / (64 * V);
         a.alpha = d.alpha;

@@ -29,7 +29,7 @@ LAYOUT = {"auto": 0, "lds": 1, "hbm": 2, "reg": 3, "reg1": 4, "frames": 5}
 LAYOUT_SHIFT = 8
 
 EXPORTS = ("ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query",
-           "ldpc_decode_workspace_size", "ldpc_decode_batch", "ldpc_last_error",
+           "ldpc_decode_workspace_size", "ldpc_decode_plan", "ldpc_decode_batch", "ldpc_last_error",
            "ldpc_version",
            # include/ldpc_sim.h
            "ldpc_encoder_info", "ldpc_encode_batch", "ldpc_random_bits", "ldpc_channel_awgn",
@@ -40,6 +40,8 @@ EXPORTS = ("ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query",
            # include/ldpc_multi.h
            "ldpc_multi_workspace_size", "ldpc_decode_multi", "ldpc_autotune")
 LAYOUT_NAME = {v: k for k, v in LAYOUT.items()}
+KERNEL_NAME = {0: "generic_int", 1: "generic_f32", 2: "two_scan", 3: "reg1", 4: "packed",
+               5: "f32_frames", 6: "two_scan_frames"}  # ldpc_kernel
 ENC_KIND = {0: "none", 1: "staircase", 2: "dense"}
 
 
@@ -71,6 +73,13 @@ class CodeInfo(ctypes.Structure):
                 ("pk_threads", ctypes.c_int32)]
 
 
+class PlanInfo(ctypes.Structure):
+    """ldpc_plan_info of include/ldpc.h."""
+    _fields_ = [("kernel", ctypes.c_int32), ("layout", ctypes.c_int32), ("threads", ctypes.c_int32),
+                ("lds_bytes", ctypes.c_int32), ("frames_per_lane", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("workspace_bytes", ctypes.c_size_t)]
+
+
 class Job(ctypes.Structure):
     """ldpc_job of include/ldpc_multi.h."""
     _fields_ = [("code", ctypes.c_void_p), ("n_frames", ctypes.c_int32), ("llr_in", ctypes.c_void_p),
@@ -95,6 +104,7 @@ def lib():
         L.ldpc_code_query.argtypes = [vp, ctypes.POINTER(CodeInfo)]
         L.ldpc_decode_workspace_size.argtypes = [vp, i32, ctypes.POINTER(DecodeParams),
                                                  ctypes.POINTER(sz)]
+        L.ldpc_decode_plan.argtypes = [vp, i32, ctypes.POINTER(DecodeParams), ctypes.POINTER(PlanInfo)]
         L.ldpc_decode_batch.argtypes = [vp, i32, vp, ctypes.POINTER(DecodeParams), vp, vp, vp,
                                         vp, vp, sz, vp]
         u32, dbl = ctypes.c_uint32, ctypes.c_double
@@ -112,7 +122,7 @@ def lib():
         L.ldpc_autotune.argtypes = [vp, i32, ctypes.POINTER(DecodeParams), ctypes.POINTER(i32),
                                     ctypes.POINTER(ctypes.c_float), ctypes.POINTER(i32)]
         for f in ("ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query",
-                  "ldpc_decode_workspace_size", "ldpc_decode_batch", "ldpc_encoder_info",
+                  "ldpc_decode_workspace_size", "ldpc_decode_plan", "ldpc_decode_batch", "ldpc_encoder_info",
                   "ldpc_encode_batch", "ldpc_random_bits", "ldpc_channel_awgn", "ldpc_count_errors",
                   "ldpc_learn_classes", "ldpc_learn_workspace_size", "ldpc_learn_forward",
                   "ldpc_learn_backward", "ldpc_multi_workspace_size", "ldpc_decode_multi",
@@ -236,6 +246,16 @@ class Code:
         _check(lib().ldpc_decode_workspace_size(self._h, int(n_frames), ctypes.byref(params),
                                                 ctypes.byref(b)))
         return int(b.value)
+
+    def plan(self, n_frames: int, params: DecodeParams) -> dict:
+        """The plan a decode of n_frames frames follows (ldpc_decode_plan):
+        kernel and layout by name, threads, LDS bytes, frames per lane,
+        workspace bytes."""
+        i = PlanInfo()
+        _check(lib().ldpc_decode_plan(self._h, int(n_frames), ctypes.byref(params), ctypes.byref(i)))
+        return {"kernel": KERNEL_NAME[i.kernel], "layout": LAYOUT_NAME[i.layout], "threads": i.threads,
+                "lds_bytes": i.lds_bytes, "frames_per_lane": i.frames_per_lane,
+                "workspace_bytes": int(i.workspace_bytes)}
 
     def decode_into(self, llr, params: DecodeParams, hard, llr_out, iters, ok, workspace,
                     stream=None) -> None:

@@ -46,7 +46,8 @@ def test_struct_layouts_match_header(L, tmp_path):
     import subprocess
     fields = {"ldpc_decode_params": [f for f, _ in L.DecodeParams._fields_],
               "ldpc_code_info": [f for f, _ in L.CodeInfo._fields_],
-              "ldpc_job": [f for f, _ in L.Job._fields_]}
+              "ldpc_job": [f for f, _ in L.Job._fields_],
+              "ldpc_plan_info": [f for f, _ in L.PlanInfo._fields_]}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ldpc.h"', '#include "ldpc_multi.h"',
              'int main(void) {']
     for st, fs in fields.items():
@@ -60,7 +61,8 @@ def test_struct_layouts_match_header(L, tmp_path):
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
     out = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
                                                        check=True).stdout.splitlines())
-    for st, cls in (("ldpc_decode_params", L.DecodeParams), ("ldpc_code_info", L.CodeInfo), ("ldpc_job", L.Job)):
+    for st, cls in (("ldpc_decode_params", L.DecodeParams), ("ldpc_code_info", L.CodeInfo), ("ldpc_job", L.Job),
+                    ("ldpc_plan_info", L.PlanInfo)):
         assert int(out[st]) == ctypes.sizeof(cls), st
         for f in fields[st]:
             assert int(out[f"{st}.{f}"]) == getattr(cls, f).offset, f"{st}.{f}"
@@ -386,3 +388,80 @@ def test_schedule_and_width_validation(L):
         big.workspace_size(1, L.make_params(msg="int8", layout="hbm"))
     for c in (small, irr, big, huge):
         c.close()
+
+
+# ---------------------------------------------------------------------------
+# ldpc_decode_plan: the plan of a call, on host-only handles
+PLAN_CASES = [("int8", "single_scan"), ("1bit", "single_scan"), ("fp32", "single_scan"),
+              ("int8", "two_scan"), ("fp32", "two_scan")]
+
+
+@pytest.mark.parametrize("name", ["peg1008", "qc7493", "ira16200", "ira64800"])
+def test_decode_plan_matches_workspace_and_forced_layout(L, name):
+    code = {"peg1008": W.code_c0_peg1008, "qc7493": W.code_c1_qc7493, "ira16200": W.code_ira16200,
+            "ira64800": W.code_c2_ira64800}[name]()
+    c = L.Code.from_parity_check(code, device=-1)
+    seen = set()
+    for msg, sched in PLAN_CASES:
+        for F in (1, 100, 256, 300, 512):
+            for flags in (0, L.F_CHECK_INPUT):
+                p = L.make_params(msg=msg, sched=sched, max_iter=20)
+                p.flags |= flags
+                pl = c.plan(F, p)
+                assert pl["workspace_bytes"] == c.workspace_size(F, p)
+                seen.add(pl["kernel"])
+                # forcing the reported layout gives the same plan
+                pf = L.make_params(msg=msg, sched=sched, max_iter=20, layout=pl["layout"])
+                pf.flags |= flags
+                assert c.plan(F, pf) == pl, (msg, sched, F, pl)
+                frames = pl["kernel"] in ("f32_frames", "two_scan_frames")
+                assert (pl["frames_per_lane"] > 0) == frames
+                assert pl["threads"] % 64 == 0 and 0 < pl["threads"] <= 1024
+                if frames:
+                    assert pl["lds_bytes"] == 0 and pl["threads"] == 256
+                else:
+                    assert 0 < pl["lds_bytes"] <= c.info()["lds_bytes_per_cu"]
+                if pl["kernel"] == "f32_frames":
+                    # four frames per lane from 256 frames (rows of at most 32 entries)
+                    assert pl["frames_per_lane"] == (4 if F >= 256 else 1)
+                if pl["kernel"] == "two_scan_frames":
+                    assert pl["frames_per_lane"] == 1
+                if pl["kernel"] == "packed":
+                    assert pl["threads"] == c.info()["pk_threads"]
+    c.close()
+    expect = {"peg1008": {"packed", "generic_f32", "two_scan"},
+              "qc7493": {"packed", "reg1", "f32_frames", "two_scan", "two_scan_frames"},
+              "ira16200": {"reg1", "f32_frames", "two_scan", "two_scan_frames"},
+              "ira64800": {"packed", "f32_frames", "two_scan_frames"}}[name]
+    assert seen == expect
+
+
+def test_decode_plan_wide_rows_one_frame_per_lane(L):
+    """Rows above 32 entries: binary32 frames across lanes keeps one frame per
+    lane at any batch size."""
+    code = W.random_small_code(60, 200, (33, 40), seed=33)
+    c = L.Code.from_parity_check(code, device=-1)
+    p = L.make_params(msg="fp32", layout="frames", max_iter=10)
+    assert c.plan(300, p)["frames_per_lane"] == 1
+    code2 = W.random_small_code(60, 200, (17, 21), seed=17)
+    c2 = L.Code.from_parity_check(code2, device=-1)
+    assert c2.plan(300, p)["frames_per_lane"] == 4 and c2.plan(255, p)["frames_per_lane"] == 1
+    c.close()
+    c2.close()
+
+
+def test_decode_plan_errors(L):
+    c = L.Code.from_parity_check(W.code_c0_peg1008(), device=-1)
+    p = L.make_params(msg="int8")
+    lib = L.lib()
+    assert lib.ldpc_decode_plan(c._h, 10, ctypes.byref(p), None) == 1  # LDPC_EINVAL
+    out = L.PlanInfo()
+    assert lib.ldpc_decode_plan(None, 10, ctypes.byref(p), ctypes.byref(out)) == 1
+    assert lib.ldpc_decode_plan(c._h, -1, ctypes.byref(p), ctypes.byref(out)) == 1
+    assert lib.ldpc_decode_plan(c._h, 10, None, ctypes.byref(out)) == 1
+    bad = L.make_params(msg="1bit", sched="two_scan")
+    assert lib.ldpc_decode_plan(c._h, 10, ctypes.byref(bad), ctypes.byref(out)) == 5  # LDPC_EUNSUPPORTED
+    fr = L.make_params(msg="int8", layout="frames")  # frames-across-lanes single-scan is FP32 only
+    with pytest.raises(L.LdpcError):
+        c.plan(10, fr)
+    c.close()
