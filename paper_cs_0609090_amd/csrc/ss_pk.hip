@@ -10,11 +10,11 @@
 //     m2   = |t2|
 //     min2 = min(min2, max(min1, m2)), min1 = min(min1, m2)   (v_pk_*_u16)
 //     parity ^= t2                          (sign bits 15 and 31)
-//   per pair of rows: A2, B2 = normalised min1/min2 (signed by the row parity);
-//     mag2 = |t2| == min1 ? B2 : A2         (one v_bfi_b32 on a per-row mask)
+//   per pair of rows: A2, B2 = normalised min1/min2;
+//     mag2 = max(A2, B2 + 64 min1 - 64 |t2|)   (one multiply-add, one max)
 //   i.e. B where |t_j| equals the row minimum and A elsewhere: no argmin is
 //   needed, since a tie at the minimum forces min2 = min1 and so A = B.
-//     L2   = sign-applied mag2, delta2 = L2 - Lold2
+//     L2   = mag2 * (+-1: own sign XOR row parity) + 64, delta2 = L2 - Lold2
 //   and one LDS atomic per edge adds the delta into the posterior field.
 //
 // Variables live in LDS "slots" chosen at code creation: slot s holds Z_old
@@ -65,6 +65,12 @@ __device__ __forceinline__ uint32_t bits(i16x2 v) { return __builtin_bit_cast(ui
 
 // min(max(x, lo), hi): one v_med3_u32
 __device__ __forceinline__ uint32_t clamp_u(uint32_t x, uint32_t lo, uint32_t hi) { return min(max(x, lo), hi); }
+
+// 128 - 256 beta in both 16-bit halves (beta in steps, capped at 32: past 31
+// every normalised magnitude is 0 either way)
+__device__ __forceinline__ uint32_t rounding_offset(int b) {
+    return (uint32_t)(uint16_t)(int16_t)(128 - 256 * min(b, 32)) * 0x00010001u;
+}
 
 // bytes (2s, 2s+1) of w -> the low bytes of the two 16-bit halves
 __device__ __forceinline__ uint32_t pair_of(uint32_t w, int s) {
@@ -140,7 +146,11 @@ __global__ void __launch_bounds__(T) ss_pk_kernel(DecodeArgs a) {
 
     const uint32_t tid16 = (uint32_t)tid * 16u;
     uint32_t a8x2 = (uint32_t)a.a8 * 0x00010001u;  // normalisation pair, both 16-bit halves
-    uint32_t bx2 = (uint32_t)a.b_int * 0x00010001u;
+    uint32_t c8x2 = rounding_offset(a.b_int);
+    // +-64 in both halves, opaque so that the products by it stay multiply-adds
+    // (a constant power of two would become a shift and a separate add)
+    uint32_t k64 = 0x00400040u, kn64 = 0xFFC0FFC0u;
+    asm volatile("" : "+s"(k64), "+s"(kn64));
     int iters = 0;
     bool converged = false;  // the decision of the last completed iteration is a codeword
     bool conv_prev = false;  // FUSED: that of the iteration before the last one is
@@ -156,7 +166,7 @@ __global__ void __launch_bounds__(T) ss_pk_kernel(DecodeArgs a) {
             int a8i, bi;
             sched_pair(a, it, a8i, bi);
             a8x2 = (uint32_t)a8i * 0x00010001u;
-            bx2 = (uint32_t)bi * 0x00010001u;
+            c8x2 = rounding_offset(bi);
         }
 #pragma unroll
         for (int p = 0; p < RP; ++p) {
@@ -215,37 +225,59 @@ __global__ void __launch_bounds__(T) ss_pk_kernel(DecodeArgs a) {
                 if (D % 2 == 0) hp ^= h2[D - 1];
                 zodd |= hp;
             }
-            // per row pair: normalised magnitudes of the saturated minima, signed
-            // once by the row parity (each message is then flipped only by its
-            // own extrinsic's sign)
+            // per row pair: normalised magnitudes of the saturated minima,
+            // A, B = max(round(alpha m) - beta, 0) with the offset folded into
+            // the rounding constant (128 - 256 beta, beta capped at 32 where A
+            // and B are 0 anyway) and an arithmetic shift: the sum stays within
+            // +-8064, so the 16-bit halves hold it exactly
             const u16x2 m1 = __builtin_elementwise_min(min1, (u16x2){31, 31});
             const u16x2 m2 = __builtin_elementwise_min(min2, (u16x2){31, 31});
-            const i16x2 Ar = as_i(bits((m1 * as_u(a8x2) + (u16x2){128, 128}) >> (u16x2){8, 8})) - as_i(bx2);
-            const i16x2 Br = as_i(bits((m2 * as_u(a8x2) + (u16x2){128, 128}) >> (u16x2){8, 8})) - as_i(bx2);
-            const i16x2 Am = __builtin_elementwise_max(Ar, (i16x2){0, 0});
-            const i16x2 Bm = __builtin_elementwise_max(Br, (i16x2){0, 0});
+            const i16x2 Am = __builtin_elementwise_max(as_i(bits(m1 * as_u(a8x2) + as_u(c8x2))) >> (i16x2){8, 8},
+                                                       (i16x2){0, 0});
+            const i16x2 Bm = __builtin_elementwise_max(as_i(bits(m2 * as_u(a8x2) + as_u(c8x2))) >> (i16x2){8, 8},
+                                                       (i16x2){0, 0});
             const i16x2 ps = as_i(par) >> (i16x2){15, 15};
-            uint32_t B2 = bits((Bm ^ ps) - ps);
-            uint32_t A2 = bits((Am ^ ps) - ps);
-            uint32_t mn1 = bits(min1);
-            asm volatile("" : "+v"(B2), "+v"(A2), "+v"(mn1));
+            uint32_t B2, A2, mn1, Cs;
+            if (ONEBIT) {  // A and B signed once by the row parity (the stored state)
+                B2 = bits((Bm ^ ps) - ps);
+                A2 = bits((Am ^ ps) - ps);
+                mn1 = bits(min1);
+                asm volatile("" : "+v"(B2), "+v"(A2), "+v"(mn1));
+            } else {
+                // |t_j| equals min1 at the minimum (and at a tie, where A = B)
+                // and is at least min1 + 1 elsewhere, where B - 64 (|t_j| - min1)
+                // < 0 <= A: so max(A, Cs - 64 |t_j|) with Cs = B + 64 min1 is B
+                // at the minimum and A elsewhere (|t_j| <= 93: no overflow)
+                A2 = bits(Am);
+                Cs = bits(min1 * as_u(k64) + as_u(bits(Bm)));
+                mn1 = bits(ps);  // the row parity as a mask per half
+                asm volatile("" : "+v"(A2), "+v"(Cs), "+v"(mn1));
+            }
             uint32_t nl[D];
             uint32_t Sn = 0;
 #pragma unroll
             for (int j = 0; j < D; ++j) {
-                // |t_j| >= min1, so (min1 - |t_j|) >> 15 is 0 at the minimum and
-                // -1 elsewhere; one bit-select then picks B or A per row
-                uint32_t nsel = bits(as_i(bits(as_u(mn1) - as_u(mg2[j]))) >> (i16x2){15, 15});
-                asm volatile("" : "+v"(nsel));  // stays a mask: no per-half compares
-                const uint32_t mag = (nsel & A2) | (~nsel & B2);
-                // own sign +-1, then L_new + 64 in one multiply-add
-                const i16x2 sg = (as_i(t2[j]) >> (i16x2){15, 15}) | (i16x2){1, 1};
                 i16x2 lb;
-                lb = as_i(mag) * sg + (i16x2){64, 64};
-                if (ONEBIT) {  // keep the own-extrinsic sign and the minimum flag
+                if (ONEBIT) {
+                    // |t_j| >= min1, so (min1 - |t_j|) >> 15 is 0 at the minimum
+                    // and -1 elsewhere; one bit-select then picks B or A per row
+                    uint32_t nsel = bits(as_i(bits(as_u(mn1) - as_u(mg2[j]))) >> (i16x2){15, 15});
+                    asm volatile("" : "+v"(nsel));  // stays a mask: no per-half compares
+                    const uint32_t mag = (nsel & A2) | (~nsel & B2);
+                    // own sign +-1, then L_new + 64 in one multiply-add
+                    const i16x2 sg = (as_i(t2[j]) >> (i16x2){15, 15}) | (i16x2){1, 1};
+                    lb = as_i(mag) * sg + (i16x2){64, 64};
+                    // keep the own-extrinsic sign and the minimum flag
                     const uint32_t sneg = bits(as_i(t2[j]) >> (i16x2){15, 15});
                     Sn = __builtin_amdgcn_bitop3_b32(sneg, 0x00010001u << j, Sn, 0xEA);  // (a & b) | c
                     Sn = __builtin_amdgcn_bitop3_b32(nsel, 0x01000100u << j, Sn, 0xAE);  // (~a & b) | c
+                } else {
+                    const i16x2 mag =
+                        __builtin_elementwise_max(as_i(mg2[j]) * as_i(kn64) + as_i(Cs), as_i(A2));
+                    // sign +-1 per half: own extrinsic's sign XOR the row parity
+                    const uint32_t sg = __builtin_amdgcn_bitop3_b32(
+                        bits(as_i(t2[j]) >> (i16x2){15, 15}), mn1, 0x00010001u, 0xBE);  // (a ^ b) | c
+                    lb = mag * as_i(sg) + (i16x2){64, 64};
                 }
                 nl[j] = bits(lb);
                 const uint32_t d = bits(lb - as_i(lo2[j]));

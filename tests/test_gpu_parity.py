@@ -392,3 +392,21 @@ def test_early_stop_hard_only_ira64800_sampled(torch_dev, L, orc, msg):
     np.testing.assert_array_equal(g["iters"][sel], r["iters"])
     np.testing.assert_array_equal(g["ok"][sel], r["ok"])
     np.testing.assert_array_equal(g["hard"][sel], r["hard"])
+
+
+@pytest.mark.parametrize("layout", ["auto", "reg1", "lds"])
+@pytest.mark.parametrize("msg", ["int8", "1bit"])
+def test_large_offsets(torch_dev, L, orc, msg, layout):
+    """Offsets near and past the largest magnitude (31 steps), against the
+    oracle: inputs at a step of 1/8 are mostly saturated, so row minima of
+    31 are common; offsets of 24-30 steps leave magnitudes of 1-7, those of
+    31, 32 and 200 steps zero every message (the packed kernel caps the
+    offset at 32 steps).  The PEG code runs the packed kernel under AUTO."""
+    code = W.code_c0_peg1008()
+    step = 0.125
+    x = W.quantize_llr(_llr_cached(code.name, code.N, code.design_rate, 64, 4.0, (0xB1, 7)), step=step)
+    variant = VARIANTS[0] if msg == "int8" else VARIANTS[1]
+    for beta in (3.0, 3.5, 3.75, 3.875, 4.0, 25.0):
+        for alpha in (1.0, 0.8):
+            _run_pair(torch_dev, L, orc, code, x, variant, max_iter=6, alpha=alpha, beta=beta, early_stop=False,
+                      layout=layout, llr_step=step)
