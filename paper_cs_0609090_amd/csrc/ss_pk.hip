@@ -63,9 +63,6 @@ __device__ __forceinline__ i16x2 as_i(uint32_t v) { return __builtin_bit_cast(i1
 __device__ __forceinline__ uint32_t bits(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
 __device__ __forceinline__ uint32_t bits(i16x2 v) { return __builtin_bit_cast(uint32_t, v); }
 
-// min(max(x, lo), hi): one v_med3_u32
-__device__ __forceinline__ uint32_t clamp_u(uint32_t x, uint32_t lo, uint32_t hi) { return min(max(x, lo), hi); }
-
 // 128 - 256 beta in both 16-bit halves (beta in steps, capped at 32: past 31
 // every normalised magnitude is 0 either way)
 __device__ __forceinline__ uint32_t rounding_offset(int b) {
@@ -75,6 +72,41 @@ __device__ __forceinline__ uint32_t rounding_offset(int b) {
 // bytes (2s, 2s+1) of w -> the low bytes of the two 16-bit halves
 __device__ __forceinline__ uint32_t pair_of(uint32_t w, int s) {
     return __builtin_amdgcn_perm(w, w, s == 0 ? 0x0c010c00u : 0x0c030c02u);
+}
+
+// Z_old bytes from the accumulator words, three 10-bit fields per word
+// biased by BIAS: four words (twelve slots) per step, one 16-byte LDS read
+// and three 4-byte writes.  BIAS is 64 mod 256, so the low byte of a field
+// clamped to [BIAS - 62, BIAS + 62] (one v_med3_u32 with constant bounds) is
+// the saturated Z_old + 64.  Words past the last one are private padding
+// words (read, never used); bytes of slots >= N (unused, the dummy) are left
+// untouched.
+template <int BIAS, int T>
+__device__ __forceinline__ void refresh3(const uint32_t *zacc, uint8_t *zold, int N, int nwords, int tid) {
+    constexpr uint32_t lo = BIAS - kZoldMax, hi = BIAS + kZoldMax;
+    const int ngroups = (nwords + 3) / 4;
+    for (int g = tid; g < ngroups; g += T) {
+        const int n0 = g * 12;
+        const uint4 v = *reinterpret_cast<const uint4 *>(zacc + 4 * g);
+        const uint32_t vw[4] = {v.x, v.y, v.z, v.w};
+        uint32_t b[12];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            b[3 * q] = min(max(vw[q] & 1023u, lo), hi);
+            b[3 * q + 1] = min(max((vw[q] >> 10) & 1023u, lo), hi);
+            b[3 * q + 2] = min(max(vw[q] >> 20, lo), hi);
+        }
+        if (n0 + 12 <= N) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const uint32_t l = __builtin_amdgcn_perm(b[4 * q + 1], b[4 * q], 0x0c0c0400u);
+                const uint32_t h = __builtin_amdgcn_perm(b[4 * q + 3], b[4 * q + 2], 0x04000c0cu);
+                *reinterpret_cast<uint32_t *>(zold + n0 + 4 * q) = l | h;
+            }
+        } else {
+            for (int i = 0; i < 12 && n0 + i < N; ++i) zold[n0 + i] = (uint8_t)b[i];
+        }
+    }
 }
 
 template <int D, int R, bool ONEBIT, bool FUSED, int T>
@@ -308,36 +340,10 @@ __global__ void __launch_bounds__(T) ss_pk_kernel(DecodeArgs a) {
         }
         if (tid == 0) *flag = 0;
         if (P == 3) {
-            // four accumulator words (twelve slots) per step: one 16-byte LDS
-            // read, three 4-byte writes.  The field bias is 64 mod 256, so the
-            // low byte of a field clamped to [bias - 62, bias + 62] is the
-            // saturated Z_old + 64.  Words past the last one are private
-            // padding words (read, never used); bytes of slots >= N (unused,
-            // the dummy) are left untouched.
-            const uint32_t zlo = (uint32_t)(biasP - kZoldMax), zhi = (uint32_t)(biasP + kZoldMax);
-            const int ngroups = (nwords + 3) / 4;
-            for (int g = tid; g < ngroups; g += kT) {
-                const int n0 = g * 12;
-                const uint4 v = *reinterpret_cast<const uint4 *>(zacc + 4 * g);
-                const uint32_t vw[4] = {v.x, v.y, v.z, v.w};
-                uint32_t b[12];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    b[3 * q] = clamp_u(vw[q] & 1023u, zlo, zhi);
-                    b[3 * q + 1] = clamp_u((vw[q] >> 10) & 1023u, zlo, zhi);
-                    b[3 * q + 2] = clamp_u(vw[q] >> 20, zlo, zhi);
-                }
-                if (n0 + 12 <= N) {
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) {
-                        const uint32_t lo = __builtin_amdgcn_perm(b[4 * q + 1], b[4 * q], 0x0c0c0400u);
-                        const uint32_t hi = __builtin_amdgcn_perm(b[4 * q + 3], b[4 * q + 2], 0x04000c0cu);
-                        *reinterpret_cast<uint32_t *>(zold + n0 + 4 * q) = lo | hi;
-                    }
-                } else {
-                    for (int i = 0; i < 12 && n0 + i < N; ++i) zold[n0 + i] = (uint8_t)b[i];
-                }
-            }
+            if (biasP == 320)
+                refresh3<320, kT>(zacc, zold, N, nwords, tid);
+            else
+                refresh3<576, kT>(zacc, zold, N, nwords, tid);
         } else {
             for (int w = tid; w < nwords; w += kT) {
                 const uint32_t v = zacc[w];
