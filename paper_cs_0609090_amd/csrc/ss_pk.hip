@@ -230,9 +230,10 @@ __global__ void __launch_bounds__(T) ss_pk_kernel(DecodeArgs a) {
                     constexpr unsigned short kS = 15, kI = 7;
                     const unsigned short ss = (unsigned short)(kS - j), si = (unsigned short)(kI - j);
                     const i16x2 sm = as_i(bits(as_u(Sp) << (u16x2){ss, ss})) >> (i16x2){15, 15};
-                    uint32_t im = bits(as_i(bits(as_u(Sp) << (u16x2){si, si})) >> (i16x2){15, 15});
-                    asm volatile("" : "+v"(im));
-                    const uint32_t mo = (im & Bold) | (~im & Aold);
+                    const uint32_t im = bits(as_i(bits(as_u(Sp) << (u16x2){si, si})) >> (i16x2){15, 15});
+                    // an explicit bit-select keeps im a mask (no per-half
+                    // compares) without fencing the schedule between slots
+                    const uint32_t mo = __builtin_amdgcn_bitop3_b32(im, Bold, Aold, 0xCA);  // a ? b : c
                     l2 = bits(as_i(mo) * (sm | (i16x2){1, 1}) + (i16x2){64, 64});
                 } else {
                     l2 = pair_of(Lw[p][j >> 1], j & 1);
@@ -293,9 +294,8 @@ __global__ void __launch_bounds__(T) ss_pk_kernel(DecodeArgs a) {
                 if (ONEBIT) {
                     // |t_j| >= min1, so (min1 - |t_j|) >> 15 is 0 at the minimum
                     // and -1 elsewhere; one bit-select then picks B or A per row
-                    uint32_t nsel = bits(as_i(bits(as_u(mn1) - as_u(mg2[j]))) >> (i16x2){15, 15});
-                    asm volatile("" : "+v"(nsel));  // stays a mask: no per-half compares
-                    const uint32_t mag = (nsel & A2) | (~nsel & B2);
+                    const uint32_t nsel = bits(as_i(bits(as_u(mn1) - as_u(mg2[j]))) >> (i16x2){15, 15});
+                    const uint32_t mag = __builtin_amdgcn_bitop3_b32(nsel, A2, B2, 0xCA);  // nsel ? A : B
                     // own sign +-1, then L_new + 64 in one multiply-add
                     const i16x2 sg = (as_i(t2[j]) >> (i16x2){15, 15}) | (i16x2){1, 1};
                     lb = as_i(mag) * sg + (i16x2){64, 64};
