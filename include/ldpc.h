@@ -77,7 +77,7 @@ typedef enum {
                                    posteriors in the caller's workspace (frame-minor, so every
                                    access is a whole-wavefront line); single-scan FP32 gives
                                    each lane four consecutive frames once a call chunk holds
-                                   256 frames and rows have at most 32 entries, otherwise one
+                                   256 frames and rows have at most 16 entries, otherwise one
                                    frame per lane.  AUTO takes it for these
                                    paths when their per-edge arrays do not fit in LDS.  The
                                    workspace then covers the whole call and depends on

@@ -261,10 +261,11 @@ FlPlan fl_plan(int N, int64_t E, int n_frames) {
 size_t round_frames(int F, int V) { return (size_t)((F + 64 * V - 1) / (64 * V)) * 64 * V; }
 }  // namespace
 
-// Rows above 32 entries keep one frame per lane (four would not fit the
-// registers); the frame padding of the plan stays.
+// Rows above 16 entries keep one frame per lane: four frames of a 32-slot
+// row need all 256 registers of a lane, and the occupancy lost costs more than
+// the wider accesses gain.  The frame padding of the plan stays.
 int fl_frames_per_lane(int N, int64_t E, int n_frames, int max_row_deg) {
-    return (fl_plan(N, E, n_frames).V == 4 && max_row_deg <= 32) ? 4 : 1;
+    return (fl_plan(N, E, n_frames).V == 4 && max_row_deg <= 16) ? 4 : 1;
 }
 
 size_t fl_workspace_bytes(int N, int64_t E, int n_frames, int max_iter) {
@@ -325,9 +326,7 @@ hipError_t launch_ss_f32_fl(const DecodeArgs &d, const int32_t *row_ptr, const u
         const int K = d.max_iter;
         hipError_t e;
         if (V == 4)
-            e = max_row_deg <= 8    ? run<8, 4>(dc, a, K, grid, s)
-                : max_row_deg <= 16 ? run<16, 4>(dc, a, K, grid, s)
-                                    : run<32, 4>(dc, a, K, grid, s);
+            e = max_row_deg <= 8 ? run<8, 4>(dc, a, K, grid, s) : run<16, 4>(dc, a, K, grid, s);
         else
             e = max_row_deg <= 8    ? run<8, 1>(dc, a, K, grid, s)
                 : max_row_deg <= 16 ? run<16, 1>(dc, a, K, grid, s)

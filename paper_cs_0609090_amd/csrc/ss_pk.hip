@@ -11,7 +11,9 @@
 //     min2 = min(min2, max(min1, m2)), min1 = min(min1, m2)   (v_pk_*_u16)
 //     parity ^= t2                          (sign bits 15 and 31)
 //   per pair of rows: A2, B2 = normalised min1/min2;
-//     mag2 = max(A2, B2 + 64 min1 - 64 |t2|)   (one multiply-add, one max)
+//     mag2 = max(A2, B2 + 64 min1 - 64 |t2|)   (one multiply-add, one max;
+//            rows of up to 8 slots), or a bit-select of A2 / B2 on the mask
+//            (min1 - |t2|) >> 15 (wider rows and the 1-bit state)
 //   i.e. B where |t_j| equals the row minimum and A elsewhere: no argmin is
 //   needed, since a tie at the minimum forces min2 = min1 and so A = B.
 //     L2   = mag2 * (+-1: own sign XOR row parity) + 64, delta2 = L2 - Lold2
@@ -116,6 +118,10 @@ __global__ void __launch_bounds__(T) ss_pk_kernel(DecodeArgs a) {
     static_assert(R % 2 == 0, "rows are processed in pairs");
     constexpr int RP = R / 2;        // row pairs per thread
     constexpr int W = (D + 1) / 2;   // registers per row pair: two slots (4 bytes) each
+    // B-or-A choice per slot: a mask and a bit-select (the 1-bit state keeps
+    // the mask; measured faster for rows wider than 8 slots), else one
+    // multiply-add and a max (fewer instructions, faster for short rows)
+    constexpr bool kMaskSelect = ONEBIT || D > 8;
     extern __shared__ __align__(16) uint8_t lds[];
     const int tid = threadIdx.x;
     const int f = blockIdx.x;
@@ -271,7 +277,7 @@ __global__ void __launch_bounds__(T) ss_pk_kernel(DecodeArgs a) {
                                                        (i16x2){0, 0});
             const i16x2 ps = as_i(par) >> (i16x2){15, 15};
             uint32_t B2, A2, mn1, Cs;
-            if (ONEBIT) {  // A and B signed once by the row parity (the stored state)
+            if (kMaskSelect) {  // A and B signed once by the row parity
                 B2 = bits((Bm ^ ps) - ps);
                 A2 = bits((Am ^ ps) - ps);
                 mn1 = bits(min1);
@@ -291,7 +297,7 @@ __global__ void __launch_bounds__(T) ss_pk_kernel(DecodeArgs a) {
 #pragma unroll
             for (int j = 0; j < D; ++j) {
                 i16x2 lb;
-                if (ONEBIT) {
+                if (kMaskSelect) {
                     // |t_j| >= min1, so (min1 - |t_j|) >> 15 is 0 at the minimum
                     // and -1 elsewhere; one bit-select then picks B or A per row
                     const uint32_t nsel = bits(as_i(bits(as_u(mn1) - as_u(mg2[j]))) >> (i16x2){15, 15});
@@ -299,10 +305,11 @@ __global__ void __launch_bounds__(T) ss_pk_kernel(DecodeArgs a) {
                     // own sign +-1, then L_new + 64 in one multiply-add
                     const i16x2 sg = (as_i(t2[j]) >> (i16x2){15, 15}) | (i16x2){1, 1};
                     lb = as_i(mag) * sg + (i16x2){64, 64};
-                    // keep the own-extrinsic sign and the minimum flag
-                    const uint32_t sneg = bits(as_i(t2[j]) >> (i16x2){15, 15});
-                    Sn = __builtin_amdgcn_bitop3_b32(sneg, 0x00010001u << j, Sn, 0xEA);  // (a & b) | c
-                    Sn = __builtin_amdgcn_bitop3_b32(nsel, 0x01000100u << j, Sn, 0xAE);  // (~a & b) | c
+                    if (ONEBIT) {  // keep the own-extrinsic sign and the minimum flag
+                        const uint32_t sneg = bits(as_i(t2[j]) >> (i16x2){15, 15});
+                        Sn = __builtin_amdgcn_bitop3_b32(sneg, 0x00010001u << j, Sn, 0xEA);  // (a & b) | c
+                        Sn = __builtin_amdgcn_bitop3_b32(nsel, 0x01000100u << j, Sn, 0xAE);  // (~a & b) | c
+                    }
                 } else {
                     const i16x2 mag =
                         __builtin_elementwise_max(as_i(mg2[j]) * as_i(kn64) + as_i(Cs), as_i(A2));

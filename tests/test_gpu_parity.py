@@ -214,11 +214,11 @@ def test_frames_layout(torch_dev, L, orc, case, fp):
                           layout="frames")
 
 
-@pytest.mark.parametrize("deg", [(3, 6), (9, 12), (17, 21), (33, 40)], ids=lambda d: f"rowdeg{d[0]}-{d[1]}")
+@pytest.mark.parametrize("deg", [(3, 6), (9, 12), (13, 16), (17, 21), (33, 40)], ids=lambda d: f"rowdeg{d[0]}-{d[1]}")
 def test_frames_layout_256_frame_batches(torch_dev, L, orc, deg):
     """binary32 single-scan, frames across lanes, with 256 frames or more:
     each lane then holds four consecutive frames (16-byte accesses) for rows
-    of up to 32 entries, one frame above that.  Every row-length bucket, a
+    of up to 16 entries, one frame above that.  Every row-length bucket, a
     batch that is not a multiple of 256, frames of one lane converging at
     different iterations (early stop), and the per-frame outputs in place."""
     code = W.random_small_code(60, 4 * deg[1] + 40, deg, seed=deg[0])
