@@ -75,10 +75,10 @@ typedef enum {
 #define LDPC_LAYOUT_FRAMES 5    /* single-scan FP32 and the two-scan baseline (INT8, FP32):
                                    frames across the lanes of a wavefront, messages and
                                    posteriors in the caller's workspace (frame-minor, so every
-                                   access is a whole-wavefront line); single-scan FP32 gives
-                                   each lane four consecutive frames once a call chunk holds
-                                   256 frames and rows have at most 16 entries, otherwise one
-                                   frame per lane.  AUTO takes it for these
+                                   access is a whole-wavefront line); each lane takes four
+                                   consecutive frames once a call chunk holds 256 frames and
+                                   rows have at most 16 entries, otherwise one frame per
+                                   lane.  AUTO takes it for these
                                    paths when their per-edge arrays do not fit in LDS.  The
                                    workspace then covers the whole call and depends on
                                    max_iter: ask ldpc_decode_workspace_size() */

@@ -98,6 +98,7 @@ constexpr int kFlThreads = 256;  // threads per workgroup of the frames-across-l
 // two-scan baseline (int8 or binary32), frames across lanes
 int ts_fl_chunk_frames(int N, int64_t E, bool int8);
 size_t ts_fl_workspace_bytes(int N, int64_t E, int n_frames, int max_iter, bool int8);
+int ts_fl_frames_per_lane(int N, int64_t E, bool int8, int n_frames, int max_row_deg);
 hipError_t launch_two_scan_fl(const DecodeArgs &d, bool int8, const int32_t *row_ptr, const uint32_t *row_ent,
                               const uint32_t *vc_csr, int64_t E, int max_row_deg, int cu_count, hipStream_t s);
 hipError_t launch_ss_f32_fl(const DecodeArgs &a, const int32_t *row_ptr, const uint32_t *row_ent, int64_t E,

@@ -662,9 +662,10 @@ ldpc_status ldpc_decode_plan(const ldpc_code *c, int32_t n_frames, const ldpc_de
                                 : LDPC_LAYOUT_HBM;
     o.threads = frames ? ldpc::kFlThreads : pl.cfg.threads;
     o.lds_bytes = frames ? 0 : (int32_t)pl.cfg.lds;
-    o.frames_per_lane = pl.family == 5 ? ldpc::fl_frames_per_lane(c->N, c->E, n_frames, c->D)
-                        : pl.family == 6 ? 1
-                                         : 0;
+    o.frames_per_lane =
+        pl.family == 5   ? ldpc::fl_frames_per_lane(c->N, c->E, n_frames, c->D)
+        : pl.family == 6 ? ldpc::ts_fl_frames_per_lane(c->N, c->E, p->msg == LDPC_MSG_INT8, n_frames, c->D)
+                         : 0;
     o.workspace_bytes = total_workspace(c, p, pl, n_frames);
     *out = o;
     return LDPC_OK;

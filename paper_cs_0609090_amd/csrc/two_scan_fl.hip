@@ -1,7 +1,8 @@
 // Two-scan min-sum (Sec. III, Eqs. 1-2), the baseline schedule, with frames
-// across lanes: one frame per lane, 64 frames per wavefront, every per-frame
-// array frame-minor (element (i, f) at i*Fp + f), so a wavefront's access to
-// one value is one contiguous line and the code's addressing is wave-uniform.
+// across lanes: one or four consecutive frames per lane (64 or 256 frames per
+// wavefront), every per-frame array frame-minor (element (i, f) at i*Fp + f),
+// so a wavefront's access to one value is one contiguous line and the code's
+// addressing is wave-uniform.
 //
 // Both per-edge arrays of the schedule are kept in the caller's workspace,
 // in the row order of H (CSR):
@@ -65,21 +66,98 @@ __device__ __forceinline__ int norm_q(int m, int a8, int b) {
     return v > 0 ? v : 0;
 }
 
+// V consecutive frames per lane (1 or 4) of one element in one access: int8
+// messages (V bytes), int16 posteriors (2V bytes), binary32 (4V bytes).
+template <int V>
+__device__ __forceinline__ void ld_i8(const Buf &b, int (&v)[V], uint32_t lo, uint32_t eo) {
+    if constexpr (V == 4) {
+        const uint32_t x = __builtin_amdgcn_raw_buffer_load_b32(b.r, lo, eo, 0);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[c] = (int)(int8_t)(uint8_t)(x >> (8 * c));
+    } else {
+        v[0] = b.ld8(lo, eo);
+    }
+}
+template <int V>
+__device__ __forceinline__ void st_i8(const Buf &b, const int (&v)[V], uint32_t lo, uint32_t eo) {
+    if constexpr (V == 4) {
+        const uint32_t x = ((uint32_t)v[0] & 255u) | (((uint32_t)v[1] & 255u) << 8) |
+                           (((uint32_t)v[2] & 255u) << 16) | ((uint32_t)v[3] << 24);
+        __builtin_amdgcn_raw_buffer_store_b32(x, b.r, lo, eo, 0);
+    } else {
+        b.st8(v[0], lo, eo);
+    }
+}
+template <int V>
+__device__ __forceinline__ void ld_i16(const Buf &b, int (&v)[V], uint32_t lo, uint32_t eo) {
+    if constexpr (V == 4) {
+        const auto x = __builtin_amdgcn_raw_buffer_load_b64(b.r, lo, eo, 0);
+        const uint32_t w0 = x[0], w1 = x[1];
+        v[0] = (int)(int16_t)(uint16_t)w0;
+        v[1] = (int)(int16_t)(uint16_t)(w0 >> 16);
+        v[2] = (int)(int16_t)(uint16_t)w1;
+        v[3] = (int)(int16_t)(uint16_t)(w1 >> 16);
+    } else {
+        v[0] = b.ld16(lo, eo);
+    }
+}
+template <int V>
+__device__ __forceinline__ void st_i16(const Buf &b, const int (&v)[V], uint32_t lo, uint32_t eo) {
+    if constexpr (V == 4) {
+        typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+        const u32x2 x = {((uint32_t)v[0] & 0xFFFFu) | ((uint32_t)v[1] << 16),
+                         ((uint32_t)v[2] & 0xFFFFu) | ((uint32_t)v[3] << 16)};
+        __builtin_amdgcn_raw_buffer_store_b64(x, b.r, lo, eo, 0);
+    } else {
+        b.st16(v[0], lo, eo);
+    }
+}
+// messages (int8 or binary32) and posteriors Z_n (int16 or binary32)
+template <bool INT, int V, class T>
+__device__ __forceinline__ void ld_msg(const Buf &b, T (&v)[V], uint32_t lo, uint32_t eo) {
+    if constexpr (INT)
+        ld_i8<V>(b, v, lo, eo);
+    else
+        b.ldv<V, 0>(v, lo, eo);
+}
+template <bool INT, int V, class T>
+__device__ __forceinline__ void st_msg(const Buf &b, const T (&v)[V], uint32_t lo, uint32_t eo) {
+    if constexpr (INT)
+        st_i8<V>(b, v, lo, eo);
+    else
+        b.stv<V, 0>(v, lo, eo);
+}
+template <bool INT, int V, class T>
+__device__ __forceinline__ void ld_post(const Buf &b, T (&v)[V], uint32_t lo, uint32_t eo) {
+    if constexpr (INT)
+        ld_i16<V>(b, v, lo, eo);
+    else
+        b.ldv<V, 0>(v, lo, eo);
+}
+template <bool INT, int V, class T>
+__device__ __forceinline__ void st_post(const Buf &b, const T (&v)[V], uint32_t lo, uint32_t eo) {
+    if constexpr (INT)
+        st_i16<V>(b, v, lo, eo);
+    else
+        b.stv<V, 0>(v, lo, eo);
+}
+
 // Horizontal scan of iteration k (UPDATE), or the syndrome of Z_n alone.
 //   syn_row >= 0: rows failing the syndrome of Z_n set fail[syn_row]
 //   conv_k  >= 1: first fold fail[conv_k] into conv (one wavefront)
-// FIRST: Z_mn = Z^(0)_n, gathered from z0.
-template <bool INT, int DMAX, bool UPDATE, bool FIRST>
+// FIRST: Z_mn = Z^(0)_n, gathered from z0.  V frames per lane.
+template <bool INT, int DMAX, bool UPDATE, bool FIRST, int V>
 __global__ void __launch_bounds__(kBlock) ts_rows(TsArgs a, int syn_row, int conv_k) {
     constexpr uint32_t es = INT ? 1 : 4, zs = INT ? 2 : 4;
+    using T = typename std::conditional<INT, int, float>::type;
     const int lane = threadIdx.x & 63;
     const int w = wave_id();
     const int Fp = a.Fp;
     if (conv_k >= 1 && w == 0) fold_conv(a.conv, a.fail, conv_k, Fp, lane);
     if (w >= a.rwaves * a.G) return;
     const int g = w % a.G;
-    const uint32_t f = (uint32_t)(g * 64 + lane);
-    const uint32_t foe = f * es, foz = f * zs;
+    const uint32_t f0 = (uint32_t)((g * 64 + lane) * V);  // first frame of the lane
+    const uint32_t foe = f0 * es, foz = f0 * zs;
     const uint32_t rowe = (uint32_t)Fp * es, rowz = (uint32_t)Fp * zs;
     const Buf b0(a.z0, a.z0bytes), bn(a.zn, a.znbytes), bm(a.zmn, a.ebytes), bl(a.L, a.ebytes);
     const auto *rp = cptr(a.row_ptr);
@@ -88,82 +166,82 @@ __global__ void __launch_bounds__(kBlock) ts_rows(TsArgs a, int syn_row, int con
     for (int m = w / a.G; m < a.M; m += a.rwaves) {
         const int e0 = rp[m];
         const int d = rp[m + 1] - e0;
-        uint32_t var[DMAX], epos[DMAX];
+        uint32_t vo0[DMAX], voz[DMAX], epos[DMAX];
 #pragma unroll
         for (int j = 0; j < DMAX; ++j) {
             const uint32_t nv = re[2 * (e0 + j)];
-            var[j] = j < d ? nv : 0xFFFFFFFFu;
+            vo0[j] = j < d ? nv * rowe : kOutOfRange;
+            voz[j] = j < d ? nv * rowz : kOutOfRange;
             epos[j] = j < d ? (uint32_t)(e0 + j) * rowe : kOutOfRange;
         }
         // loads first (slots j >= d out of range), then the arithmetic
-        typename std::conditional<INT, int, float>::type t[DMAX];
-        int hz[DMAX];
+        T t[DMAX][V];
+        T zv[DMAX][V];
 #pragma unroll
         for (int j = 0; j < DMAX; ++j) {
-            const uint32_t vo0 = var[j] == 0xFFFFFFFFu ? kOutOfRange : var[j] * rowe;
-            const uint32_t voz = var[j] == 0xFFFFFFFFu ? kOutOfRange : var[j] * rowz;
             if (UPDATE) {
-                if constexpr (INT)
-                    t[j] = FIRST ? b0.ld8(foe, vo0) : bm.ld8(foe, epos[j]);
+                if (FIRST)
+                    ld_msg<INT, V>(b0, t[j], foe, vo0[j]);
                 else
-                    t[j] = FIRST ? b0.ldf(foe, vo0) : bm.ldf(foe, epos[j]);
+                    ld_msg<INT, V>(bm, t[j], foe, epos[j]);
             }
-            if (syn_on) {
-                if constexpr (INT)
-                    hz[j] = bn.ld16(foz, voz) > 0 ? 0 : 1;
-                else
-                    hz[j] = bn.ldf(foz, voz) > 0.0f ? 0 : 1;
-            }
+            if (syn_on) ld_post<INT, V>(bn, zv[j], foz, voz[j]);
         }
-        if (syn_on) {
-            int syn = 0;
 #pragma unroll
-            for (int j = 0; j < DMAX; ++j) syn ^= j < d ? hz[j] : 0;
-            if (syn) a.fail[(size_t)syn_row * Fp + f] = 1;
+        for (int c = 0; c < V; ++c) {  // each frame on its own
+            if (syn_on) {
+                int syn = 0;
+#pragma unroll
+                for (int j = 0; j < DMAX; ++j) syn ^= (j < d && !(zv[j][c] > (T)0)) ? 1 : 0;
+                if (syn) a.fail[(size_t)syn_row * Fp + f0 + c] = 1;
+            }
+            if (UPDATE) {
+                int par = 0, idx = 0;
+                T min1, min2;
+                if constexpr (INT) {
+                    min1 = 255;
+                    min2 = 255;
+                } else {
+                    min1 = INFINITY;
+                    min2 = INFINITY;
+                }
+#pragma unroll
+                for (int j = 0; j < DMAX; ++j) {
+                    const bool in = j < d;
+                    par ^= (in && t[j][c] < (T)0) ? 1 : 0;
+                    T av;
+                    if constexpr (INT)
+                        av = in ? abs(t[j][c]) : 255;
+                    else
+                        av = in ? fabsf(t[j][c]) : INFINITY;
+                    if constexpr (INT) {
+                        min2 = min(min2, max(min1, av));
+                        idx = av < min1 ? j : idx;
+                        min1 = min(min1, av);
+                    } else {
+                        min2 = fminf(min2, fmaxf(min1, av));
+                        idx = av < min1 ? j : idx;
+                        min1 = fminf(min1, av);
+                    }
+                }
+                T A, B;
+                if constexpr (INT) {
+                    A = norm_q(min1, a.a8, a.b_int);
+                    B = norm_q(min2, a.a8, a.b_int);
+                } else {
+                    A = norm_f(min1, a.alpha, a.beta);
+                    B = norm_f(min2, a.alpha, a.beta);
+                }
+#pragma unroll
+                for (int j = 0; j < DMAX; ++j) {
+                    const T mag = j == idx ? B : A;
+                    t[j][c] = (par ^ (t[j][c] < (T)0 ? 1 : 0)) ? -mag : mag;  // L_mn
+                }
+            }
         }
         if (UPDATE) {
-            int par = 0, idx = 0;
-            if constexpr (INT) {
-                int min1 = 255, min2 = 255;
 #pragma unroll
-                for (int j = 0; j < DMAX; ++j) {
-                    const bool in = j < d;
-                    par ^= (in && t[j] < 0) ? 1 : 0;
-                    const int av = in ? abs(t[j]) : 255;
-                    min2 = min(min2, max(min1, av));
-                    idx = av < min1 ? j : idx;
-                    min1 = min(min1, av);
-                }
-                const int A = norm_q(min1, a.a8, a.b_int), B = norm_q(min2, a.a8, a.b_int);
-                int out[DMAX];
-#pragma unroll
-                for (int j = 0; j < DMAX; ++j) {
-                    const int mag = j == idx ? B : A;
-                    out[j] = (par ^ (t[j] < 0 ? 1 : 0)) ? -mag : mag;
-                }
-#pragma unroll
-                for (int j = 0; j < DMAX; ++j) bl.st8(out[j], foe, epos[j]);
-            } else {
-                float min1 = INFINITY, min2 = INFINITY;
-#pragma unroll
-                for (int j = 0; j < DMAX; ++j) {
-                    const bool in = j < d;
-                    par ^= (in && t[j] < 0.0f) ? 1 : 0;
-                    const float av = in ? fabsf(t[j]) : INFINITY;
-                    min2 = fminf(min2, fmaxf(min1, av));
-                    idx = av < min1 ? j : idx;
-                    min1 = fminf(min1, av);
-                }
-                const float A = norm_f(min1, a.alpha, a.beta), B = norm_f(min2, a.alpha, a.beta);
-                float out[DMAX];
-#pragma unroll
-                for (int j = 0; j < DMAX; ++j) {
-                    const float mag = j == idx ? B : A;
-                    out[j] = (par ^ (t[j] < 0.0f ? 1 : 0)) ? -mag : mag;
-                }
-#pragma unroll
-                for (int j = 0; j < DMAX; ++j) bl.stf(out[j], foe, epos[j]);
-            }
+            for (int j = 0; j < DMAX; ++j) st_msg<INT, V>(bl, t[j], foe, epos[j]);
         }
     }
 }
@@ -171,42 +249,51 @@ __global__ void __launch_bounds__(kBlock) ts_rows(TsArgs a, int syn_row, int con
 // Vertical scan of iteration k: Z_n and the new Z_mn.  Frames frozen by the
 // early stop keep their Z_n.  Variables of degree up to 8 keep their
 // messages in registers between the sum and the extrinsics; larger degrees
-// read them twice.
-template <bool INT, bool FREEZE>
+// read them twice.  V frames per lane.
+template <bool INT, bool FREEZE, int V>
 __global__ void __launch_bounds__(kBlock) ts_vars(TsArgs a, int fail_row) {
     constexpr uint32_t es = INT ? 1 : 4, zs = INT ? 2 : 4;
-    using V = typename std::conditional<INT, int, float>::type;
+    using T = typename std::conditional<INT, int, float>::type;
     const int lane = threadIdx.x & 63;
     const int w = wave_id();
     const int Fp = a.Fp;
     if (w >= a.rwaves * a.G) return;
     const int g = w % a.G;
-    const uint32_t f = (uint32_t)(g * 64 + lane);
-    const uint32_t foe = f * es, foz = f * zs;
+    const uint32_t f0 = (uint32_t)((g * 64 + lane) * V);
+    const uint32_t foe = f0 * es, foz = f0 * zs;
     const uint32_t rowe = (uint32_t)Fp * es, rowz = (uint32_t)Fp * zs;
     const Buf b0(a.z0, a.z0bytes), bn(a.zn, a.znbytes), bm(a.zmn, a.ebytes), bl(a.L, a.ebytes);
-    bool frozen = false;
-    if (FREEZE) frozen = a.conv[f] != kNotConverged || a.fail[(size_t)fail_row * Fp + f] == 0;
+    bool frozen[V];
+    bool any_frozen = false;
+#pragma unroll
+    for (int c = 0; c < V; ++c) {
+        frozen[c] = FREEZE && (a.conv[f0 + c] != kNotConverged || a.fail[(size_t)fail_row * Fp + f0 + c] == 0);
+        any_frozen = any_frozen || frozen[c];
+    }
+    // frozen frames keep Z_n: their old values are read back only by lanes
+    // that hold one (an out-of-range offset moves no data)
+    const uint32_t fc = (FREEZE && any_frozen) ? foz : kOutOfRange;
     const auto *vp = cptr(a.vc_ptr);
     const auto *vcs = cptr(a.vc_csr);
-    auto ld = [&](const Buf &b, uint32_t off) -> V {
-        if constexpr (INT)
-            return b.ld8(foe, off);
-        else
-            return b.ldf(foe, off);
-    };
-    auto st_ext = [&](V zsum, V lv, uint32_t off) {  // Z_mn = Z_n - L_mn
-        if constexpr (INT) {
-            const int v = zsum - lv;
-            bm.st8(v > kQmax ? kQmax : (v < -kQmax ? -kQmax : v), foe, off);
-        } else {
-            bm.stf(__fsub_rn(zsum, lv), foe, off);
+    auto st_ext = [&](const T (&zsum)[V], const T (&lv)[V], uint32_t off) {  // Z_mn = Z_n - L_mn
+        T x[V];
+#pragma unroll
+        for (int c = 0; c < V; ++c) {
+            if constexpr (INT) {
+                const int v = zsum[c] - lv[c];
+                x[c] = v > kQmax ? kQmax : (v < -kQmax ? -kQmax : v);
+            } else {
+                x[c] = __fsub_rn(zsum[c], lv[c]);
+            }
         }
+        st_msg<INT, V>(bm, x, foe, off);
     };
     for (int n = w / a.G; n < a.N; n += a.rwaves) {
         const int e0 = vp[n], e1 = vp[n + 1];
-        V s = ld(b0, (uint32_t)n * rowe);
-        V l[8];
+        T s[V], cp[V];
+        ld_msg<INT, V>(b0, s, foe, (uint32_t)n * rowe);
+        if (FREEZE) ld_post<INT, V>(bn, cp, fc, (uint32_t)n * rowz);
+        T l[8][V];
         uint32_t eo[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) eo[i] = kOutOfRange;
@@ -219,20 +306,22 @@ __global__ void __launch_bounds__(kBlock) ts_vars(TsArgs a, int fail_row) {
                 eo[i] = e + i < e1 ? ce * rowe : kOutOfRange;
             }
 #pragma unroll
-            for (int i = 0; i < 8; ++i) l[i] = ld(bl, eo[i]);
+            for (int i = 0; i < 8; ++i) ld_msg<INT, V>(bl, l[i], foe, eo[i]);
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                if constexpr (INT)
-                    s = e + i < e1 ? s + l[i] : s;
-                else
-                    s = e + i < e1 ? __fadd_rn(s, l[i]) : s;
-            }
+            for (int i = 0; i < 8; ++i)
+#pragma unroll
+                for (int c = 0; c < V; ++c) {
+                    if constexpr (INT)
+                        s[c] = e + i < e1 ? s[c] + l[i][c] : s[c];
+                    else
+                        s[c] = e + i < e1 ? __fadd_rn(s[c], l[i][c]) : s[c];
+                }
         }
-        if (!(FREEZE && frozen)) {
-            if constexpr (INT)
-                bn.st16(s, foz, (uint32_t)n * rowz);
-            else
-                bn.stf(s, foz, (uint32_t)n * rowz);
+        {
+            T zn[V];
+#pragma unroll
+            for (int c = 0; c < V; ++c) zn[c] = (FREEZE && frozen[c]) ? cp[c] : s[c];
+            st_post<INT, V>(bn, zn, foz, (uint32_t)n * rowz);
         }
         // extrinsics: a variable of degree <= 8 still holds its messages and
         // their offsets in registers (out-of-range slots are dropped stores);
@@ -248,7 +337,7 @@ __global__ void __launch_bounds__(kBlock) ts_vars(TsArgs a, int fail_row) {
                     eo[i] = e + i < e1 ? ce * rowe : kOutOfRange;
                 }
 #pragma unroll
-                for (int i = 0; i < 8; ++i) l[i] = ld(bl, eo[i]);
+                for (int i = 0; i < 8; ++i) ld_msg<INT, V>(bl, l[i], foe, eo[i]);
 #pragma unroll
                 for (int i = 0; i < 8; ++i) st_ext(s, l[i], eo[i]);
             }
@@ -256,12 +345,12 @@ __global__ void __launch_bounds__(kBlock) ts_vars(TsArgs a, int fail_row) {
     }
 }
 
-template <bool INT, int DMAX>
+template <bool INT, int DMAX, int V>
 hipError_t run(const DecodeArgs &d, const TsArgs &a, int K, unsigned grid, hipStream_t s) {
     using Tin = typename std::conditional<INT, int8_t, float>::type;
     using Tz = typename std::conditional<INT, int16_t, float>::type;
     const bool es = d.early_stop != 0;
-    const dim3 tgrid((unsigned)((a.N + 63) / 64), (unsigned)a.G);
+    const dim3 tgrid((unsigned)((a.N + 63) / 64), (unsigned)(a.Fp / 64));
     hipLaunchKernelGGL(transpose_in<Tin>, tgrid, dim3(kBlock), 0, s, static_cast<const Tin *>(d.llr_in),
                        static_cast<Tin *>(a.z0), a.N, a.F, a.Fp);
     const int64_t nfail = (int64_t)(K + 1) * a.Fp;
@@ -275,16 +364,17 @@ hipError_t run(const DecodeArgs &d, const TsArgs &a, int K, unsigned grid, hipSt
         const int syn_row = (es && k >= 2) ? k - 1 : -1;
         const int conv_k = (es && k >= 3) ? k - 2 : 0;
         if (k == 1)
-            hipLaunchKernelGGL((ts_rows<INT, DMAX, true, true>), dim3(grid), dim3(kBlock), 0, s, a, syn_row, conv_k);
+            hipLaunchKernelGGL((ts_rows<INT, DMAX, true, true, V>), dim3(grid), dim3(kBlock), 0, s, a, syn_row,
+                               conv_k);
         else
-            hipLaunchKernelGGL((ts_rows<INT, DMAX, true, false>), dim3(grid), dim3(kBlock), 0, s, a, syn_row,
+            hipLaunchKernelGGL((ts_rows<INT, DMAX, true, false, V>), dim3(grid), dim3(kBlock), 0, s, a, syn_row,
                                conv_k);
         if (es && k >= 2)
-            hipLaunchKernelGGL((ts_vars<INT, true>), dim3(grid), dim3(kBlock), 0, s, a, k - 1);
+            hipLaunchKernelGGL((ts_vars<INT, true, V>), dim3(grid), dim3(kBlock), 0, s, a, k - 1);
         else
-            hipLaunchKernelGGL((ts_vars<INT, false>), dim3(grid), dim3(kBlock), 0, s, a, 0);
+            hipLaunchKernelGGL((ts_vars<INT, false, V>), dim3(grid), dim3(kBlock), 0, s, a, 0);
     }
-    hipLaunchKernelGGL((ts_rows<INT, DMAX, false, false>), dim3(grid), dim3(kBlock), 0, s, a, K,
+    hipLaunchKernelGGL((ts_rows<INT, DMAX, false, false, V>), dim3(grid), dim3(kBlock), 0, s, a, K,
                        (es && K >= 3) ? K - 2 : 0);
     hipLaunchKernelGGL(frame_out, dim3((unsigned)((a.F + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a.fail, a.conv,
                        a.F, a.Fp, K, d.early_stop, d.iters_out, d.ok_out);
@@ -293,15 +383,47 @@ hipError_t run(const DecodeArgs &d, const TsArgs &a, int K, unsigned grid, hipSt
     return hipGetLastError();
 }
 
+template <bool INT, int V>
+hipError_t run_deg(const DecodeArgs &d, const TsArgs &a, int K, unsigned grid, hipStream_t s, int max_row_deg) {
+    if (max_row_deg <= 8) return run<INT, 8, V>(d, a, K, grid, s);
+    if (max_row_deg <= 16) return run<INT, 16, V>(d, a, K, grid, s);
+    if constexpr (V == 1) {
+        if (max_row_deg <= 32) return run<INT, 32, 1>(d, a, K, grid, s);
+        return run<INT, 64, 1>(d, a, K, grid, s);
+    }
+    return hipErrorInvalidValue;  // four frames per lane take rows of at most 16 entries
+}
+
+// Chunk of a call (frames) and frames per lane of its plan: four per lane
+// (one 4-, 8- or 16-byte access per element) once a chunk holds 256 frames,
+// chunks then a multiple of 256.
+struct TsPlan {
+    int V, chunk;
+};
+TsPlan ts_plan(int N, int64_t E, bool int8, int n_frames) {
+    const int chunk = ts_fl_chunk_frames(N, E, int8);
+    if (std::min(n_frames, chunk) >= 256) return {4, chunk / 256 * 256};
+    return {1, chunk};
+}
+size_t ts_round_frames(int F, int V) { return (size_t)((F + 64 * V - 1) / (64 * V)) * 64 * V; }
+
 }  // namespace
 
 int ts_fl_chunk_frames(int N, int64_t E, bool int8) {
     return fl::chunk_frames(std::max<int64_t>(E * (int8 ? 1 : 4), (int64_t)N * 4));
 }
 
+// Rows above 16 entries keep one frame per lane (four frames of a wide row
+// would take the registers that hide the gathers' latency); the frame padding
+// of the plan stays.
+int ts_fl_frames_per_lane(int N, int64_t E, bool int8, int n_frames, int max_row_deg) {
+    return (ts_plan(N, E, int8, n_frames).V == 4 && max_row_deg <= 16) ? 4 : 1;
+}
+
 size_t ts_fl_workspace_bytes(int N, int64_t E, int n_frames, int max_iter, bool int8) {
-    const int fr = std::min(n_frames, std::max(ts_fl_chunk_frames(N, E, int8), 1));
-    const size_t Fp = (size_t)((fr + 63) / 64) * 64;
+    const TsPlan pl = ts_plan(N, E, int8, n_frames);
+    const int fr = std::min(n_frames, std::max(pl.chunk, 1));
+    const size_t Fp = ts_round_frames(fr, pl.V);
     const size_t es = int8 ? 1 : 4, zs = int8 ? 2 : 4;
     return fl::al256((size_t)N * Fp * es) + fl::al256((size_t)N * Fp * zs) + 2 * fl::al256((size_t)E * Fp * es) +
            fl::al256((size_t)(max_iter + 1) * Fp * 4) + fl::al256(Fp * 4);
@@ -309,8 +431,10 @@ size_t ts_fl_workspace_bytes(int N, int64_t E, int n_frames, int max_iter, bool 
 
 hipError_t launch_two_scan_fl(const DecodeArgs &d, bool int8, const int32_t *row_ptr, const uint32_t *row_ent,
                               const uint32_t *vc_csr, int64_t E, int max_row_deg, int cu_count, hipStream_t s) {
-    const int chunk = ts_fl_chunk_frames(d.c.N, E, int8);
+    const TsPlan pl = ts_plan(d.c.N, E, int8, d.n_frames);
+    const int chunk = pl.chunk;
     if (chunk <= 0 || max_row_deg > 64) return hipErrorInvalidValue;
+    const int V = ts_fl_frames_per_lane(d.c.N, E, int8, d.n_frames, max_row_deg);
     const size_t es = int8 ? 1 : 4, zs = int8 ? 2 : 4;
     for (int c0 = 0; c0 < d.n_frames; c0 += chunk) {
         const int F = std::min(chunk, d.n_frames - c0);
@@ -325,8 +449,8 @@ hipError_t launch_two_scan_fl(const DecodeArgs &d, bool int8, const int32_t *row
         a.M = d.c.M;
         a.N = d.c.N;
         a.F = F;
-        a.G = (F + 63) / 64;
-        a.Fp = a.G * 64;
+        a.Fp = (int)ts_round_frames(F, pl.V);
+        a.G = a.Fp / (64 * V);
         a.a8 = d.a8;
         a.b_int = d.b_int;
         a.alpha = d.alpha;
@@ -355,25 +479,12 @@ hipError_t launch_two_scan_fl(const DecodeArgs &d, bool int8, const int32_t *row
         wave_layout(cu_count, a.G, std::max(a.M, a.N), &a.rwaves, &grid);
         const int K = d.max_iter;
         hipError_t e;
-        if (int8) {
-            if (max_row_deg <= 8)
-                e = run<true, 8>(dc, a, K, grid, s);
-            else if (max_row_deg <= 16)
-                e = run<true, 16>(dc, a, K, grid, s);
-            else if (max_row_deg <= 32)
-                e = run<true, 32>(dc, a, K, grid, s);
-            else
-                e = run<true, 64>(dc, a, K, grid, s);
-        } else {
-            if (max_row_deg <= 8)
-                e = run<false, 8>(dc, a, K, grid, s);
-            else if (max_row_deg <= 16)
-                e = run<false, 16>(dc, a, K, grid, s);
-            else if (max_row_deg <= 32)
-                e = run<false, 32>(dc, a, K, grid, s);
-            else
-                e = run<false, 64>(dc, a, K, grid, s);
-        }
+        if (int8)
+            e = V == 4 ? run_deg<true, 4>(dc, a, K, grid, s, max_row_deg)
+                       : run_deg<true, 1>(dc, a, K, grid, s, max_row_deg);
+        else
+            e = V == 4 ? run_deg<false, 4>(dc, a, K, grid, s, max_row_deg)
+                       : run_deg<false, 1>(dc, a, K, grid, s, max_row_deg);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -421,12 +421,10 @@ def test_decode_plan_matches_workspace_and_forced_layout(L, name):
                     assert pl["lds_bytes"] == 0 and pl["threads"] == 256
                 else:
                     assert 0 < pl["lds_bytes"] <= c.info()["lds_bytes_per_cu"]
-                if pl["kernel"] == "f32_frames":
+                if frames:
                     # four frames per lane from 256 frames, rows of at most 16 entries
                     wide = c.info()["max_row_deg"] > 16
                     assert pl["frames_per_lane"] == (4 if F >= 256 and not wide else 1)
-                if pl["kernel"] == "two_scan_frames":
-                    assert pl["frames_per_lane"] == 1
                 if pl["kernel"] == "packed":
                     assert pl["threads"] == c.info()["pk_threads"]
     c.close()

@@ -214,19 +214,26 @@ def test_frames_layout(torch_dev, L, orc, case, fp):
                           layout="frames")
 
 
+@pytest.mark.parametrize("fp", [VARIANTS[2], VARIANTS[3], VARIANTS[4]], ids=lambda v: f"{v[0]}-{v[1]}")
 @pytest.mark.parametrize("deg", [(3, 6), (9, 12), (13, 16), (17, 21), (33, 40)], ids=lambda d: f"rowdeg{d[0]}-{d[1]}")
-def test_frames_layout_256_frame_batches(torch_dev, L, orc, deg):
-    """binary32 single-scan, frames across lanes, with 256 frames or more:
-    each lane then holds four consecutive frames (16-byte accesses) for rows
-    of up to 16 entries, one frame above that.  Every row-length bucket, a
-    batch that is not a multiple of 256, frames of one lane converging at
-    different iterations (early stop), and the per-frame outputs in place."""
+def test_frames_layout_256_frame_batches(torch_dev, L, orc, deg, fp):
+    """Frames across lanes (binary32 single-scan, both two-scan baselines)
+    with 256 frames or more: each lane then holds four consecutive frames (one
+    4-, 8- or 16-byte access per element) for rows of up to 16 entries, one
+    frame above that.  Every row-length bucket, a batch that is not a
+    multiple of 256, frames of one lane converging at different iterations
+    (early stop), and the per-frame outputs in place."""
     code = W.random_small_code(60, 4 * deg[1] + 40, deg, seed=deg[0])
     eb = np.random.default_rng(deg[0]).uniform(2.0, 7.0, size=300)  # a spread of convergence times
     x = W.awgn_llr(code.N, 300, eb, code.design_rate, key=(0x256, deg[0]))
+    if fp[0] == "int8":
+        x = W.quantize_llr(x)
+    gc = L.Code.from_parity_check(code, device=-1)
+    pl = gc.plan(300, L.make_params(msg=fp[0], sched=fp[1], layout="frames", max_iter=12))
+    gc.close()
+    assert pl["frames_per_lane"] == (4 if deg[1] <= 16 else 1)
     for es in (True, False):
-        g, r = _run_pair(torch_dev, L, orc, code, x, VARIANTS[2], max_iter=12, alpha=0.8, early_stop=es,
-                         layout="frames")
+        g, r = _run_pair(torch_dev, L, orc, code, x, fp, max_iter=12, alpha=0.8, early_stop=es, layout="frames")
         if es:  # lanes mix frozen and running frames
             it = r["iters"][:256].reshape(64, 4)
             assert (it.min(axis=1) != it.max(axis=1)).sum() > 30
