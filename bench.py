@@ -65,6 +65,12 @@ MEASURED_TRAFFIC = [
      "bytes": 236.1e6, "profile": "profiles/ss_pk_1bit_ira64800_512f.md"},
     {"kernel": "f32_frames", "hash": "1c5cdaa9c2275be3", "workload": ("fp32", "single_scan", 512, 50),
      "bytes": 105147.1e6, "profile": "profiles/fl_f32_ira64800_512f.md"},
+    {"kernel": "reg1", "hash": "e7d86239f37f995e", "workload": ("int8", "single_scan", 512, 50),
+     "bytes": 221.2e6, "profile": "profiles/ss_reg_int8_ira64800_512f.md"},
+    {"kernel": "two_scan_frames", "hash": "cbfdbc070410dda8", "workload": ("int8", "two_scan", 512, 50),
+     "bytes": 29395.0e6, "profile": "profiles/ts_fl_int8_ira64800_512f.md"},
+    {"kernel": "two_scan_frames", "hash": "cbfdbc070410dda8", "workload": ("fp32", "two_scan", 512, 50),
+     "bytes": 107935.3e6, "profile": "profiles/ts_fl_f32_ira64800_512f.md"},
 ]
 
 
