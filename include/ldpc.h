@@ -67,7 +67,8 @@ typedef enum {
                                    two-rows-per-lane kernel (pk_threads per workgroup) when it
                                    has a shape (1BIT up to 8 slots per row), else the one-row
                                    kernel (1024 threads).  AUTO picks, for fixed point: the
-                                   packed kernel from 16 rows per thread (M > 8192), for rows
+                                   packed kernel from 16 rows per thread (M > 8192; 1BIT from
+                                   8 rows per thread), for rows
                                    wider than 8 slots (INT8) and with 256-thread shapes for
                                    small codes; the one-row register kernel otherwise; the
                                    LDS-resident kernels for the remaining codes with M <= 1024 */

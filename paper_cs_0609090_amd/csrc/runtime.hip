@@ -93,10 +93,11 @@ ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl)
         return fail(LDPC_EUNSUPPORTED, "7-8 bit messages run on the LDS/HBM kernel only");
     // AUTO for fixed point (measured on MI355X, 50 iterations): the packed
     // two-rows-per-lane kernel pays off from 16 rows per thread (M > 8192),
-    // for rows wider than 8 slots (int8 only) and with its 256-thread shapes
-    // for small codes; otherwise the one-row register kernel is faster, and
-    // other codes of at most 1024 checks run best LDS-resident with one thread
-    // per row (the register kernels give every frame 1024 threads).
+    // from 8 rows per thread for the 1-bit state, for rows wider than 8 slots
+    // (int8 only) and with its 256-thread shapes for small codes; otherwise
+    // the one-row register kernel is faster, and other codes of at most 1024
+    // checks run best LDS-resident with one thread per row (the register
+    // kernels give every frame 1024 threads).
     const bool small_pk = c->pkD > 0 && c->pkT <= 256;  // packed shape with small workgroups
     const bool wide_pk = c->pkD > 8 && 5 * c->D >= 4 * c->pkD;  // wide rows filling >= 80% of the slots
     const bool small_auto = layout == LDPC_LAYOUT_AUTO && c->M <= 1024 && !small_pk;
@@ -104,7 +105,8 @@ ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl)
         (layout == LDPC_LAYOUT_AUTO || reg_layout)) {
         const bool packed = c->pkD > 0 && layout != LDPC_LAYOUT_REG1 &&
                             (p->msg == LDPC_MSG_INT8 || c->pkD <= 8) &&  // 1-bit: 8 slots per half
-                            (layout == LDPC_LAYOUT_REG || c->pkR >= 16 || wide_pk || small_pk);
+                            (layout == LDPC_LAYOUT_REG || c->pkR >= 16 || wide_pk || small_pk ||
+                             (p->msg == LDPC_MSG_1BIT && c->pkR >= 8));
         const bool ok = packed || c->regD > 0;
         if (ok) {
             pl->family = packed ? 4 : 3;
