@@ -65,7 +65,7 @@ typedef enum {
                                    INT8/1BIT; codes with an instantiated shape, see
                                    ldpc_code_info.reg_* / pk_*); INT8 and 1BIT use the packed
                                    two-rows-per-lane kernel (pk_threads per workgroup) when it
-                                   has a shape (1BIT up to 8 slots per row), else the one-row
+                                   has a shape, else the one-row
                                    kernel (1024 threads).  AUTO picks, for fixed point: the
                                    packed kernel from 16 rows per thread (M > 8192; 1BIT from
                                    8 rows per thread), for rows
@@ -149,8 +149,7 @@ typedef struct {
     int32_t reg_slots;          /* register-resident shape: slots per row (0 = none) */
     int32_t reg_rows_per_thread;
     int32_t reg_zpack;          /* posterior accumulator fields per 32-bit LDS word */
-    int32_t pk_slots;           /* packed (two rows per lane) shape: slots per row (0 = none);
-                                   1BIT only when pk_slots <= 8 */
+    int32_t pk_slots;           /* packed (two rows per lane) shape: slots per row (0 = none) */
     int32_t pk_rows_per_thread;
     int32_t pk_threads;         /* threads per workgroup (one frame) of the packed kernel */
 } ldpc_code_info;

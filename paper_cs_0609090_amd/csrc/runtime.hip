@@ -104,7 +104,6 @@ ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl)
     if (p->sched == LDPC_SINGLE_SCAN && p->msg != LDPC_MSG_FP32 && !small_auto && qmax == kQmax6 &&
         (layout == LDPC_LAYOUT_AUTO || reg_layout)) {
         const bool packed = c->pkD > 0 && layout != LDPC_LAYOUT_REG1 &&
-                            (p->msg == LDPC_MSG_INT8 || c->pkD <= 8) &&  // 1-bit: 8 slots per half
                             (layout == LDPC_LAYOUT_REG || c->pkR >= 16 || wide_pk || small_pk ||
                              (p->msg == LDPC_MSG_1BIT && c->pkR >= 8));
         const bool ok = packed || c->regD > 0;

@@ -113,11 +113,11 @@ __device__ __forceinline__ void refresh3(const uint32_t *zacc, uint8_t *zold, in
 
 template <int D, int R, bool ONEBIT, bool FUSED, int T>
 __global__ void __launch_bounds__(T) ss_pk_kernel(DecodeArgs a) {
-    static_assert(!ONEBIT || D <= 8, "1-bit state keeps 8 slots per 16-bit half");
     constexpr int kT = T;  // threads per workgroup (one frame)
     static_assert(R % 2 == 0, "rows are processed in pairs");
     constexpr int RP = R / 2;        // row pairs per thread
     constexpr int W = (D + 1) / 2;   // registers per row pair: two slots (4 bytes) each
+    constexpr int NS = (D + 7) / 8;  // 1-bit state registers per row pair: eight slots each
     // B-or-A choice per slot: a mask and a bit-select (the 1-bit state keeps
     // the mask; measured faster for rows wider than 8 slots), else one
     // multiply-add and a max (fewer instructions, faster for short rows)
@@ -164,18 +164,20 @@ __global__ void __launch_bounds__(T) ss_pk_kernel(DecodeArgs a) {
 
     // Message state of each row pair.
     //   int8:  Lw[p][i], bytes 2s / 2s+1: slot 2i+s of rows a / b, as L + 64.
-    //   1-bit (Sec. V): St[p] bit j / 16+j: sign of slot j's own extrinsic
-    //          t in row a / b; bit 8+j / 24+j: slot j held the row minimum, so
-    //          its magnitude is B (A elsewhere); Ab[p] bytes: A_a, B_a, A_b,
+    //   1-bit (Sec. V): St[p][k] for slots j = 8k + i: bit i / 16+i: sign of
+    //          slot j's own extrinsic t in row a / b; bit 8+i / 24+i: slot j
+    //          held the row minimum, so its magnitude is B (A elsewhere); Ab[p]
+    //          bytes: A_a, B_a, A_b,
     //          B_b, signed by the row's sign parity.  A message is then the
     //          stored sign times the signed A or B, exactly the Sec. V message
     //          s_mn f(A, B): the row parity moves from every per-edge sign bit
     //          into the per-row A and B (s_mn = own sign XOR parity).
     uint32_t Lw[RP][ONEBIT ? 1 : W];
-    uint32_t St[RP], Ab[RP];
+    uint32_t St[RP][NS], Ab[RP];
 #pragma unroll
     for (int p = 0; p < RP; ++p) {
-        St[p] = 0u;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) St[p][k] = 0u;
         Ab[p] = 0u;
 #pragma unroll
         for (int i = 0; i < (ONEBIT ? 1 : W); ++i) Lw[p][i] = 0x40404040u;
@@ -211,9 +213,10 @@ __global__ void __launch_bounds__(T) ss_pk_kernel(DecodeArgs a) {
             __builtin_amdgcn_sched_barrier(0);
             uint32_t acc_a[D], acc_b[D], t2[D], lo2[D], mg2[D], h2[D];
             u16x2 min1 = {0xFFFF, 0xFFFF}, min2 = {0xFFFF, 0xFFFF};
-            uint32_t Sp = 0, Aold = 0, Bold = 0;
+            uint32_t Sp[NS], Aold = 0, Bold = 0;
+#pragma unroll
+            for (int k = 0; k < NS; ++k) Sp[k] = ONEBIT ? St[p][k] : 0u;
             if (ONEBIT) {  // signed bytes to 16-bit halves
-                Sp = St[p];
                 Aold = bits(as_i(bits(as_u(Ab[p]) << (u16x2){8, 8})) >> (i16x2){8, 8});
                 Bold = bits(as_i(Ab[p] & 0xFF00FF00u) >> (i16x2){8, 8});
             }
@@ -234,9 +237,10 @@ __global__ void __launch_bounds__(T) ss_pk_kernel(DecodeArgs a) {
                     // L_old = s * (slot held the minimum ? B : A), rebuilt per
                     // 16-bit half from the state bits (Eqs. 4-5 inverted)
                     constexpr unsigned short kS = 15, kI = 7;
-                    const unsigned short ss = (unsigned short)(kS - j), si = (unsigned short)(kI - j);
-                    const i16x2 sm = as_i(bits(as_u(Sp) << (u16x2){ss, ss})) >> (i16x2){15, 15};
-                    const uint32_t im = bits(as_i(bits(as_u(Sp) << (u16x2){si, si})) >> (i16x2){15, 15});
+                    const uint32_t Sj = Sp[j >> 3];
+                    const unsigned short ss = (unsigned short)(kS - (j & 7)), si = (unsigned short)(kI - (j & 7));
+                    const i16x2 sm = as_i(bits(as_u(Sj) << (u16x2){ss, ss})) >> (i16x2){15, 15};
+                    const uint32_t im = bits(as_i(bits(as_u(Sj) << (u16x2){si, si})) >> (i16x2){15, 15});
                     // an explicit bit-select keeps im a mask (no per-half
                     // compares) without fencing the schedule between slots
                     const uint32_t mo = __builtin_amdgcn_bitop3_b32(im, Bold, Aold, 0xCA);  // a ? b : c
@@ -293,7 +297,9 @@ __global__ void __launch_bounds__(T) ss_pk_kernel(DecodeArgs a) {
                 asm volatile("" : "+v"(A2), "+v"(Cs), "+v"(mn1));
             }
             uint32_t nl[D];
-            uint32_t Sn = 0;
+            uint32_t Sn[NS];
+#pragma unroll
+            for (int k = 0; k < NS; ++k) Sn[k] = 0u;
 #pragma unroll
             for (int j = 0; j < D; ++j) {
                 i16x2 lb;
@@ -307,8 +313,9 @@ __global__ void __launch_bounds__(T) ss_pk_kernel(DecodeArgs a) {
                     lb = as_i(mag) * sg + (i16x2){64, 64};
                     if (ONEBIT) {  // keep the own-extrinsic sign and the minimum flag
                         const uint32_t sneg = bits(as_i(t2[j]) >> (i16x2){15, 15});
-                        Sn = __builtin_amdgcn_bitop3_b32(sneg, 0x00010001u << j, Sn, 0xEA);  // (a & b) | c
-                        Sn = __builtin_amdgcn_bitop3_b32(nsel, 0x01000100u << j, Sn, 0xAE);  // (~a & b) | c
+                        uint32_t &S = Sn[j >> 3];
+                        S = __builtin_amdgcn_bitop3_b32(sneg, 0x00010001u << (j & 7), S, 0xEA);  // (a & b) | c
+                        S = __builtin_amdgcn_bitop3_b32(nsel, 0x01000100u << (j & 7), S, 0xAE);  // (~a & b) | c
                     }
                 } else {
                     const i16x2 mag =
@@ -326,9 +333,13 @@ __global__ void __launch_bounds__(T) ss_pk_kernel(DecodeArgs a) {
                 lds_add(acc_b[j] >> 5, (uint32_t)db << (acc_b[j] & 31u));
             }
             if (ONEBIT) {
-                St[p] = Sn;
+#pragma unroll
+                for (int k = 0; k < NS; ++k) {
+                    St[p][k] = Sn[k];
+                    asm volatile("" : "+v"(St[p][k]));
+                }
                 Ab[p] = __builtin_amdgcn_perm(B2, A2, 0x06020400u);  // low bytes of the signed halves
-                asm volatile("" : "+v"(St[p]), "+v"(Ab[p]));
+                asm volatile("" : "+v"(Ab[p]));
             } else {
 #pragma unroll
                 for (int i = 0; i < W; ++i) {
@@ -433,11 +444,10 @@ hipError_t launch_one(const DecodeArgs &a, size_t lds, hipStream_t s) {
 }  // namespace
 
 // Instantiated (slots per row, rows per thread, threads) shapes of the packed
-// kernel.  Rows of up to 8 slots run 1024 threads (int8 and 1-bit), or 256 for
-// codes of at most 512 / 1024 checks, so that a CU holds several frames; wider
-// rows (int8 only: the 1-bit state keeps 8 slots per half) keep 6 D registers
-// per row pair live, so they run 768 threads, whose 3 waves per SIMD leave
-// each wave up to 168 VGPRs.
+// kernel (int8 and 1-bit).  Rows of up to 8 slots run 1024 threads, or 256
+// for codes of at most 512 / 1024 checks, so that a CU holds several frames;
+// wider rows keep 6 D registers per row pair live, so they run 768 threads,
+// whose 3 waves per SIMD leave each wave up to 168 VGPRs.
 #define LDPC_PK_SHAPES(X) \
     X(6, 2, 256)          \
     X(8, 2, 256)          \
@@ -471,12 +481,8 @@ template <int D, int R, int T>
 hipError_t launch_shape(const DecodeArgs &a, bool onebit, size_t lds, hipStream_t s) {
     // the fused check needs at least one iteration and no posterior output
     const bool fused = a.early_stop && a.llr_out == nullptr && a.max_iter >= 1;
-    if constexpr (D <= 8) {
-        if (onebit)
-            return fused ? launch_one<D, R, true, true, T>(a, lds, s) : launch_one<D, R, true, false, T>(a, lds, s);
-    } else {
-        if (onebit) return hipErrorInvalidValue;
-    }
+    if (onebit)
+        return fused ? launch_one<D, R, true, true, T>(a, lds, s) : launch_one<D, R, true, false, T>(a, lds, s);
     return fused ? launch_one<D, R, false, true, T>(a, lds, s) : launch_one<D, R, false, false, T>(a, lds, s);
 }
 }  // namespace
