@@ -67,10 +67,10 @@ MEASURED_TRAFFIC = [
      "bytes": 105147.1e6, "profile": "profiles/fl_f32_ira64800_512f.md"},
     {"kernel": "reg1", "hash": "e7d86239f37f995e", "workload": ("int8", "single_scan", 512, 50),
      "bytes": 221.2e6, "profile": "profiles/ss_reg_int8_ira64800_512f.md"},
-    {"kernel": "two_scan_frames", "hash": "cbfdbc070410dda8", "workload": ("int8", "two_scan", 512, 50),
-     "bytes": 29395.0e6, "profile": "profiles/ts_fl_int8_ira64800_512f.md"},
-    {"kernel": "two_scan_frames", "hash": "cbfdbc070410dda8", "workload": ("fp32", "two_scan", 512, 50),
-     "bytes": 107935.3e6, "profile": "profiles/ts_fl_f32_ira64800_512f.md"},
+    {"kernel": "two_scan_frames", "hash": "f38ce1eb2e646923", "workload": ("int8", "two_scan", 512, 50),
+     "bytes": 29393.9e6, "profile": "profiles/ts_fl_int8_ira64800_512f.md"},
+    {"kernel": "two_scan_frames", "hash": "f38ce1eb2e646923", "workload": ("fp32", "two_scan", 512, 50),
+     "bytes": 107936.3e6, "profile": "profiles/ts_fl_f32_ira64800_512f.md"},
 ]
 
 

@@ -345,6 +345,222 @@ __global__ void __launch_bounds__(kBlock) ts_vars(TsArgs a, int fail_row) {
     }
 }
 
+// int8 with four frames per lane: two frames per 32-bit register in 16-bit
+// halves (packed VALU), four int8 messages per 4-byte access, four int16
+// posteriors per 8-byte access.  Same arithmetic as the kernels above.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ u16x2 as_u(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
+__device__ __forceinline__ i16x2 as_i(uint32_t v) { return __builtin_bit_cast(i16x2, v); }
+__device__ __forceinline__ uint32_t bits(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+__device__ __forceinline__ uint32_t bits(i16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+// four int8 of frames 0..3 -> (frames 0, 1) and (frames 2, 3), sign-extended
+// 16-bit halves: each byte moved to the top of its half, then shifted back
+__device__ __forceinline__ void unpack4(uint32_t x, uint32_t &p0, uint32_t &p1) {
+    p0 = bits(as_i(__builtin_amdgcn_perm(x, x, 0x010c000cu)) >> (i16x2){8, 8});
+    p1 = bits(as_i(__builtin_amdgcn_perm(x, x, 0x030c020cu)) >> (i16x2){8, 8});
+}
+// the low byte of each half of (frames 0, 1), (frames 2, 3) -> four int8
+__device__ __forceinline__ uint32_t pack4(uint32_t p0, uint32_t p1) {
+    return __builtin_amdgcn_perm(p1, p0, 0x06040200u);
+}
+
+template <int DMAX, bool UPDATE, bool FIRST>
+__global__ void __launch_bounds__(kBlock) ts_rows_i8x4(TsArgs a, int syn_row, int conv_k) {
+    const int lane = threadIdx.x & 63;
+    const int w = wave_id();
+    const int Fp = a.Fp;
+    if (conv_k >= 1 && w == 0) fold_conv(a.conv, a.fail, conv_k, Fp, lane);
+    if (w >= a.rwaves * a.G) return;
+    const int g = w % a.G;
+    const uint32_t f0 = (uint32_t)((g * 64 + lane) * 4);  // first frame of the lane
+    const uint32_t foe = f0, foz = f0 * 2u;
+    const uint32_t rowe = (uint32_t)Fp, rowz = (uint32_t)Fp * 2u;
+    const Buf b0(a.z0, a.z0bytes), bn(a.zn, a.znbytes), bm(a.zmn, a.ebytes), bl(a.L, a.ebytes);
+    const auto *rp = cptr(a.row_ptr);
+    const auto *re = cptr(a.row_ent);
+    const bool syn_on = syn_row >= 0;
+    // A, B = max(((m a8 + 128) >> 8) - b, 0) per half: m <= 127 keeps the
+    // product below 2^15; offsets past 255 steps zero every magnitude anyway
+    const u16x2 a8x2 = (u16x2){(unsigned short)a.a8, (unsigned short)a.a8};
+    const short bq = (short)min(a.b_int, 255);
+    const i16x2 bx2 = (i16x2){bq, bq};
+    for (int m = w / a.G; m < a.M; m += a.rwaves) {
+        const int e0 = rp[m];
+        const int d = rp[m + 1] - e0;
+        uint32_t vo0[DMAX], voz[DMAX], epos[DMAX];
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j) {
+            const uint32_t nv = re[2 * (e0 + j)];
+            vo0[j] = j < d ? nv * rowe : kOutOfRange;
+            voz[j] = j < d ? nv * rowz : kOutOfRange;
+            epos[j] = j < d ? (uint32_t)(e0 + j) * rowe : kOutOfRange;
+        }
+        uint32_t x[DMAX], za[DMAX], zb[DMAX];
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j) {
+            if (UPDATE)
+                x[j] = FIRST ? __builtin_amdgcn_raw_buffer_load_b32(b0.r, foe, vo0[j], 0)
+                             : __builtin_amdgcn_raw_buffer_load_b32(bm.r, foe, epos[j], 0);
+            if (syn_on) {
+                const auto zz = __builtin_amdgcn_raw_buffer_load_b64(bn.r, foz, voz[j], 0);
+                za[j] = zz[0];
+                zb[j] = zz[1];
+            }
+        }
+        if (syn_on) {  // bits 15 / 31: odd number of Z_n <= 0 in the row (Z_n - 1 < 0)
+            uint32_t h0 = 0, h1 = 0;
+#pragma unroll
+            for (int j = 0; j < DMAX; ++j) {
+                if (j < d) {
+                    h0 ^= bits(as_i(za[j]) - (i16x2){1, 1});
+                    h1 ^= bits(as_i(zb[j]) - (i16x2){1, 1});
+                }
+            }
+            const uint32_t hb[4] = {h0 & 0x8000u, h0 & 0x80000000u, h1 & 0x8000u, h1 & 0x80000000u};
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (hb[c]) a.fail[(size_t)syn_row * Fp + f0 + c] = 1;
+        }
+        if (UPDATE) {
+            uint32_t t[2][DMAX], mg[2][DMAX];
+            u16x2 mn1[2] = {{255, 255}, {255, 255}}, mn2[2] = {{255, 255}, {255, 255}};
+            uint32_t par[2] = {0u, 0u};
+#pragma unroll
+            for (int j = 0; j < DMAX; ++j) {
+                unpack4(x[j], t[0][j], t[1][j]);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    // slots past the row's end read 0: no sign, magnitude forced to 255
+                    par[h] ^= t[h][j];
+                    const i16x2 tv = as_i(t[h][j]);
+                    const u16x2 av = j < d ? as_u(bits(__builtin_elementwise_max(tv, -tv))) : (u16x2){255, 255};
+                    mg[h][j] = bits(av);
+                    mn2[h] = __builtin_elementwise_min(mn2[h], __builtin_elementwise_max(mn1[h], av));
+                    mn1[h] = __builtin_elementwise_min(mn1[h], av);
+                }
+            }
+            uint32_t A[2], B[2], ps[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                A[h] = bits(__builtin_elementwise_max(
+                    as_i(bits((mn1[h] * a8x2 + (u16x2){128, 128}) >> (u16x2){8, 8})) - bx2, (i16x2){0, 0}));
+                B[h] = bits(__builtin_elementwise_max(
+                    as_i(bits((mn2[h] * a8x2 + (u16x2){128, 128}) >> (u16x2){8, 8})) - bx2, (i16x2){0, 0}));
+                ps[h] = bits(as_i(par[h]) >> (i16x2){15, 15});
+            }
+#pragma unroll
+            for (int j = 0; j < DMAX; ++j) {
+                uint32_t L[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    // |t_j| >= min1: (min1 - |t_j|) >> 15 is 0 at the minimum (B there,
+                    // and at a tie, where B = A) and -1 elsewhere (A)
+                    const uint32_t nsel =
+                        bits(as_i(bits(mn1[h] - as_u(mg[h][j]))) >> (i16x2){15, 15});
+                    const uint32_t mag = __builtin_amdgcn_bitop3_b32(nsel, A[h], B[h], 0xCA);  // nsel ? A : B
+                    const uint32_t sg = __builtin_amdgcn_bitop3_b32(bits(as_i(t[h][j]) >> (i16x2){15, 15}), ps[h],
+                                                                     0x00010001u, 0xBE);  // (a ^ b) | c
+                    L[h] = bits(as_i(mag) * as_i(sg));
+                }
+                __builtin_amdgcn_raw_buffer_store_b32(pack4(L[0], L[1]), bl.r, foe, epos[j], 0);
+            }
+        }
+    }
+}
+
+template <bool FREEZE>
+__global__ void __launch_bounds__(kBlock) ts_vars_i8x4(TsArgs a, int fail_row) {
+    const int lane = threadIdx.x & 63;
+    const int w = wave_id();
+    const int Fp = a.Fp;
+    if (w >= a.rwaves * a.G) return;
+    const int g = w % a.G;
+    const uint32_t f0 = (uint32_t)((g * 64 + lane) * 4);
+    const uint32_t foe = f0, foz = f0 * 2u;
+    const uint32_t rowe = (uint32_t)Fp, rowz = (uint32_t)Fp * 2u;
+    const Buf b0(a.z0, a.z0bytes), bn(a.zn, a.znbytes), bm(a.zmn, a.ebytes), bl(a.L, a.ebytes);
+    // frozen frames keep Z_n: a mask per 16-bit half selects their old value
+    uint32_t fm[2] = {0u, 0u};
+    bool any_frozen = false;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const bool fz = FREEZE && (a.conv[f0 + c] != kNotConverged || a.fail[(size_t)fail_row * Fp + f0 + c] == 0);
+        if (fz) fm[c >> 1] |= (c & 1) ? 0xFFFF0000u : 0x0000FFFFu;
+        any_frozen = any_frozen || fz;
+    }
+    const uint32_t fc = (FREEZE && any_frozen) ? foz : kOutOfRange;
+    const auto *vp = cptr(a.vc_ptr);
+    const auto *vcs = cptr(a.vc_csr);
+    // Z_mn = sat(Z_n - L_mn) to +-Q for both pairs, stored as four int8
+    auto st_ext = [&](const uint32_t (&sz)[2], const uint32_t (&lv)[2], uint32_t off) {
+        uint32_t e[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            e[h] = bits(__builtin_elementwise_min(
+                __builtin_elementwise_max(as_i(sz[h]) - as_i(lv[h]), (i16x2){-kQmax, -kQmax}), (i16x2){kQmax, kQmax}));
+        __builtin_amdgcn_raw_buffer_store_b32(pack4(e[0], e[1]), bm.r, foe, off, 0);
+    };
+    for (int n = w / a.G; n < a.N; n += a.rwaves) {
+        const int e0 = vp[n], e1 = vp[n + 1];
+        uint32_t sz[2], cp[2] = {0u, 0u};
+        unpack4(__builtin_amdgcn_raw_buffer_load_b32(b0.r, foe, (uint32_t)n * rowe, 0), sz[0], sz[1]);
+        if (FREEZE) {
+            const auto c2 = __builtin_amdgcn_raw_buffer_load_b64(bn.r, fc, (uint32_t)n * rowz, 0);
+            cp[0] = c2[0];
+            cp[1] = c2[1];
+        }
+        uint32_t l[8][2];
+        uint32_t eo[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) eo[i] = kOutOfRange;
+        // Z_n: eight messages per step, all loads in flight together; slots
+        // past the last edge are out of range and skipped (nothing is added)
+        for (int e = e0; e < e1; e += 8) {
+            uint32_t raw[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const uint32_t ce = vcs[e + i];
+                eo[i] = e + i < e1 ? ce * rowe : kOutOfRange;
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) raw[i] = __builtin_amdgcn_raw_buffer_load_b32(bl.r, foe, eo[i], 0);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                unpack4(raw[i], l[i][0], l[i][1]);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) sz[h] = e + i < e1 ? bits(as_i(sz[h]) + as_i(l[i][h])) : sz[h];
+            }
+        }
+        {
+            typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+            const u32x2 zn = {(uint32_t)__builtin_amdgcn_bitop3_b32(fm[0], cp[0], sz[0], 0xCA),  // frozen ? old : new
+                              (uint32_t)__builtin_amdgcn_bitop3_b32(fm[1], cp[1], sz[1], 0xCA)};
+            __builtin_amdgcn_raw_buffer_store_b64(zn, bn.r, foz, (uint32_t)n * rowz, 0);
+        }
+        // extrinsics: a variable of degree <= 8 still holds its messages and
+        // their offsets in registers (out-of-range slots are dropped stores);
+        // larger degrees read them again
+        if (e1 - e0 <= 8) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) st_ext(sz, l[i], eo[i]);
+        } else {
+            for (int e = e0; e < e1; e += 8) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const uint32_t ce = vcs[e + i];
+                    eo[i] = e + i < e1 ? ce * rowe : kOutOfRange;
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    unpack4(__builtin_amdgcn_raw_buffer_load_b32(bl.r, foe, eo[i], 0), l[i][0], l[i][1]);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) st_ext(sz, l[i], eo[i]);
+            }
+        }
+    }
+}
+
 template <bool INT, int DMAX, int V>
 hipError_t run(const DecodeArgs &d, const TsArgs &a, int K, unsigned grid, hipStream_t s) {
     using Tin = typename std::conditional<INT, int8_t, float>::type;
@@ -360,22 +576,40 @@ hipError_t run(const DecodeArgs &d, const TsArgs &a, int K, unsigned grid, hipSt
     const int64_t nz = (int64_t)a.N * a.Fp;
     hipLaunchKernelGGL((widen_z0<Tin, Tz>), dim3((unsigned)std::min<int64_t>((nz + kBlock - 1) / kBlock, 65536)),
                        dim3(kBlock), 0, s, static_cast<const Tin *>(a.z0), static_cast<Tz *>(a.zn), nz);
+    constexpr bool kPacked = INT && V == 4;  // two frames per register
     for (int k = 1; k <= K; ++k) {
         const int syn_row = (es && k >= 2) ? k - 1 : -1;
         const int conv_k = (es && k >= 3) ? k - 2 : 0;
-        if (k == 1)
-            hipLaunchKernelGGL((ts_rows<INT, DMAX, true, true, V>), dim3(grid), dim3(kBlock), 0, s, a, syn_row,
-                               conv_k);
-        else
-            hipLaunchKernelGGL((ts_rows<INT, DMAX, true, false, V>), dim3(grid), dim3(kBlock), 0, s, a, syn_row,
-                               conv_k);
-        if (es && k >= 2)
-            hipLaunchKernelGGL((ts_vars<INT, true, V>), dim3(grid), dim3(kBlock), 0, s, a, k - 1);
-        else
-            hipLaunchKernelGGL((ts_vars<INT, false, V>), dim3(grid), dim3(kBlock), 0, s, a, 0);
+        if constexpr (kPacked) {
+            if (k == 1)
+                hipLaunchKernelGGL((ts_rows_i8x4<DMAX, true, true>), dim3(grid), dim3(kBlock), 0, s, a, syn_row,
+                                   conv_k);
+            else
+                hipLaunchKernelGGL((ts_rows_i8x4<DMAX, true, false>), dim3(grid), dim3(kBlock), 0, s, a, syn_row,
+                                   conv_k);
+            if (es && k >= 2)
+                hipLaunchKernelGGL((ts_vars_i8x4<true>), dim3(grid), dim3(kBlock), 0, s, a, k - 1);
+            else
+                hipLaunchKernelGGL((ts_vars_i8x4<false>), dim3(grid), dim3(kBlock), 0, s, a, 0);
+        } else {
+            if (k == 1)
+                hipLaunchKernelGGL((ts_rows<INT, DMAX, true, true, V>), dim3(grid), dim3(kBlock), 0, s, a, syn_row,
+                                   conv_k);
+            else
+                hipLaunchKernelGGL((ts_rows<INT, DMAX, true, false, V>), dim3(grid), dim3(kBlock), 0, s, a, syn_row,
+                                   conv_k);
+            if (es && k >= 2)
+                hipLaunchKernelGGL((ts_vars<INT, true, V>), dim3(grid), dim3(kBlock), 0, s, a, k - 1);
+            else
+                hipLaunchKernelGGL((ts_vars<INT, false, V>), dim3(grid), dim3(kBlock), 0, s, a, 0);
+        }
     }
-    hipLaunchKernelGGL((ts_rows<INT, DMAX, false, false, V>), dim3(grid), dim3(kBlock), 0, s, a, K,
-                       (es && K >= 3) ? K - 2 : 0);
+    if constexpr (kPacked)
+        hipLaunchKernelGGL((ts_rows_i8x4<DMAX, false, false>), dim3(grid), dim3(kBlock), 0, s, a, K,
+                           (es && K >= 3) ? K - 2 : 0);
+    else
+        hipLaunchKernelGGL((ts_rows<INT, DMAX, false, false, V>), dim3(grid), dim3(kBlock), 0, s, a, K,
+                           (es && K >= 3) ? K - 2 : 0);
     hipLaunchKernelGGL(frame_out, dim3((unsigned)((a.F + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a.fail, a.conv,
                        a.F, a.Fp, K, d.early_stop, d.iters_out, d.ok_out);
     hipLaunchKernelGGL(transpose_out<Tz>, tgrid, dim3(kBlock), 0, s, static_cast<const Tz *>(a.zn), a.N, a.F, a.Fp,
