@@ -93,9 +93,10 @@ ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl)
         return fail(LDPC_EUNSUPPORTED, "7-8 bit messages run on the LDS/HBM kernel only");
     // AUTO for fixed point (measured on MI355X, 50 iterations): the packed
     // two-rows-per-lane kernel pays off from 16 rows per thread (M > 8192),
-    // from 8 rows per thread for the 1-bit state, for rows wider than 8 slots
-    // (int8 only) and with its 256-thread shapes for small codes; otherwise
-    // the one-row register kernel is faster, and other codes of at most 1024
+    // from 8 rows per thread for rows of up to 7 slots (two frames per CU) and
+    // for the 1-bit state, for rows wider than 8 slots that fill the 21-slot
+    // shape and with its 256-thread shapes for small codes; otherwise the
+    // one-row register kernel is faster, and other codes of at most 1024
     // checks run best LDS-resident with one thread per row (the register
     // kernels give every frame 1024 threads).
     const bool small_pk = c->pkD > 0 && c->pkT <= 256;  // packed shape with small workgroups
@@ -105,7 +106,7 @@ ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl)
         (layout == LDPC_LAYOUT_AUTO || reg_layout)) {
         const bool packed = c->pkD > 0 && layout != LDPC_LAYOUT_REG1 &&
                             (layout == LDPC_LAYOUT_REG || c->pkR >= 16 || wide_pk || small_pk ||
-                             (p->msg == LDPC_MSG_1BIT && c->pkR >= 8));
+                             (c->pkR >= 8 && (p->msg == LDPC_MSG_1BIT || c->pkD <= 7)));
         const bool ok = packed || c->regD > 0;
         if (ok) {
             pl->family = packed ? 4 : 3;

@@ -111,8 +111,19 @@ __device__ __forceinline__ void refresh3(const uint32_t *zacc, uint8_t *zold, in
     }
 }
 
+// Shapes of 1024 threads with at most 8 rows per thread and 7 slots ask for
+// 8 waves per SIMD (at most 64 VGPRs): with the small LDS of such codes two
+// frames then share a CU, and one frame's barriers hide behind the other's
+// work (IRA N=16200, 2048 frames: int8 3.33 -> 2.57 ms, 1-bit 4.04 -> 3.32
+// ms; the int8 form spills 16 bytes per thread for it).
+template <int D, int R, int T>
+constexpr int pk_waves_per_eu() {
+    return (T == 1024 && R <= 8 && D <= 7) ? 8 : 1;
+}
+
 template <int D, int R, bool ONEBIT, bool FUSED, int T>
-__global__ void __launch_bounds__(T) ss_pk_kernel(DecodeArgs a) {
+__global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(pk_waves_per_eu<D, R, T>())))
+ss_pk_kernel(DecodeArgs a) {
     constexpr int kT = T;  // threads per workgroup (one frame)
     static_assert(R % 2 == 0, "rows are processed in pairs");
     constexpr int RP = R / 2;        // row pairs per thread

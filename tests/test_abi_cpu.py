@@ -430,7 +430,7 @@ def test_decode_plan_matches_workspace_and_forced_layout(L, name):
     c.close()
     expect = {"peg1008": {"packed", "generic_f32", "two_scan"},
               "qc7493": {"packed", "f32_frames", "two_scan", "two_scan_frames"},
-              "ira16200": {"reg1", "packed", "f32_frames", "two_scan", "two_scan_frames"},
+              "ira16200": {"packed", "f32_frames", "two_scan", "two_scan_frames"},
               "ira64800": {"packed", "f32_frames", "two_scan_frames"}}[name]
     assert seen == expect
 
