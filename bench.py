@@ -29,6 +29,9 @@ if ROOT not in sys.path:
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+# context variants of the default run: calls timed after warm-up calls (the
+# first calls after a switch of kernel run slower)
+VAR_STEPS, VAR_WARMUP = 10, 3
 # Packed 16-bit integer VALU rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2
 # (two 16-bit operations per lane per instruction) x 2.4 GHz.
 ALU16_PEAK_TOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
@@ -262,17 +265,17 @@ def main():
             if (msg, sched) == (args.msg, args.sched):
                 continue
             log(f"[bench] variant {msg} {sched}")
-            v = run(msg, sched, 5, 1)
+            v = run(msg, sched, VAR_STEPS, VAR_WARMUP)
             var[f"{msg}_{sched}"] = {"coded_gbps": round(v["gbps"], 4),
                                      "edge_updates_per_s": v["eups"],
-                                     "ms_per_step": round(v["wall"] / 5 * 1e3, 4),
+                                     "ms_per_step": round(v["wall"] / VAR_STEPS * 1e3, 4),
                                      "hbm_frac_alg": round(v["alg_bytes"] / v["kernel_s"] / 1e9 / HBM_PEAK_GBS, 4)}
         log("[bench] early-stop regime")
         # the early-stop regime as a FER measurement runs it: hard decisions only
-        v = run(args.msg, args.sched, 5, 1, early_stop=True, with_llr=False)
+        v = run(args.msg, args.sched, VAR_STEPS, VAR_WARMUP, early_stop=True, with_llr=False)
         var["early_stop"] = {"coded_gbps": round(v["gbps"], 4),
                              "avg_iters": v["iters"] / F, "fer": 1.0 - v["ok"] / F,
-                             "ms_per_step": round(v["wall"] / 5 * 1e3, 4), "outputs": "hard decisions"}
+                             "ms_per_step": round(v["wall"] / VAR_STEPS * 1e3, 4), "outputs": "hard decisions"}
         res["variants"] = var
     if not args.no_cpu_baseline:
         threads = max(1, min(16, os.cpu_count() or 1))
