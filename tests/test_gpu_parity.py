@@ -131,7 +131,7 @@ def test_random_small_codes(torch_dev, L, orc, variant, layout):
             lay = layout
             if layout == "reg1":
                 rs = L.Code.from_parity_check(code, device=-1).info()["reg_slots"]
-                if variant[1] != "single_scan" or rs == 0 or (variant[0] == "1bit" and rs + 15 > 32):
+                if variant[1] != "single_scan" or rs == 0:
                     lay = "auto"
             _run_pair(torch_dev, L, orc, code, x, variant, max_iter=int(rng.integers(0, 12)),
                       alpha=alpha, beta=beta, early_stop=es, layout=lay)
@@ -159,6 +159,7 @@ def test_ira16200(torch_dev, L, orc, variant, layout):
 
 @pytest.mark.parametrize("variant,layout", [(VARIANTS[0], "auto"), (VARIANTS[0], "reg1"), (VARIANTS[0], "lds"),
                                             (VARIANTS[0], "hbm"), (VARIANTS[1], "lds"), (VARIANTS[1], "auto"),
+                                            (VARIANTS[1], "reg1"),
                                             (VARIANTS[3], "auto"), (VARIANTS[2], "auto")],
                          ids=lambda v: v if isinstance(v, str) else f"{v[0]}-{v[1]}")
 def test_qc7493_batch_sampled(torch_dev, L, orc, variant, layout):
@@ -347,7 +348,7 @@ ES_CODES = {"peg1008": W.code_c0_peg1008, "ira16200": W.code_ira16200, "qc7493":
 ES_CASES = [("peg1008", "int8", "auto"), ("peg1008", "1bit", "auto"), ("peg1008", "int8", "hbm"),
             ("peg1008", "int8", "reg1"), ("peg1008", "1bit", "reg1"), ("ira16200", "int8", "reg"),
             ("ira16200", "1bit", "reg"), ("ira16200", "int8", "reg1"), ("qc7493", "int8", "auto"),
-            ("qc7493", "1bit", "auto")]
+            ("qc7493", "1bit", "auto"), ("qc7493", "1bit", "reg1")]
 
 
 def _spread_inputs(code, F, seed, lo=0.5, hi=3.5):
