@@ -175,21 +175,23 @@ ss_pk_kernel(DecodeArgs a) {
 
     // Message state of each row pair.
     //   int8:  Lw[p][i], bytes 2s / 2s+1: slot 2i+s of rows a / b, as L + 64.
-    //   1-bit (Sec. V): St[p][k] for slots j = 8k + i: bit i / 16+i: sign of
-    //          slot j's own extrinsic t in row a / b; bit 8+i / 24+i: slot j
-    //          held the row minimum, so its magnitude is B (A elsewhere); Ab[p]
-    //          bytes: A_a, B_a, A_b,
-    //          B_b, signed by the row's sign parity.  A message is then the
-    //          stored sign times the signed A or B, exactly the Sec. V message
-    //          s_mn f(A, B): the row parity moves from every per-edge sign bit
-    //          into the per-row A and B (s_mn = own sign XOR parity).
+    //   1-bit (Sec. V): St[p][k] for slots j = 8k + i: bit 2i / 16+2i: slot
+    //          j held the row minimum in row a / b, so its magnitude is B (A
+    //          elsewhere); bit 2i+1 / 17+2i: sign of slot j's own extrinsic t;
+    //          Ab[p] bytes: A_a, A_b, B_a, B_b signed by the row's sign
+    //          parity, plus 64.  A message is then the stored sign times the
+    //          signed A or B, exactly the Sec. V message s_mn f(A, B): the row
+    //          parity moves from every per-edge sign bit into the per-row A
+    //          and B (s_mn = own sign XOR parity).  The two bits of a slot
+    //          index a four-entry byte table per row (+A, +B, -A, -B, plus
+    //          64), so one permute rebuilds the old message pair.
     uint32_t Lw[RP][ONEBIT ? 1 : W];
     uint32_t St[RP][NS], Ab[RP];
 #pragma unroll
     for (int p = 0; p < RP; ++p) {
 #pragma unroll
         for (int k = 0; k < NS; ++k) St[p][k] = 0u;
-        Ab[p] = 0u;
+        Ab[p] = 0x40404040u;  // A = B = 0
 #pragma unroll
         for (int i = 0; i < (ONEBIT ? 1 : W); ++i) Lw[p][i] = 0x40404040u;
     }
@@ -202,6 +204,9 @@ ss_pk_kernel(DecodeArgs a) {
     // (a constant power of two would become a shift and a separate add)
     uint32_t k64 = 0x00400040u, kn64 = 0xFFC0FFC0u;
     asm volatile("" : "+s"(k64), "+s"(kn64));
+    // 1-bit table lookup: selector bytes 1 and 3 pick zero, byte 2 the second table
+    uint32_t kSelBase = 0x0c040c00u;
+    asm volatile("" : "+v"(kSelBase));
     int iters = 0;
     bool converged = false;  // the decision of the last completed iteration is a codeword
     bool conv_prev = false;  // FUSED: that of the iteration before the last one is
@@ -224,12 +229,15 @@ ss_pk_kernel(DecodeArgs a) {
             __builtin_amdgcn_sched_barrier(0);
             uint32_t acc_a[D], acc_b[D], t2[D], lo2[D], mg2[D], h2[D];
             u16x2 min1 = {0xFFFF, 0xFFFF}, min2 = {0xFFFF, 0xFFFF};
-            uint32_t Sp[NS], Aold = 0, Bold = 0;
+            uint32_t Sp[NS], LUTa = 0, LUTb = 0;
 #pragma unroll
             for (int k = 0; k < NS; ++k) Sp[k] = ONEBIT ? St[p][k] : 0u;
-            if (ONEBIT) {  // signed bytes to 16-bit halves
-                Aold = bits(as_i(bits(as_u(Ab[p]) << (u16x2){8, 8})) >> (i16x2){8, 8});
-                Bold = bits(as_i(Ab[p] & 0xFF00FF00u) >> (i16x2){8, 8});
+            if (ONEBIT) {
+                // per row, the bytes +A, +B, -A, -B (each plus 64): Ab holds the
+                // positive ones; 128 - x negates a biased byte with no borrow
+                const uint32_t Nb = 0x80808080u - Ab[p];
+                LUTa = __builtin_amdgcn_perm(Nb, Ab[p], 0x06040200u);
+                LUTb = __builtin_amdgcn_perm(Nb, Ab[p], 0x07050301u);
             }
 #pragma unroll
             for (int j = 0; j < D; ++j) {
@@ -245,17 +253,14 @@ ss_pk_kernel(DecodeArgs a) {
                 if (FUSED) h2[j] = bits(as_i(z2) - (i16x2){65, 65});
                 uint32_t l2;
                 if (ONEBIT) {
-                    // L_old = s * (slot held the minimum ? B : A), rebuilt per
-                    // 16-bit half from the state bits (Eqs. 4-5 inverted)
-                    constexpr unsigned short kS = 15, kI = 7;
-                    const uint32_t Sj = Sp[j >> 3];
-                    const unsigned short ss = (unsigned short)(kS - (j & 7)), si = (unsigned short)(kI - (j & 7));
-                    const i16x2 sm = as_i(bits(as_u(Sj) << (u16x2){ss, ss})) >> (i16x2){15, 15};
-                    const uint32_t im = bits(as_i(bits(as_u(Sj) << (u16x2){si, si})) >> (i16x2){15, 15});
-                    // an explicit bit-select keeps im a mask (no per-half
-                    // compares) without fencing the schedule between slots
-                    const uint32_t mo = __builtin_amdgcn_bitop3_b32(im, Bold, Aold, 0xCA);  // a ? b : c
-                    l2 = bits(as_i(mo) * (sm | (i16x2){1, 1}) + (i16x2){64, 64});
+                    // L_old = s * (slot held the minimum ? B : A) + 64 (Eqs. 4-5
+                    // inverted): the slot's two bits per row (flag, sign) become
+                    // the table index in bytes 0 and 2 of a permute selector
+                    // (bytes 1 and 3 select zero), one table per row
+                    const unsigned short sh = (unsigned short)(2 * (j & 7));
+                    const uint32_t x = bits(as_u(Sp[j >> 3]) >> (u16x2){sh, sh});
+                    const uint32_t sel = __builtin_amdgcn_bitop3_b32(x, 0x00030003u, kSelBase, 0xEA);  // (a & b) | c
+                    l2 = __builtin_amdgcn_perm(LUTb, LUTa, sel);
                 } else {
                     l2 = pair_of(Lw[p][j >> 1], j & 1);
                 }
@@ -325,8 +330,8 @@ ss_pk_kernel(DecodeArgs a) {
                     if (ONEBIT) {  // keep the own-extrinsic sign and the minimum flag
                         const uint32_t sneg = bits(as_i(t2[j]) >> (i16x2){15, 15});
                         uint32_t &S = Sn[j >> 3];
-                        S = __builtin_amdgcn_bitop3_b32(sneg, 0x00010001u << (j & 7), S, 0xEA);  // (a & b) | c
-                        S = __builtin_amdgcn_bitop3_b32(nsel, 0x01000100u << (j & 7), S, 0xAE);  // (~a & b) | c
+                        S = __builtin_amdgcn_bitop3_b32(sneg, 0x00020002u << (2 * (j & 7)), S, 0xEA);  // (a & b) | c
+                        S = __builtin_amdgcn_bitop3_b32(nsel, 0x00010001u << (2 * (j & 7)), S, 0xAE);  // (~a & b) | c
                     }
                 } else {
                     const i16x2 mag =
@@ -349,7 +354,9 @@ ss_pk_kernel(DecodeArgs a) {
                     St[p][k] = Sn[k];
                     asm volatile("" : "+v"(St[p][k]));
                 }
-                Ab[p] = __builtin_amdgcn_perm(B2, A2, 0x06020400u);  // low bytes of the signed halves
+                // low bytes of the signed halves plus 64: A_a, A_b, B_a, B_b
+                Ab[p] = __builtin_amdgcn_perm(bits(as_i(B2) + (i16x2){64, 64}), bits(as_i(A2) + (i16x2){64, 64}),
+                                              0x06040200u);
                 asm volatile("" : "+v"(Ab[p]));
             } else {
 #pragma unroll
