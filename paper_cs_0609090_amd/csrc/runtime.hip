@@ -474,9 +474,9 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
                     pT = t;
                 }
             }
-            // 10-bit fields are biased by 320 or 576 (both 64 mod 256: the low
-            // byte of a field clamped to bias +- 62 is then Z_old + 64)
-            const int pbias = bestP == 1 ? 0 : bestP == 2 ? 32768 : span <= 320 ? 320 : span <= 447 ? 576 : -1;
+            // 10-bit fields are biased by 319 or 575 (both 63 mod 256: the low
+            // byte of a field clamped to bias +- 62 is then Z_old + 63)
+            const int pbias = bestP == 1 ? 0 : bestP == 2 ? 32768 : span <= 319 ? 319 : span <= 448 ? 575 : -1;
             if (pD < (1 << 30) && pbias >= 0) {
                 c->pkD = pD;
                 c->pkR = pR;

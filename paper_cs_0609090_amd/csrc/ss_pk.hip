@@ -6,7 +6,7 @@
 //
 //   thread t of T owns the rows a = p*T + t and b = (p + R/2)*T + t for
 //   p < R/2; for every slot j the pair (row a, row b) is one 16-bit lane pair:
-//     t2   = Zold2 - Lold2                  (v_pk_sub_i16; both stored +64)
+//     t2   = Zold2 - Lold2                  (v_pk_sub_i16; both stored +63)
 //     m2   = |t2|
 //     min2 = min(min2, max(min1, m2)), min1 = min(min1, m2)   (v_pk_*_u16)
 //     parity ^= t2                          (sign bits 15 and 31)
@@ -16,7 +16,7 @@
 //            (min1 - |t2|) >> 15 (wider rows and the 1-bit state)
 //   i.e. B where |t_j| equals the row minimum and A elsewhere: no argmin is
 //   needed, since a tie at the minimum forces min2 = min1 and so A = B.
-//     L2   = mag2 * (+-1: own sign XOR row parity) + 64, delta2 = L2 - Lold2
+//     L2   = mag2 * (+-1: own sign XOR row parity) + 63, delta2 = L2 - Lold2
 //   and one LDS atomic per edge adds the delta into the posterior field.
 //
 // Variables live in LDS "slots" chosen at code creation: slot s holds Z_old
@@ -30,13 +30,13 @@
 // The byte address/shift pair encodes any accumulator packing, so the kernel
 // needs no division by the field count; padding entries of short rows read
 // the dummy slot (Z_old at its maximum, never the row minimum) and add into a
-// private word per lane.  Z_old is stored as Z + 64 (bytes), messages as
-// L + 64.
+// private word per lane.  Z_old is stored as Z + 63 (bytes), messages as
+// L + 63: a stored Z_old byte has bit 6 clear exactly when Z_old <= 0.
 //
 // Early stop (FUSED, for callers that want hard decisions only): the gather
 // of iteration k already reads every Z^(k-1) byte, so the syndrome of the
-// hard decisions of Z^(k-1) is formed there (one packed subtract and a share
-// of a three-input XOR per slot pair) instead of in a separate pass over the
+// hard decisions of Z^(k-1) is formed there (a share of a three-input XOR of
+// the stored bytes per slot pair) instead of in a separate pass over the
 // rows.  When it is zero after iteration k, the frame stops with k-1
 // iterations and its decisions are read from Z_old, which saturation leaves
 // with the sign (and zero) of Z^(k-1).  The exact posteriors of Z^(k-1) are
@@ -47,6 +47,7 @@ namespace ldpc {
 namespace {
 
 constexpr uint32_t kRsrcWord3 = 0x00020000u;  // raw buffer, gfx9 family
+constexpr int kZB = 63;  // bias of the stored Z_old bytes and messages
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 typedef short i16x2 __attribute__((ext_vector_type(2)));
@@ -78,9 +79,9 @@ __device__ __forceinline__ uint32_t pair_of(uint32_t w, int s) {
 
 // Z_old bytes from the accumulator words, three 10-bit fields per word
 // biased by BIAS: four words (twelve slots) per step, one 16-byte LDS read
-// and three 4-byte writes.  BIAS is 64 mod 256, so the low byte of a field
+// and three 4-byte writes.  BIAS is 63 mod 256, so the low byte of a field
 // clamped to [BIAS - 62, BIAS + 62] (one v_med3_u32 with constant bounds) is
-// the saturated Z_old + 64.  Words past the last one are private padding
+// the saturated Z_old + 63.  Words past the last one are private padding
 // words (read, never used); bytes of slots >= N (unused, the dummy) are left
 // untouched.
 template <int BIAS, int T>
@@ -139,7 +140,7 @@ ss_pk_kernel(DecodeArgs a) {
     const int N = a.c.N;
     const int P = a.zpack;
     const uint32_t dummy = (uint32_t)a.c.dummy;
-    uint8_t *zold = lds;  // Z_old + 64 at LDS offset 0 (the planner places it there)
+    uint8_t *zold = lds;  // Z_old + 63 at LDS offset 0 (the planner places it there)
     uint32_t *zacc = reinterpret_cast<uint32_t *>(lds + a.off_zacc);
     int *flag = reinterpret_cast<int *>(lds + a.off_aux);  // [0]: separate check, [1], [2]: fused
     const int8_t *__restrict__ z0 = static_cast<const int8_t *>(a.llr_in) + (size_t)f * N;
@@ -153,16 +154,16 @@ ss_pk_kernel(DecodeArgs a) {
     const uint32_t *__restrict__ slot_of = a.c.pk_slot;
     for (int n = tid; n <= (int)dummy; n += kT) {
         if (n < N)
-            zold[slot_of[n]] = (uint8_t)(64 + min(max((int)z0[n], -kQmax), kQmax));
+            zold[slot_of[n]] = (uint8_t)(kZB + min(max((int)z0[n], -kQmax), kQmax));
         else  // unused slots read as zero; the dummy slot as the largest magnitude
-            zold[n] = (uint8_t)(64 + (n == (int)dummy ? kZoldMax : 0));
+            zold[n] = (uint8_t)(kZB + (n == (int)dummy ? kZoldMax : 0));
     }
     __syncthreads();
     for (int w = tid; w < nwords; w += kT) {
         uint32_t v = 0;
         for (int i = 0; i < P; ++i) {
             const int sl = w * P + i;
-            const int z = sl < N ? (int)zold[sl] - 64 : 0;
+            const int z = sl < N ? (int)zold[sl] - kZB : 0;
             v |= (uint32_t)(z + biasP) << (i * bitsP);
         }
         zacc[w] = v;
@@ -174,26 +175,26 @@ ss_pk_kernel(DecodeArgs a) {
     }
 
     // Message state of each row pair.
-    //   int8:  Lw[p][i], bytes 2s / 2s+1: slot 2i+s of rows a / b, as L + 64.
+    //   int8:  Lw[p][i], bytes 2s / 2s+1: slot 2i+s of rows a / b, as L + 63.
     //   1-bit (Sec. V): St[p][k] for slots j = 8k + i: bit 2i / 16+2i: slot
     //          j held the row minimum in row a / b, so its magnitude is B (A
     //          elsewhere); bit 2i+1 / 17+2i: sign of slot j's own extrinsic t;
     //          Ab[p] bytes: A_a, A_b, B_a, B_b signed by the row's sign
-    //          parity, plus 64.  A message is then the stored sign times the
+    //          parity, plus 63.  A message is then the stored sign times the
     //          signed A or B, exactly the Sec. V message s_mn f(A, B): the row
     //          parity moves from every per-edge sign bit into the per-row A
     //          and B (s_mn = own sign XOR parity).  The two bits of a slot
     //          index a four-entry byte table per row (+A, +B, -A, -B, plus
-    //          64), so one permute rebuilds the old message pair.
+    //          63), so one permute rebuilds the old message pair.
     uint32_t Lw[RP][ONEBIT ? 1 : W];
     uint32_t St[RP][NS], Ab[RP];
 #pragma unroll
     for (int p = 0; p < RP; ++p) {
 #pragma unroll
         for (int k = 0; k < NS; ++k) St[p][k] = 0u;
-        Ab[p] = 0x40404040u;  // A = B = 0
+        Ab[p] = 0x3F3F3F3Fu;  // A = B = 0
 #pragma unroll
-        for (int i = 0; i < (ONEBIT ? 1 : W); ++i) Lw[p][i] = 0x40404040u;
+        for (int i = 0; i < (ONEBIT ? 1 : W); ++i) Lw[p][i] = 0x3F3F3F3Fu;
     }
     __syncthreads();
 
@@ -214,7 +215,7 @@ ss_pk_kernel(DecodeArgs a) {
     for (int it = 1; it <= a.max_iter; ++it) {
         uint32_t it0 = 0;  // opaque zero: keeps the index loads inside the iteration loop
         asm volatile("" : "+s"(it0));
-        // FUSED: bits 15 / 31 collect odd hard-decision parities of Z^(it-1)
+        // FUSED: bits 6 / 22 collect odd hard-decision parities of Z^(it-1)
         // rows; flag[1 + (it & 1)] is set by this iteration and read after its
         // first barrier, the other one (read last iteration) is cleared here
         uint32_t zodd = 0;
@@ -243,9 +244,9 @@ ss_pk_kernel(DecodeArgs a) {
 #pragma unroll
             for (int k = 0; k < NS; ++k) Sp[k] = ONEBIT ? St[p][k] : 0u;
             if (ONEBIT) {
-                // per row, the bytes +A, +B, -A, -B (each plus 64): Ab holds the
-                // positive ones; 128 - x negates a biased byte with no borrow
-                const uint32_t Nb = 0x80808080u - Ab[p];
+                // per row, the bytes +A, +B, -A, -B (each plus 63): Ab holds the
+                // positive ones; 126 - x negates a biased byte with no borrow
+                const uint32_t Nb = 0x7E7E7E7Eu - Ab[p];
                 LUTa = __builtin_amdgcn_perm(Nb, Ab[p], 0x06040200u);
                 LUTb = __builtin_amdgcn_perm(Nb, Ab[p], 0x07050301u);
             }
@@ -257,12 +258,11 @@ ss_pk_kernel(DecodeArgs a) {
                 acc_b[j] = r4[3];
                 const u16x2 zv = {(unsigned short)lds_byte(na), (unsigned short)lds_byte(nb)};
                 const uint32_t z2 = bits(zv);
-                // FUSED: sign bit of each half set iff Z_old <= 0 (stored Z + 64 <= 64);
-                // a packed 16-bit subtract, so no borrow crosses the halves
-                if (FUSED) h2[j] = bits(as_i(z2) - (i16x2){65, 65});
+                // FUSED: bit 6 / 22 clear iff Z_old <= 0 (stored Z + 63 <= 63)
+                if (FUSED) h2[j] = z2;
                 uint32_t l2;
                 if (ONEBIT) {
-                    // L_old = s * (slot held the minimum ? B : A) + 64 (Eqs. 4-5
+                    // L_old = s * (slot held the minimum ? B : A) + 63 (Eqs. 4-5
                     // inverted): the slot's two bits per row (flag, sign) become
                     // the table index in bytes 0 and 2 of a permute selector
                     // (bytes 1 and 3 select zero), one table per row
@@ -291,7 +291,13 @@ ss_pk_kernel(DecodeArgs a) {
 #pragma unroll
                 for (int j = 1; j + 1 < D; j += 2) hp = __builtin_amdgcn_bitop3_b32(hp, h2[j], h2[j + 1], 0x96);
                 if (D % 2 == 0) hp ^= h2[D - 1];
-                zodd |= hp;
+                // bits 6 / 22 of hp: parity of the set bits 6 (Z_old > 0) over
+                // the D slots; the hard-decision parity is that plus D (padding
+                // slots read the dummy, bit 6 set: they add nothing either way)
+                if (D % 2 == 0)
+                    zodd |= hp;
+                else
+                    zodd = __builtin_amdgcn_bitop3_b32(zodd, hp, 0u, 0xF3);  // a | ~b
             }
             // per row pair: normalised magnitudes of the saturated minima,
             // A, B = max(round(alpha m) - beta, 0) with the offset folded into
@@ -333,9 +339,9 @@ ss_pk_kernel(DecodeArgs a) {
                     // and -1 elsewhere; one bit-select then picks B or A per row
                     const uint32_t nsel = bits(as_i(bits(as_u(mn1) - as_u(mg2[j]))) >> (i16x2){15, 15});
                     const uint32_t mag = __builtin_amdgcn_bitop3_b32(nsel, A2, B2, 0xCA);  // nsel ? A : B
-                    // own sign +-1, then L_new + 64 in one multiply-add
+                    // own sign +-1, then L_new + 63 in one multiply-add
                     const i16x2 sg = (as_i(t2[j]) >> (i16x2){15, 15}) | (i16x2){1, 1};
-                    lb = as_i(mag) * sg + (i16x2){64, 64};
+                    lb = as_i(mag) * sg + (i16x2){kZB, kZB};
                     if (ONEBIT) {  // keep the own-extrinsic sign and the minimum flag
                         const uint32_t sneg = bits(as_i(t2[j]) >> (i16x2){15, 15});
                         uint32_t &S = Sn[j >> 3];
@@ -348,7 +354,7 @@ ss_pk_kernel(DecodeArgs a) {
                     // sign +-1 per half: own extrinsic's sign XOR the row parity
                     const uint32_t sg = __builtin_amdgcn_bitop3_b32(
                         bits(as_i(t2[j]) >> (i16x2){15, 15}), mn1, 0x00010001u, 0xBE);  // (a ^ b) | c
-                    lb = mag * as_i(sg) + (i16x2){64, 64};
+                    lb = mag * as_i(sg) + (i16x2){kZB, kZB};
                 }
                 nl[j] = bits(lb);
                 const uint32_t d = bits(lb - as_i(lo2[j]));
@@ -363,21 +369,21 @@ ss_pk_kernel(DecodeArgs a) {
                     St[p][k] = Sn[k];
                     asm volatile("" : "+v"(St[p][k]));
                 }
-                // low bytes of the signed halves plus 64: A_a, A_b, B_a, B_b
-                Ab[p] = __builtin_amdgcn_perm(bits(as_i(B2) + (i16x2){64, 64}), bits(as_i(A2) + (i16x2){64, 64}),
+                // low bytes of the signed halves plus 63: A_a, A_b, B_a, B_b
+                Ab[p] = __builtin_amdgcn_perm(bits(as_i(B2) + (i16x2){kZB, kZB}), bits(as_i(A2) + (i16x2){kZB, kZB}),
                                               0x06040200u);
                 asm volatile("" : "+v"(Ab[p]));
             } else {
 #pragma unroll
                 for (int i = 0; i < W; ++i) {
                     const uint32_t lo = nl[2 * i];
-                    const uint32_t hi = (2 * i + 1 < D) ? nl[2 * i + 1] : 0x00400040u;
+                    const uint32_t hi = (2 * i + 1 < D) ? nl[2 * i + 1] : 0x003F003Fu;
                     Lw[p][i] = __builtin_amdgcn_perm(hi, lo, 0x06040200u);
                     asm volatile("" : "+v"(Lw[p][i]));
                 }
             }
         }
-        if (FUSED && it >= 2 && (zodd & 0x80008000u)) flag[1 + (it & 1)] = 1;
+        if (FUSED && it >= 2 && (zodd & 0x00400040u)) flag[1 + (it & 1)] = 1;
         __syncthreads();
         if (FUSED && it >= 2 && flag[1 + (it & 1)] == 0) {  // Z^(it-1) is a codeword
             conv_prev = true;
@@ -385,10 +391,10 @@ ss_pk_kernel(DecodeArgs a) {
         }
         if (tid == 0) *flag = 0;
         if (P == 3) {
-            if (biasP == 320)
-                refresh3<320, kT>(zacc, zold, N, nwords, tid);
+            if (biasP == 319)
+                refresh3<319, kT>(zacc, zold, N, nwords, tid);
             else
-                refresh3<576, kT>(zacc, zold, N, nwords, tid);
+                refresh3<575, kT>(zacc, zold, N, nwords, tid);
         } else {
             for (int w = tid; w < nwords; w += kT) {
                 const uint32_t v = zacc[w];
@@ -396,7 +402,7 @@ ss_pk_kernel(DecodeArgs a) {
                     const int n = w * P + i;
                     if (n < N) {
                         const int z = (P == 1) ? (int)v : (int)((v >> (i * bitsP)) & maskP) - biasP;
-                        zold[n] = (uint8_t)(64 + min(max(z, -kZoldMax), kZoldMax));
+                        zold[n] = (uint8_t)(kZB + min(max(z, -kZoldMax), kZoldMax));
                     }
                 }
             }
@@ -409,8 +415,8 @@ ss_pk_kernel(DecodeArgs a) {
                 for (int j = 0; j < D; ++j) {
                     const auto r4 = __builtin_amdgcn_raw_buffer_load_b128(
                         rec, tid16, (uint32_t)((p * D + j) * kT * 16), 0);
-                    pa ^= zold[r4[0]] <= 64 ? 1 : 0;
-                    pb ^= zold[r4[1]] <= 64 ? 1 : 0;
+                    pa ^= zold[r4[0]] <= kZB ? 1 : 0;
+                    pb ^= zold[r4[1]] <= kZB ? 1 : 0;
                 }
                 if (pa | pb) atomicOr(flag, 1);
             }
@@ -431,8 +437,8 @@ ss_pk_kernel(DecodeArgs a) {
             for (int j = 0; j < D; ++j) {
                 const auto r4 = __builtin_amdgcn_raw_buffer_load_b128(
                     rec, tid16, (uint32_t)((p * D + j) * kT * 16), 0);
-                pa ^= zold[r4[0]] <= 64 ? 1 : 0;
-                pb ^= zold[r4[1]] <= 64 ? 1 : 0;
+                pa ^= zold[r4[0]] <= kZB ? 1 : 0;
+                pb ^= zold[r4[1]] <= kZB ? 1 : 0;
             }
             if (pa | pb) atomicOr(flag, 1);
         }
@@ -440,7 +446,7 @@ ss_pk_kernel(DecodeArgs a) {
         ok = (*flag == 0);
     }
     if (FUSED && conv_prev) {  // decisions of Z^(iters) from its saturated copy
-        for (int n = tid; n < N; n += kT) a.hard_out[(size_t)f * N + n] = zold[slot_of[n]] <= 64 ? 1 : 0;
+        for (int n = tid; n < N; n += kT) a.hard_out[(size_t)f * N + n] = zold[slot_of[n]] <= kZB ? 1 : 0;
     } else for (int n = tid; n < N; n += kT) {
         const uint32_t sl = slot_of[n];
         const uint32_t w = (P == 1) ? sl : (P == 2 ? sl >> 1 : sl / 3u);
