@@ -344,11 +344,18 @@ def test_workspace_too_small_rejected(torch_dev, L):
 # of iteration k-1 into the gathers of iteration k.  Same decisions, iteration
 # counts and flags as the oracle and as the path that also returns posteriors.
 ES_CODES = {"peg1008": W.code_c0_peg1008, "ira16200": W.code_ira16200, "qc7493": W.code_c1_qc7493,
-            "ira64800": W.code_c2_ira64800}
+            "ira64800": W.code_c2_ira64800,
+            # ragged rows on the packed 8-, 6- and 21-slot shapes: padding slots
+            # with an even and an odd slot count in the fused syndrome
+            "rand6_8": lambda: W.random_small_code(60, 200, (6, 8), seed=5),
+            "rand3_6": lambda: W.random_small_code(60, 200, (3, 6), seed=6),
+            "rand9_12": lambda: W.random_small_code(60, 200, (9, 12), seed=7)}
 ES_CASES = [("peg1008", "int8", "auto"), ("peg1008", "1bit", "auto"), ("peg1008", "int8", "hbm"),
             ("peg1008", "int8", "reg1"), ("peg1008", "1bit", "reg1"), ("ira16200", "int8", "reg"),
             ("ira16200", "1bit", "reg"), ("ira16200", "int8", "reg1"), ("qc7493", "int8", "auto"),
-            ("qc7493", "1bit", "auto"), ("qc7493", "1bit", "reg1")]
+            ("qc7493", "1bit", "auto"), ("qc7493", "1bit", "reg1"),
+            ("rand6_8", "int8", "reg"), ("rand6_8", "1bit", "reg"), ("rand3_6", "int8", "reg"),
+            ("rand3_6", "1bit", "reg"), ("rand9_12", "int8", "reg"), ("rand9_12", "1bit", "reg")]
 
 
 def _spread_inputs(code, F, seed, lo=0.5, hi=3.5):
