@@ -63,9 +63,9 @@ KERNELS = {
 # taken on; any other source reports traffic as null.
 MEASURED_TRAFFIC = [
     {"kernel": "packed", "hash": "8dd74e9e6dd23e67", "workload": ("int8", "single_scan", 512, 50),
-     "bytes": 236.4e6, "profile": "profiles/ss_pk_int8_ira64800_512f.md"},
+     "bytes": 236.3e6, "profile": "profiles/ss_pk_int8_ira64800_512f.md"},
     {"kernel": "packed", "hash": "8dd74e9e6dd23e67", "workload": ("1bit", "single_scan", 512, 50),
-     "bytes": 235.7e6, "profile": "profiles/ss_pk_1bit_ira64800_512f.md"},
+     "bytes": 235.8e6, "profile": "profiles/ss_pk_1bit_ira64800_512f.md"},
     {"kernel": "f32_frames", "hash": "1c5cdaa9c2275be3", "workload": ("fp32", "single_scan", 512, 50),
      "bytes": 105147.1e6, "profile": "profiles/fl_f32_ira64800_512f.md"},
     {"kernel": "reg1", "hash": "e7d86239f37f995e", "workload": ("int8", "single_scan", 512, 50),
