@@ -409,6 +409,39 @@ def test_early_stop_hard_only_ira64800_sampled(torch_dev, L, orc, msg):
     np.testing.assert_array_equal(g["hard"][sel], r["hard"])
 
 
+@pytest.mark.parametrize("msg", ["int8", "1bit"])
+def test_accumulator_bias_for_degree_12_columns(torch_dev, L, orc, msg):
+    """N=64800 IRA code with degree-12 information columns: the packed kernel
+    keeps three 10-bit posterior fields per LDS word, and sums of up to
+    31 x 13 steps in magnitude need the larger field bias.  Mostly saturated
+    inputs and no normalisation drive the sums towards that bound; posteriors
+    and the fused early stop against the oracle."""
+    torch = torch_dev
+    code = W.ira_code(64800, 32400, 360, {12: 20, 3: 70}, seed=0x5750, name="ira64800_d12")
+    gcode = L.Code.from_parity_check(code)
+    i = gcode.info()
+    gcode.close()
+    assert (i["pk_slots"], i["pk_rows_per_thread"], i["reg_zpack"]) == (7, 32, 3)
+    assert 319 < 31 * (i["max_col_deg"] + 1) <= 448  # span of the larger bias
+    eb = np.array([6.0, 4.0, 2.5, 1.5, 1.0, 0.5])
+    step = 0.125
+    x = W.quantize_llr(W.awgn_llr(code.N, len(eb), eb, code.design_rate, key=(0x575, 1)), step=step)
+    assert (np.abs(x) == 31).mean() > 0.3
+    variant = VARIANTS[0] if msg == "int8" else VARIANTS[1]
+    for alpha in (1.0, 0.8):
+        _run_pair(torch, L, orc, code, x, variant, max_iter=10, alpha=alpha, early_stop=False, layout="reg",
+                  llr_step=step)
+    gcode = L.Code.from_parity_check(code)
+    g = {k: (v.cpu().numpy() if v is not None else None)
+         for k, v in gcode.decode(torch.from_numpy(x).cuda(), max_iter=10, early_stop=True, msg=msg,
+                                  layout="reg", with_llr=False, alpha=1.0).items()}
+    gcode.close()
+    algo = "one_bit" if msg == "1bit" else "single_scan"
+    r = orc.decode(code, x, algo=algo, arith="int", max_iter=10, alpha=1.0, early_stop=True, step=0.5)
+    for k in ("iters", "ok", "hard"):
+        np.testing.assert_array_equal(g[k], r[k], err_msg=k)
+
+
 @pytest.mark.parametrize("layout", ["auto", "reg1", "lds"])
 @pytest.mark.parametrize("msg", ["int8", "1bit"])
 def test_large_offsets(torch_dev, L, orc, msg, layout):
