@@ -62,9 +62,9 @@ KERNELS = {
 # path's kernels), keyed by the hash of the kernel sources the counters were
 # taken on; any other source reports traffic as null.
 MEASURED_TRAFFIC = [
-    {"kernel": "packed", "hash": "8dd74e9e6dd23e67", "workload": ("int8", "single_scan", 512, 50),
-     "bytes": 236.3e6, "profile": "profiles/ss_pk_int8_ira64800_512f.md"},
-    {"kernel": "packed", "hash": "8dd74e9e6dd23e67", "workload": ("1bit", "single_scan", 512, 50),
+    {"kernel": "packed", "hash": "16c4436e50885503", "workload": ("int8", "single_scan", 512, 50),
+     "bytes": 236.6e6, "profile": "profiles/ss_pk_int8_ira64800_512f.md"},
+    {"kernel": "packed", "hash": "16c4436e50885503", "workload": ("1bit", "single_scan", 512, 50),
      "bytes": 235.8e6, "profile": "profiles/ss_pk_1bit_ira64800_512f.md"},
     {"kernel": "f32_frames", "hash": "1c5cdaa9c2275be3", "workload": ("fp32", "single_scan", 512, 50),
      "bytes": 105147.1e6, "profile": "profiles/fl_f32_ira64800_512f.md"},

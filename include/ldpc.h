@@ -149,8 +149,10 @@ typedef struct {
     int32_t reg_slots;          /* register-resident shape: slots per row (0 = none) */
     int32_t reg_rows_per_thread;
     int32_t reg_zpack;          /* posterior accumulator fields per 32-bit LDS word */
-    int32_t pk_slots;           /* packed (two rows per lane) shape: slots per row (0 = none) */
-    int32_t pk_rows_per_thread;
+    int32_t pk_slots;           /* packed (two rows per lane) shape: slots per lane (0 = none);
+                                   rows longer than that span a lane pair (max_row_deg
+                                   > pk_slots: each lane holds half of every row) */
+    int32_t pk_rows_per_thread; /* rows per thread, or per lane pair when rows span two */
     int32_t pk_threads;         /* threads per workgroup (one frame) of the packed kernel */
 } ldpc_code_info;
 

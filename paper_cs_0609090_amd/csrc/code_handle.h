@@ -25,7 +25,8 @@ struct ldpc_code {
     int32_t regD = 0, regR = 0, regP = 0;
     uint32_t *d_ell_reg = nullptr;
     // packed two-rows-per-lane INT8 shape (0 = none); uses regP's packing
-    int32_t pkD = 0, pkR = 0, pkT = 0;  // slots, rows per thread, threads per workgroup
+    int32_t pkD = 0, pkR = 0, pkT = 0;  // slots per lane, rows per thread, threads per workgroup
+    int32_t pkS = 1;                    // lanes per row (2: a row's slots split over a lane pair)
     int32_t pkBias = 0;  // accumulator field bias of the packed kernel
     uint32_t *d_pk_idx = nullptr;
     uint32_t *d_pk_slot = nullptr;  // [N] posterior slot of each variable

@@ -106,8 +106,8 @@ hipError_t launch_ss_f32_fl(const DecodeArgs &a, const int32_t *row_ptr, const u
                             const int32_t *row_cls, int n_classes, hipStream_t s);
 hipError_t launch_two_scan(const DecodeArgs &a, int msg, const LaunchCfg &cfg, hipStream_t s);
 hipError_t launch_ss_reg(const DecodeArgs &a, int msg, int D, int R, int P, size_t lds, hipStream_t s);
-hipError_t launch_ss_pk(const DecodeArgs &a, int D, int R, int T, bool onebit, size_t lds, hipStream_t s);
-void pk_shapes(int *out, int cap, int *count);   // (D, R, T) triples
+hipError_t launch_ss_pk(const DecodeArgs &a, int D, int R, int T, int S, bool onebit, size_t lds, hipStream_t s);
+void pk_shapes(int *out, int cap, int *count);   // (D, R, T, lanes per row) quadruples
 bool reg_shape_available(int D, int R, int P);
 void reg_shapes(int *out, int cap, int *count);  // (D, R, P) triples
 constexpr int kRegThreads = 1024;

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/ldpc.h"
@@ -94,13 +95,13 @@ ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl)
     // AUTO for fixed point (measured on MI355X, 50 iterations): the packed
     // two-rows-per-lane kernel pays off from 16 rows per thread (M > 8192),
     // from 8 rows per thread for rows of up to 7 slots (two frames per CU) and
-    // for the 1-bit state, for rows wider than 8 slots that fill the 21-slot
-    // shape and with its 256-thread shapes for small codes; otherwise the
+    // for the 1-bit state, for rows wider than 8 slots that fill a wide packed
+    // shape (22 slots on a lane pair) and with its 256-thread shapes for small codes; otherwise the
     // one-row register kernel is faster, and other codes of at most 1024
     // checks run best LDS-resident with one thread per row (the register
     // kernels give every frame 1024 threads).
     const bool small_pk = c->pkD > 0 && c->pkT <= 256;  // packed shape with small workgroups
-    const bool wide_pk = c->pkD > 8 && 5 * c->D >= 4 * c->pkD;  // wide rows filling >= 80% of the slots
+    const bool wide_pk = c->pkD * c->pkS > 8 && 5 * c->D >= 4 * c->pkD * c->pkS;  // wide rows filling >= 80% of the slots
     const bool small_auto = layout == LDPC_LAYOUT_AUTO && c->M <= 1024 && !small_pk;
     if (p->sched == LDPC_SINGLE_SCAN && p->msg != LDPC_MSG_FP32 && !small_auto && qmax == kQmax6 &&
         (layout == LDPC_LAYOUT_AUTO || reg_layout)) {
@@ -248,7 +249,7 @@ __global__ void zero_word_kernel(int32_t *p) { *p = 0; }
 // are least used by the half-wavefronts that will touch it, so each half's 32
 // gathers and 32 atomics spread over the banks.
 std::vector<uint32_t> pk_slot_assignment(int M, int N, const int32_t *row_ptr, const int32_t *col_idx,
-                                         int pkD, int pkR, int T, int P, uint32_t zacc_off) {
+                                         int pkD, int pkR, int T, int S, int P, uint32_t zacc_off) {
     const int RP = pkR / 2, nwave = T / 32;  // half-wavefront groups
     const int ngroups = RP * 2 * pkD * nwave;
     std::vector<int32_t> gptr((size_t)N + 1, 0);
@@ -259,8 +260,10 @@ std::vector<uint32_t> pk_slot_assignment(int M, int N, const int32_t *row_ptr, c
                     for (int w = 0; w < nwave; ++w) {
                         const int g = ((pp * 2 + h) * pkD + j) * nwave + w;
                         for (int l = 0; l < 32; ++l) {
-                            const int m = (pp + h * RP) * T + w * 32 + l;
-                            if (m < M && j < row_ptr[m + 1] - row_ptr[m]) fn(col_idx[row_ptr[m] + j], g);
+                            // lane w*32+l: row (pp + h*RP)*(T/S) + lane/S, its slots from (lane%S)*pkD
+                            const int lane = w * 32 + l;
+                            const int m = (pp + h * RP) * (T / S) + lane / S, jr = (lane % S) * pkD + j;
+                            if (m < M && jr < row_ptr[m + 1] - row_ptr[m]) fn(col_idx[row_ptr[m] + jr], g);
                         }
                     }
     };
@@ -457,21 +460,26 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
             c->regP = bestP;
             // packed kernel: any instantiated (slots, even rows/thread) covering the
             // code; its accumulator addressing comes from the per-edge records
-            int pks[3 * 64], pcnt = 0;
+            int pks[4 * 64], pcnt = 0;
             ldpc::pk_shapes(pks, 64, &pcnt);
-            int pD = 1 << 30, pR = 1 << 30, pT = 0;
+            int pD = 1 << 30, pR = 1 << 30, pT = 0, pS = 1;
             // it also keeps 64 private accumulator words for padding slots
             const size_t need_pk = align_up((size_t)c->dummy + 1, 16) +
                                    align_up(4 * ((size_t)c->dummy / bestP + 1 + 64), 16) + 16;
+            // rows of more than 16 entries on a lane pair when a shape allows it
+            // (1024 threads instead of 768), other rows on one lane; then fewest
+            // slots per row, fewest padded rows, fewest rows per thread
+            auto rank = [&](int d, int r, int t, int l) {
+                return std::make_tuple((D > 16) == (l == 2) ? 0 : 1, d * l, (int64_t)r * (t / l), r);
+            };
             for (int i = 0; i < pcnt && i < 64 && need_pk <= (size_t)lds_dev; ++i) {
-                const int d = pks[3 * i], r = pks[3 * i + 1], t = pks[3 * i + 2];
-                if (d < D || (int64_t)r * t < M) continue;
-                // fewest slots, then fewest padded rows, then fewest rows per thread
-                if (d < pD || (d == pD && (int64_t)r * t < (int64_t)pR * pT) ||
-                    (d == pD && (int64_t)r * t == (int64_t)pR * pT && r < pR)) {
+                const int d = pks[4 * i], r = pks[4 * i + 1], t = pks[4 * i + 2], l = pks[4 * i + 3];
+                if (d * l < D || (int64_t)r * (t / l) < M) continue;
+                if (pT == 0 || rank(d, r, t, l) < rank(pD, pR, pT, pS)) {
                     pD = d;
                     pR = r;
                     pT = t;
+                    pS = l;
                 }
             }
             // 10-bit fields are biased by 319 or 575 (both 63 mod 256: the low
@@ -481,6 +489,7 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
                 c->pkD = pD;
                 c->pkR = pR;
                 c->pkT = pT;
+                c->pkS = pS;
                 c->pkBias = pbias;
             }
         }
@@ -521,14 +530,15 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
     std::vector<uint32_t> pk_idx, pk_slot;
     hipError_t e5 = hipSuccess, e6 = hipSuccess;
     if (c->pkD > 0) {
-        // record {zold_a, zold_b, acc_a, acc_b} of slot j of rows a = p*T + t,
-        // b = (p + R/2)*T + t (T threads): LDS byte address of the saturated
-        // posterior and (LDS byte address of the accumulator word << 5) | field shift
-        const int T = c->pkT, RP = c->pkR / 2, Dk = c->pkD, Pk = c->regP;
+        // record {zold_a, zold_b, acc_a, acc_b} of slot j of rows a = p*T/S + t/S,
+        // b = (p + R/2)*T/S + t/S (T threads, S lanes per row; lane t holds the
+        // row slots (t%S)*D + j): LDS byte address of the saturated posterior
+        // and (LDS byte address of the accumulator word << 5) | field shift
+        const int T = c->pkT, RP = c->pkR / 2, Dk = c->pkD, Pk = c->regP, S = c->pkS;
         const int fbits = Pk == 1 ? 32 : (Pk == 2 ? 16 : 10);
         const uint32_t zacc_off = (uint32_t)align_up((size_t)c->dummy + 1, 16);
         const uint32_t nwords = (uint32_t)c->dummy / (uint32_t)Pk + 1;
-        pk_slot = pk_slot_assignment(M, N, row_ptr, col_idx, Dk, c->pkR, T, Pk, zacc_off);
+        pk_slot = pk_slot_assignment(M, N, row_ptr, col_idx, Dk, c->pkR, T, S, Pk, zacc_off);
         pk_idx.assign((size_t)RP * Dk * T * 4, 0u);
         auto acc_of_slot = [&](uint32_t sl) -> uint32_t {
             const uint32_t w = sl / (uint32_t)Pk, fld = sl % (uint32_t)Pk;
@@ -538,10 +548,10 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
             for (int j = 0; j < Dk; ++j)
                 for (int t = 0; t < T; ++t)
                     for (int h = 0; h < 2; ++h) {
-                        const int m = (pp + h * RP) * T + t;
+                        const int m = (pp + h * RP) * (T / S) + t / S, jr = (t % S) * Dk + j;
                         uint32_t *r = &pk_idx[(((size_t)pp * Dk + j) * T + t) * 4];
-                        if (m < M && j < row_ptr[m + 1] - row_ptr[m]) {
-                            const uint32_t sl = pk_slot[col_idx[row_ptr[m] + j]];
+                        if (m < M && jr < row_ptr[m + 1] - row_ptr[m]) {
+                            const uint32_t sl = pk_slot[col_idx[row_ptr[m] + jr]];
                             r[h] = sl;
                             r[2 + h] = acc_of_slot(sl);
                         } else {  // padding: shared Z_old byte, a private accumulator word per lane
@@ -767,7 +777,7 @@ ldpc_status decode_job(const ldpc_code *c, int32_t n_frames, const void *llr_in,
     else if (pl.family == 3)
         e = ldpc::launch_ss_reg(a, p->msg, c->regD, c->regR, c->regP, pl.cfg.lds, s);
     else if (pl.family == 4)
-        e = ldpc::launch_ss_pk(a, c->pkD, c->pkR, c->pkT, p->msg == LDPC_MSG_1BIT, pl.cfg.lds, s);
+        e = ldpc::launch_ss_pk(a, c->pkD, c->pkR, c->pkT, c->pkS, p->msg == LDPC_MSG_1BIT, pl.cfg.lds, s);
     else if (pl.family == 1)
         e = ldpc::launch_ss_f32(a, pl.cfg, s);
     else if (pl.family == 6)

@@ -72,6 +72,11 @@ __device__ __forceinline__ uint32_t rounding_offset(int b) {
     return (uint32_t)(uint16_t)(int16_t)(128 - 256 * min(b, 32)) * 0x00010001u;
 }
 
+// the same register of the partner lane (lane ^ 1): DPP quad_perm [1,0,3,2]
+__device__ __forceinline__ uint32_t partner(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+}
+
 // bytes (2s, 2s+1) of w -> the low bytes of the two 16-bit halves
 __device__ __forceinline__ uint32_t pair_of(uint32_t w, int s) {
     return __builtin_amdgcn_perm(w, w, s == 0 ? 0x0c010c00u : 0x0c030c02u);
@@ -119,12 +124,16 @@ __device__ __forceinline__ void refresh3(const uint32_t *zacc, uint8_t *zold, in
 // ms; the int8 form spills 16 bytes per thread for it).
 template <int D, int R, int T>
 constexpr int pk_waves_per_eu() {
-    return (T == 1024 && R <= 8 && D <= 7) ? 8 : 1;
+    return (T == 1024 && R <= 8 && D <= 7) ? 8 : T == 512 ? 4 : 1;
 }
 
-template <int D, int R, bool ONEBIT, bool FUSED, int T>
+// LANES per row: with 2 the lanes 2u and 2u + 1 hold slots 0..D-1 and
+// D..2D-1 of the same two rows, and combine their minima, sign parities and
+// syndrome shares with one DPP exchange per row pair.
+template <int D, int R, bool ONEBIT, bool FUSED, int T, int LANES>
 __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(pk_waves_per_eu<D, R, T>())))
 ss_pk_kernel(DecodeArgs a) {
+    static_assert(LANES == 1 || LANES == 2, "one or two lanes per row");
     constexpr int kT = T;  // threads per workgroup (one frame)
     static_assert(R % 2 == 0, "rows are processed in pairs");
     constexpr int RP = R / 2;        // row pairs per thread
@@ -291,13 +300,20 @@ ss_pk_kernel(DecodeArgs a) {
 #pragma unroll
                 for (int j = 1; j + 1 < D; j += 2) hp = __builtin_amdgcn_bitop3_b32(hp, h2[j], h2[j + 1], 0x96);
                 if (D % 2 == 0) hp ^= h2[D - 1];
+                if (LANES == 2) hp ^= partner(hp);
                 // bits 6 / 22 of hp: parity of the set bits 6 (Z_old > 0) over
-                // the D slots; the hard-decision parity is that plus D (padding
-                // slots read the dummy, bit 6 set: they add nothing either way)
-                if (D % 2 == 0)
+                // the LANES D slots; the hard-decision parity is that plus LANES D
+                // (padding slots read the dummy, bit 6 set: they add nothing)
+                if ((LANES * D) % 2 == 0)
                     zodd |= hp;
                 else
                     zodd = __builtin_amdgcn_bitop3_b32(zodd, hp, 0u, 0xF3);  // a | ~b
+            }
+            if (LANES == 2) {  // the partner lane holds the other slots of both rows
+                const u16x2 o1 = as_u(partner(bits(min1))), o2 = as_u(partner(bits(min2)));
+                min2 = __builtin_elementwise_min(__builtin_elementwise_max(min1, o1), __builtin_elementwise_min(min2, o2));
+                min1 = __builtin_elementwise_min(min1, o1);
+                par ^= partner(par);
             }
             // per row pair: normalised magnitudes of the saturated minima,
             // A, B = max(round(alpha m) - beta, 0) with the offset folded into
@@ -418,6 +434,10 @@ ss_pk_kernel(DecodeArgs a) {
                     pa ^= zold[r4[0]] <= kZB ? 1 : 0;
                     pb ^= zold[r4[1]] <= kZB ? 1 : 0;
                 }
+                if (LANES == 2) {
+                    pa ^= (int)partner((uint32_t)pa);
+                    pb ^= (int)partner((uint32_t)pb);
+                }
                 if (pa | pb) atomicOr(flag, 1);
             }
             __syncthreads();
@@ -439,6 +459,10 @@ ss_pk_kernel(DecodeArgs a) {
                     rec, tid16, (uint32_t)((p * D + j) * kT * 16), 0);
                 pa ^= zold[r4[0]] <= kZB ? 1 : 0;
                 pb ^= zold[r4[1]] <= kZB ? 1 : 0;
+            }
+            if (LANES == 2) {
+                pa ^= (int)partner((uint32_t)pa);
+                pb ^= (int)partner((uint32_t)pb);
             }
             if (pa | pb) atomicOr(flag, 1);
         }
@@ -462,9 +486,9 @@ ss_pk_kernel(DecodeArgs a) {
     }
 }
 
-template <int D, int R, bool ONEBIT, bool FUSED, int T>
+template <int D, int R, bool ONEBIT, bool FUSED, int T, int S>
 hipError_t launch_one(const DecodeArgs &a, size_t lds, hipStream_t s) {
-    auto kern = ss_pk_kernel<D, R, ONEBIT, FUSED, T>;
+    auto kern = ss_pk_kernel<D, R, ONEBIT, FUSED, T, S>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -476,32 +500,35 @@ hipError_t launch_one(const DecodeArgs &a, size_t lds, hipStream_t s) {
 
 }  // namespace
 
-// Instantiated (slots per row, rows per thread, threads) shapes of the packed
-// kernel (int8 and 1-bit).  Rows of up to 8 slots run 1024 threads, or 256
-// for codes of at most 512 / 1024 checks, so that a CU holds several frames;
-// wider rows keep 6 D registers per row pair live, so they run 768 threads,
-// whose 3 waves per SIMD leave each wave up to 168 VGPRs.
-#define LDPC_PK_SHAPES(X) \
-    X(6, 2, 256)          \
-    X(8, 2, 256)          \
-    X(8, 4, 256)          \
-    X(6, 2, 1024)         \
-    X(6, 4, 1024)         \
-    X(7, 8, 1024)         \
-    X(7, 16, 1024)        \
-    X(7, 32, 1024)        \
-    X(8, 8, 1024)         \
-    X(8, 16, 1024)        \
-    X(8, 32, 1024)        \
-    X(21, 4, 768)
+// Instantiated (slots per lane, rows per thread, threads, lanes per row)
+// shapes of the packed kernel (int8 and 1-bit).  Rows of up to 8 slots run
+// 1024 threads, or 256 for codes of at most 512 / 1024 checks, so that a CU
+// holds several frames; wider rows keep 6 D registers per row pair live, so
+// they run 768 threads, whose 3 waves per SIMD leave each wave up to 168
+// VGPRs, or split over two lanes (11 slots each) in 1024 threads.
+#define LDPC_PK_SHAPES(X)   \
+    X(6, 2, 256, 1)         \
+    X(8, 2, 256, 1)         \
+    X(8, 4, 256, 1)         \
+    X(6, 2, 1024, 1)        \
+    X(6, 4, 1024, 1)        \
+    X(7, 8, 1024, 1)        \
+    X(7, 16, 1024, 1)       \
+    X(7, 32, 1024, 1)       \
+    X(8, 8, 1024, 1)        \
+    X(8, 16, 1024, 1)       \
+    X(8, 32, 1024, 1)       \
+    X(21, 4, 768, 1)        \
+    X(11, 6, 1024, 2)
 
 void pk_shapes(int *out, int cap, int *count) {
     int i = 0;
-#define X(d, r, t)           \
+#define X(d, r, t, l)        \
     if (i < cap) {           \
-        out[3 * i] = d;      \
-        out[3 * i + 1] = r;  \
-        out[3 * i + 2] = t;  \
+        out[4 * i] = d;      \
+        out[4 * i + 1] = r;  \
+        out[4 * i + 2] = t;  \
+        out[4 * i + 3] = l;  \
     }                        \
     ++i;
     LDPC_PK_SHAPES(X)
@@ -510,19 +537,19 @@ void pk_shapes(int *out, int cap, int *count) {
 }
 
 namespace {
-template <int D, int R, int T>
+template <int D, int R, int T, int S>
 hipError_t launch_shape(const DecodeArgs &a, bool onebit, size_t lds, hipStream_t s) {
     // the fused check needs at least one iteration and no posterior output
     const bool fused = a.early_stop && a.llr_out == nullptr && a.max_iter >= 1;
     if (onebit)
-        return fused ? launch_one<D, R, true, true, T>(a, lds, s) : launch_one<D, R, true, false, T>(a, lds, s);
-    return fused ? launch_one<D, R, false, true, T>(a, lds, s) : launch_one<D, R, false, false, T>(a, lds, s);
+        return fused ? launch_one<D, R, true, true, T, S>(a, lds, s) : launch_one<D, R, true, false, T, S>(a, lds, s);
+    return fused ? launch_one<D, R, false, true, T, S>(a, lds, s) : launch_one<D, R, false, false, T, S>(a, lds, s);
 }
 }  // namespace
 
-hipError_t launch_ss_pk(const DecodeArgs &a, int D, int R, int T, bool onebit, size_t lds, hipStream_t s) {
-#define X(d, r, t) \
-    if (D == d && R == r && T == t) return launch_shape<d, r, t>(a, onebit, lds, s);
+hipError_t launch_ss_pk(const DecodeArgs &a, int D, int R, int T, int S, bool onebit, size_t lds, hipStream_t s) {
+#define X(d, r, t, l) \
+    if (D == d && R == r && T == t && S == l) return launch_shape<d, r, t, l>(a, onebit, lds, s);
     LDPC_PK_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;
