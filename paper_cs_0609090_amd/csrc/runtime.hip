@@ -467,7 +467,8 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
             const size_t need_pk = align_up((size_t)c->dummy + 1, 16) +
                                    align_up(4 * ((size_t)c->dummy / bestP + 1 + 64), 16) + 16;
             // rows of more than 16 entries on a lane pair when a shape allows it
-            // (1024 threads instead of 768), other rows on one lane; then fewest
+            // (512 threads, two frames per CU, instead of 768), other rows on one
+            // lane; then fewest
             // slots per row, fewest padded rows, fewest rows per thread
             auto rank = [&](int d, int r, int t, int l) {
                 return std::make_tuple((D > 16) == (l == 2) ? 0 : 1, d * l, (int64_t)r * (t / l), r);

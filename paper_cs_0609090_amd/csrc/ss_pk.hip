@@ -505,7 +505,8 @@ hipError_t launch_one(const DecodeArgs &a, size_t lds, hipStream_t s) {
 // 1024 threads, or 256 for codes of at most 512 / 1024 checks, so that a CU
 // holds several frames; wider rows keep 6 D registers per row pair live, so
 // they run 768 threads, whose 3 waves per SIMD leave each wave up to 168
-// VGPRs, or split over two lanes (11 slots each) in 1024 threads.
+// VGPRs, or split over two lanes (11 slots each) in 512 threads held to 128
+// VGPRs, so that two frames share a CU.
 #define LDPC_PK_SHAPES(X)   \
     X(6, 2, 256, 1)         \
     X(8, 2, 256, 1)         \
@@ -519,7 +520,7 @@ hipError_t launch_one(const DecodeArgs &a, size_t lds, hipStream_t s) {
     X(8, 16, 1024, 1)       \
     X(8, 32, 1024, 1)       \
     X(21, 4, 768, 1)        \
-    X(11, 6, 1024, 2)
+    X(11, 12, 512, 2)
 
 void pk_shapes(int *out, int cap, int *count) {
     int i = 0;

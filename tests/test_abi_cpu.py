@@ -154,9 +154,9 @@ def test_workspace_plans(L):
     info = big.info()
     assert (info["reg_slots"], info["reg_rows_per_thread"], info["reg_zpack"]) == (7, 32, 3)
     assert (info["pk_slots"], info["pk_rows_per_thread"], info["pk_threads"]) == (7, 32, 1024)
-    # rows of up to 21 slots: 11 slots on each lane of a pair, 1024 threads
+    # rows of up to 21 slots: 11 slots on each lane of a pair, 512 threads
     qc = L.Code.from_parity_check(W.code_c1_qc7493(), device=-1).info()
-    assert (qc["pk_slots"], qc["pk_rows_per_thread"], qc["pk_threads"]) == (11, 6, 1024)
+    assert (qc["pk_slots"], qc["pk_rows_per_thread"], qc["pk_threads"]) == (11, 12, 512)
     for msg in ("int8", "1bit"):
         assert big.workspace_size(4, L.make_params(msg=msg)) == 0
         assert big.workspace_size(4, L.make_params(msg=msg, layout="reg")) == 0

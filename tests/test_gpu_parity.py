@@ -248,7 +248,7 @@ def test_register_path_selected(torch_dev, L):
     slots)."""
     for code, shape, pk in ((W.code_c0_peg1008(), (6, 1, 1), (6, 2, 256)),
                             (W.code_ira16200(), (7, 8, 1), (7, 8, 1024)),
-                            (W.code_c1_qc7493(), (21, 3, 1), (11, 6, 1024)),
+                            (W.code_c1_qc7493(), (21, 3, 1), (11, 12, 512)),
                             (W.code_c2_ira64800(), (7, 32, 3), (7, 32, 1024))):
         gc = L.Code.from_parity_check(code)
         i = gc.info()
