@@ -55,6 +55,12 @@ def _row_groups(code):
     return out
 
 
+def _pair(W, t, cls_rows):
+    """The (a, b) pair of iteration t (1-based) for rows of classes ``cls_rows``:
+    row t - 1 of the table, column = the row's class."""
+    return W[t - 1, cls_rows, 0], W[t - 1, cls_rows, 1]
+
+
 def _check_update(tm, a, b):
     """Exclusion-form check update of one degree group.
     tm [F, R, d] extrinsics, a/b [R] weights.  Returns L [F, R, d] and, per
@@ -108,8 +114,7 @@ def forward(code, llr, weights, target=None, dtype=np.float64):
         Ln = np.zeros((F, E), dtype=dtype)
         for d, rows, e, cols in groups:
             tm = Zp[:, cols] - Lp[:, e]
-            a = W[t - 1, cls[rows], 0]
-            b = W[t - 1, cls[rows], 1]
+            a, b = _pair(W, t, cls[rows])
             L, *_ = _check_update(tm, a, b)
             Ln[:, e] = L
         Zn = llr.copy()
@@ -146,8 +151,7 @@ def adjoint(code, llr, weights, target=None):
         tbar = np.zeros((F, E))
         for d, rows, e, cols in groups:
             tm = Zs[t - 1][:, cols] - Ls[t - 1][:, e]
-            a = W[t - 1, cls[rows], 0]
-            b = W[t - 1, cls[rows], 1]
+            a, b = _pair(W, t, cls[rows])
             _, K, MN, SG, ACT = _check_update(tm, a, b)
             lb = Lbar[:, e]                                    # [F, R, d]
             live = lb * SG * ACT                               # dL_j / d(a*mn - b)

@@ -3,8 +3,12 @@
 Forward: with the same (a, b) at every iteration and class, the unrolled
 posteriors are the plain NMS/OMS single-scan posteriors of the binary64 C
 oracle, iteration by iteration and bit for bit (same summation order).
+Per-class, per-iteration pairs: a class-zeroing identity against the C
+oracle on H restricted to one class's rows (below), with planted mapping
+mistakes that it must catch.
 Adjoint: central finite differences of the binary64 loss, on codes with
-several check-degree classes, with a nonzero transmitted codeword.
+several check-degree classes, with a nonzero transmitted codeword; with the
+forward pinned, this pins the adjoint of the same decoder.
 """
 import numpy as np
 import pytest
@@ -82,3 +86,98 @@ def test_loss_of_the_transmitted_word_direction():
     w[:, :, 0] = 0.7
     g, _ = LO.adjoint(code, llr, w)
     assert np.all(g[:, :, 0] < 0)
+
+
+# --------------------------------------------------------------------------
+# Per-class and per-iteration pairs: a class-zeroing identity.
+#
+# A pair (a, b) = (1, 1e12) makes every message of its rows exactly zero
+# (max(m - 1e12, 0) = 0 for any finite minimum), so those rows drop out of
+# Eq. (3) and of the posterior sums.  With every class but one zeroed at
+# every iteration, and every class zeroed during the first t0 iterations,
+# the unrolled decoder must reproduce the plain single-scan decoder of the
+# binary64 C oracle run for T - t0 iterations with the kept class's pair on
+# H restricted to that class's rows (the zeroed iterations leave L = 0 and
+# Z = Z(0), the decoder's initial state).  A wrong class-to-row mapping or a
+# shifted iteration index makes the kept rows take another pair or start
+# early, and the posteriors differ.
+# --------------------------------------------------------------------------
+_ZERO_PAIR = (1.0, 1e12)
+
+
+def _restrict_rows(code, keep_rows):
+    rp, ci = np.asarray(code.row_ptr), np.asarray(code.col_idx)
+    rows = [ci[rp[m]:rp[m + 1]] for m in keep_rows]
+    return W.ParityCheck.from_rows(len(rows), code.N, rows, code.name + "_restricted")
+
+
+def _classy_code():
+    # row degrees 3..7: five classes, cycles allowed
+    code = W.random_small_code(30, 64, (3, 7), seed=909)
+    _, cls, levels = LO.degree_classes(code)
+    assert len(levels) >= 3
+    return code, cls, levels
+
+
+def check_class_identity(orc, code, cls, levels, kept, pair, t0, T, llr):
+    """Run the identity for one kept class; raises AssertionError on mismatch."""
+    C = len(levels)
+    w = np.empty((T, C, 2))
+    w[:, :, 0], w[:, :, 1] = _ZERO_PAIR
+    w[t0:, kept, 0], w[t0:, kept, 1] = pair
+    fw = LO.forward(code, llr, w)
+    keep_rows = np.nonzero(cls == kept)[0]
+    sub = _restrict_rows(code, keep_rows)
+    r = orc.decode(sub, llr, algo="single_scan", arith="f64", max_iter=T - t0, alpha=pair[0],
+                   beta=pair[1], early_stop=False, trace=True)
+    rp = np.asarray(code.row_ptr)
+    kept_edges = np.concatenate([np.arange(rp[m], rp[m + 1]) for m in keep_rows])
+    other_edges = np.setdiff1d(np.arange(code.E), kept_edges)
+    for t in range(1, T + 1):
+        if t <= t0:
+            np.testing.assert_array_equal(fw["Z"][t], llr)
+            assert not np.any(fw["L"][t])
+            continue
+        np.testing.assert_array_equal(fw["Z"][t], r["Z"][:, t - t0 - 1, :])
+        np.testing.assert_array_equal(fw["L"][t][:, kept_edges], r["L"][:, t - t0 - 1, :])
+        assert not np.any(fw["L"][t][:, other_edges])
+    # the kept rows really decode: some of their messages are nonzero
+    assert np.any(fw["L"][T][:, kept_edges])
+
+
+@pytest.mark.parametrize("t0", [0, 2])
+def test_class_zeroing_identity(orc, t0):
+    code, cls, levels = _classy_code()
+    llr = W.awgn_llr(code.N, 4, 1.5, code.design_rate, key=(0x1EA, 7))
+    pairs = [(0.55, 0.0), (0.7, 0.25), (0.85, 0.125), (1.0, 0.5), (0.625, 0.375), (0.9, 0.0)]
+    T = 5
+    for kept in range(len(levels)):
+        check_class_identity(orc, code, cls, levels, kept, pairs[kept % len(pairs)], t0, T, llr)
+
+
+def test_class_identity_catches_planted_mapping_errors(orc, monkeypatch):
+    """Plant mistakes in the oracle's pair lookup (on the CPU): a reversed
+    class order, an off-by-one class and an off-by-one iteration.  Each must
+    fail the identity."""
+    code, cls, levels = _classy_code()
+    llr = W.awgn_llr(code.N, 4, 1.5, code.design_rate, key=(0x1EA, 7))
+    good = LO._pair
+    C = len(levels)
+    planted = {
+        "reversed classes": lambda Wt, t, c: good(Wt, t, C - 1 - c),
+        "class + 1": lambda Wt, t, c: good(Wt, t, np.minimum(c + 1, C - 1)),
+        "iteration + 1": lambda Wt, t, c: good(Wt, min(t + 1, Wt.shape[0]), c),
+        "iteration - 1": lambda Wt, t, c: good(Wt, max(t - 1, 1), c),
+    }
+    for name, fn in planted.items():
+        monkeypatch.setattr(LO, "_pair", fn)
+        caught = False
+        for kept in range(C):
+            try:
+                check_class_identity(orc, code, cls, levels, kept, (0.7, 0.25), 2, 5, llr)
+            except AssertionError:
+                caught = True
+                break
+        assert caught, f"planted mistake not caught: {name}"
+    monkeypatch.setattr(LO, "_pair", good)
+    check_class_identity(orc, code, cls, levels, 0, (0.7, 0.25), 2, 5, llr)
