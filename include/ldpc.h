@@ -92,7 +92,8 @@ typedef enum {
  *  beta       >= 0, in LLR units.
  *  llr_step   LLR value of one fixed-point unit for INT8 / 1BIT (0.5 for the
  *             6-bit range +-15.5).  Fixed point uses a8 = round(256 alpha),
- *             b = round(beta / llr_step) (half away from zero) and
+ *             b = round(min(beta / llr_step, 255)) (half away from zero; 255
+ *             steps already zero every message) and
  *             |L| = max(((m*a8 + 128) >> 8) - b, 0).
  *  early_stop nonzero: stop a frame after the first iteration k >= 1 whose
  *             hard decision satisfies H x^T = 0 (Sec. III decoding step).
@@ -154,7 +155,53 @@ typedef struct {
                                    > pk_slots: each lane holds half of every row) */
     int32_t pk_rows_per_thread; /* rows per thread, or per lane pair when rows span two */
     int32_t pk_threads;         /* threads per workgroup (one frame) of the packed kernel */
+
+    /* Degree distributions (Sec. II: |N(m)| and |M(n)|): row_deg_hist[d] rows
+     * of degree d (d <= 64, the largest accepted); col_deg_hist[d] columns of
+     * degree d for d < 64, col_deg_hist[64] columns of degree 64 or more. */
+    int32_t row_deg_hist[65];
+    int32_t col_deg_hist[65];
+
+    /* Structure found in H (bit set of LDPC_STRUCT_*; 0 = none found). */
+    int32_t structure;
+    int32_t qc_lift;            /* LDPC_STRUCT_QC: the largest Z >= 2 for which H is an array of
+                                   Z x Z blocks, each empty or one circulant permutation */
+    int32_t ira_group;          /* LDPC_STRUCT_IRA_GROUPS: the largest Q for which information
+                                   column j of every group of Q columns hits the rows of the
+                                   group's first column shifted by j * M / Q (mod M); 0 if none */
+    int32_t reserved;           /* 0 */
+
+    /* Per-frame storage of the stored values each form keeps (Secs. IV-V):
+     *  var_values_single  N: one posterior Z_n per variable (single-scan)
+     *  var_values_two     E = N x mean column degree: one Z_mn per edge (two-scan)
+     * and bytes per frame of each message type's per-edge / per-check state
+     * and of the posteriors, as the library stores them: */
+    int64_t var_values_single;
+    int64_t var_values_two;
+    int64_t msg_bytes_int8;     /* E: one b-bit message (b = 6..8) per byte */
+    int64_t msg_bytes_1bit;     /* ceil(E / 8) sign bytes + 2 M bytes of (A, B, n~) state */
+    int64_t msg_bytes_fp32;     /* 4 E */
+    int64_t post_bytes_int;     /* 2 N: one int16 posterior per variable */
+    int64_t post_bytes_fp32;    /* 4 N */
+    /* Bytes per frame and iteration that a decoder streaming every per-frame
+     * array through device memory moves (the algorithmic traffic model):
+     * single-scan int8 2E + 5N (messages read and written, Z_old read and
+     * Z_new written as int16, Z(0) read), 1-bit 2 ceil(E/8) + 4M + 5N,
+     * binary32 8E + 12N; two-scan int8 4E + 3N, two-scan binary32 16E + 8N. */
+    int64_t stream_bytes_int8;
+    int64_t stream_bytes_1bit;
+    int64_t stream_bytes_fp32;
+    int64_t stream_bytes_two_int8;
+    int64_t stream_bytes_two_fp32;
 } ldpc_code_info;
+
+/* ldpc_code_info.structure bits */
+#define LDPC_STRUCT_QC 0x1         /* circulant-permutation blocks, lift qc_lift */
+#define LDPC_STRUCT_IRA 0x2        /* the last M columns are a dual-diagonal staircase: column
+                                      N - M + p hits rows p and p + 1 (the last one row M - 1) */
+#define LDPC_STRUCT_IRA_GROUPS 0x4 /* and the information columns come in cyclic groups of
+                                      ira_group columns (repeat-accumulate codes in the form of
+                                      the DVB-S2 tables) */
 
 /*
  * Create a code handle from a sparse parity-check matrix H (M x N over GF(2),
@@ -176,7 +223,8 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
 /* Free a handle and its device memory.  NULL is accepted. */
 ldpc_status ldpc_code_destroy(ldpc_code *code);
 
-/* Fill *out with the facts above.  Host only. */
+/* Fill *out with the facts above.  Host only; the structure is found once,
+ * when the handle is created. */
 ldpc_status ldpc_code_query(const ldpc_code *code, ldpc_code_info *out);
 
 /*

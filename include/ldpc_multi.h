@@ -50,7 +50,9 @@ ldpc_status ldpc_decode_multi(const ldpc_job *jobs, int32_t n_jobs, void *worksp
  * LDS, HBM, FRAMES; each on n_frames zero-LLR frames with early stop off and
  * p->max_iter iterations, best of 3 after a warm-up), allocating device
  * memory for the trial, and make AUTO use the fastest one for this (msg,
- * sched) on this handle from now on.  Synchronises the device.
+ * sched, msg_bits) on this handle from now on.  A later AUTO call whose
+ * parameters the tuned layout cannot run (another frame count's workspace
+ * form, say) falls back to the built-in policy.  Synchronises the device.
  *  best_layout  out: LDPC_LAYOUT_* chosen.
  *  best_ms      out: its time per call in milliseconds (may be NULL).
  *  n_tried      out: layouts timed (may be NULL).

@@ -148,7 +148,10 @@ static int params_q(double alpha, double beta, double step, int *a8, int *b)
 {
     if (!(alpha > 0.0 && alpha <= 1.0) || !(beta >= 0.0) || !(step > 0.0)) return -1;
     *a8 = (int)lround(alpha * 256.0);
-    *b = (int)lround(beta / step);
+    /* an offset of 255 steps already exceeds every b-bit magnitude (b <= 8),
+     * so every larger beta gives the same all-zero messages; the cap keeps
+     * the conversion in range */
+    *b = (int)lround(fmin(beta / step, 255.0));
     return 0;
 }
 

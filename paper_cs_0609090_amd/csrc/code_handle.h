@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include "../../include/ldpc.h"
+#include "code_facts.h"
 
 struct ldpc_code {
     int32_t device = 0;
@@ -17,6 +18,7 @@ struct ldpc_code {
     int64_t E = 0;
     int32_t D = 0, Mp = 0, dummy = 0;
     int32_t min_row_deg = 0, max_col_deg = 0;
+    ldpc::CodeFacts facts;  // degree histograms and block structure (ldpc_code_query)
     int32_t lds_limit = 65536;
     uint32_t *d_ell = nullptr;
     int32_t *d_vc_ptr = nullptr;
@@ -53,12 +55,20 @@ struct ldpc_code {
     int32_t learn_classes = 0;
     std::vector<int32_t> learn_degrees;
     int32_t *d_row_cls = nullptr;  // [M] class of each row
-    // layout used by LDPC_LAYOUT_AUTO per (msg, sched), index msg * 2 + sched;
-    // 0 = the built-in policy (set by ldpc_autotune, read atomically)
-    int32_t tuned_layout[6] = {0, 0, 0, 0, 0, 0};
+    // layout used by LDPC_LAYOUT_AUTO per (msg, sched, message width), index
+    // tuned_slot(); 0 = the built-in policy (set by ldpc_autotune, read
+    // atomically).  A tuned layout that cannot plan a later call falls back to
+    // the built-in policy for that call.
+    int32_t tuned_layout[18] = {};
 };
 
 namespace ldpc {
+// index of (msg, sched, msg_bits) in ldpc_code::tuned_layout
+inline int tuned_slot(const ldpc_decode_params *p) {
+    const int w = p->msg_bits <= 6 ? 0 : p->msg_bits - 6;  // 0, 6 -> 0; 7 -> 1; 8 -> 2
+    return (p->msg * 2 + p->sched) * 3 + w;
+}
+
 // Makes `dev` the current device for the guard's lifetime.
 struct DeviceGuard {
     int prev = -1;

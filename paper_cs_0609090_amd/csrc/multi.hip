@@ -290,7 +290,7 @@ ldpc_status ldpc_autotune(ldpc_code *code, int32_t n_frames, const ldpc_decode_p
     if (hard) (void)hipFree(hard);
     if (llr) (void)hipFree(llr);
     if (st != LDPC_OK) return ldpc::set_error(st, msg);
-    __atomic_store_n(&code->tuned_layout[p->msg * 2 + p->sched], best, __ATOMIC_RELAXED);
+    __atomic_store_n(&code->tuned_layout[ldpc::tuned_slot(p)], best, __ATOMIC_RELAXED);
     *best_layout = best;
     if (best_ms) *best_ms = best_t;
     if (n_tried) *n_tried = tried;

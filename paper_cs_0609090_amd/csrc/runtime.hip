@@ -69,14 +69,27 @@ ldpc_status validate_params(const ldpc_decode_params *p) {
 // Q of the call's fixed-point messages: 2^(b-1) - 1 for b = msg_bits (6 by default).
 int qmax_of(const ldpc_decode_params *p) { return (1 << ((p->msg_bits ? p->msg_bits : 6) - 1)) - 1; }
 
+ldpc_status plan_layout(const ldpc_code *c, const ldpc_decode_params *p, uint32_t layout, Plan *pl);
+
 ldpc_status make_plan(const ldpc_code *c, const ldpc_decode_params *p, Plan *pl) {
+    const uint32_t layout = (p->flags >> LDPC_F_LAYOUT_SHIFT) & 0xFu;
+    if (layout == LDPC_LAYOUT_AUTO && !p->weights) {  // a layout chosen by ldpc_autotune
+        const int32_t t = __atomic_load_n(&c->tuned_layout[ldpc::tuned_slot(p)], __ATOMIC_RELAXED);
+        if (t > 0) {
+            Plan tp;
+            if (plan_layout(c, p, (uint32_t)t, &tp) == LDPC_OK) {
+                *pl = tp;
+                return LDPC_OK;
+            }
+            g_err.clear();  // the tuned layout cannot run this call: the built-in policy decides
+        }
+    }
+    return plan_layout(c, p, layout, pl);
+}
+
+ldpc_status plan_layout(const ldpc_code *c, const ldpc_decode_params *p, uint32_t layout, Plan *pl) {
     const int D = c->D, Mp = c->Mp;
     const size_t nz = (size_t)c->dummy + 1;
-    uint32_t layout = (p->flags >> LDPC_F_LAYOUT_SHIFT) & 0xFu;
-    if (layout == LDPC_LAYOUT_AUTO && !p->weights) {  // a layout chosen by ldpc_autotune
-        const int32_t t = __atomic_load_n(&c->tuned_layout[p->msg * 2 + p->sched], __ATOMIC_RELAXED);
-        if (t > 0) layout = (uint32_t)t;
-    }
     const size_t limit = (size_t)c->lds_limit;
     const size_t aux = 16;
     int dmax = D <= 8 ? 8 : (D <= 16 ? 16 : (D <= 32 ? 32 : 64));
@@ -391,6 +404,7 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
     c->min_row_deg = dmin;
     c->h_row_ptr.assign(row_ptr, row_ptr + M + 1);
     c->h_col_idx.assign(col_idx, col_idx + nnz);
+    ldpc::analyse_code(M, N, row_ptr, col_idx, &c->facts);
     std::vector<int32_t> row_cls(M);
     {
         std::vector<int32_t> degs(M);
@@ -640,6 +654,26 @@ ldpc_status ldpc_code_query(const ldpc_code *c, ldpc_code_info *o) {
     o->pk_slots = c->pkD;
     o->pk_rows_per_thread = c->pkR;
     o->pk_threads = c->pkT;
+    for (int d = 0; d <= 64; ++d) {
+        o->row_deg_hist[d] = c->facts.row_hist[d];
+        o->col_deg_hist[d] = c->facts.col_hist[d];
+    }
+    o->structure = c->facts.structure;
+    o->qc_lift = c->facts.qc_lift;
+    o->ira_group = c->facts.ira_group;
+    const int64_t E = c->E, N = c->N, M = c->M, Eb = (E + 7) / 8;
+    o->var_values_single = N;
+    o->var_values_two = E;
+    o->msg_bytes_int8 = E;
+    o->msg_bytes_1bit = Eb + 2 * M;
+    o->msg_bytes_fp32 = 4 * E;
+    o->post_bytes_int = 2 * N;
+    o->post_bytes_fp32 = 4 * N;
+    o->stream_bytes_int8 = 2 * E + 5 * N;
+    o->stream_bytes_1bit = 2 * Eb + 4 * M + 5 * N;
+    o->stream_bytes_fp32 = 8 * E + 12 * N;
+    o->stream_bytes_two_int8 = 4 * E + 3 * N;
+    o->stream_bytes_two_fp32 = 16 * E + 8 * N;
     return LDPC_OK;
 }
 
@@ -748,7 +782,11 @@ ldpc_status decode_job(const ldpc_code *c, int32_t n_frames, const void *llr_in,
     a.early_stop = p->early_stop ? 1 : 0;
     a.llr_in = llr_in;
     a.a8 = (int32_t)std::lround((double)p->alpha * 256.0);
-    a.b_int = p->msg == LDPC_MSG_FP32 ? 0 : (int32_t)std::lround((double)p->beta / (double)p->llr_step);
+    // offsets of 255 steps and more all zero every b-bit message (b <= 8):
+    // capped there so that the conversion stays in range
+    a.b_int = p->msg == LDPC_MSG_FP32
+                  ? 0
+                  : (int32_t)std::lround(std::fmin((double)p->beta / (double)p->llr_step, 255.0));
     a.alpha = p->alpha;
     a.beta = p->beta;
     a.step = (double)p->llr_step;

@@ -43,6 +43,7 @@ LAYOUT_NAME = {v: k for k, v in LAYOUT.items()}
 KERNEL_NAME = {0: "generic_int", 1: "generic_f32", 2: "two_scan", 3: "reg1", 4: "packed",
                5: "f32_frames", 6: "two_scan_frames"}  # ldpc_kernel
 ENC_KIND = {0: "none", 1: "staircase", 2: "dense"}
+STRUCT = {0x1: "qc", 0x2: "ira", 0x4: "ira_groups"}  # LDPC_STRUCT_* bits
 
 
 class LdpcError(RuntimeError):
@@ -70,7 +71,17 @@ class CodeInfo(ctypes.Structure):
                 ("lds_bytes_per_cu", ctypes.c_int32), ("reg_slots", ctypes.c_int32),
                 ("reg_rows_per_thread", ctypes.c_int32), ("reg_zpack", ctypes.c_int32),
                 ("pk_slots", ctypes.c_int32), ("pk_rows_per_thread", ctypes.c_int32),
-                ("pk_threads", ctypes.c_int32)]
+                ("pk_threads", ctypes.c_int32),
+                ("row_deg_hist", ctypes.c_int32 * 65), ("col_deg_hist", ctypes.c_int32 * 65),
+                ("structure", ctypes.c_int32), ("qc_lift", ctypes.c_int32), ("ira_group", ctypes.c_int32),
+                ("reserved", ctypes.c_int32),
+                ("var_values_single", ctypes.c_int64), ("var_values_two", ctypes.c_int64),
+                ("msg_bytes_int8", ctypes.c_int64), ("msg_bytes_1bit", ctypes.c_int64),
+                ("msg_bytes_fp32", ctypes.c_int64), ("post_bytes_int", ctypes.c_int64),
+                ("post_bytes_fp32", ctypes.c_int64),
+                ("stream_bytes_int8", ctypes.c_int64), ("stream_bytes_1bit", ctypes.c_int64),
+                ("stream_bytes_fp32", ctypes.c_int64), ("stream_bytes_two_int8", ctypes.c_int64),
+                ("stream_bytes_two_fp32", ctypes.c_int64)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -148,16 +159,45 @@ def make_params(max_iter=50, alpha=0.8, beta=0.0, early_stop=True, msg="int8",
     iteration, binary32 and fixed point).  ``msg_bits``: fixed-point message
     width 6 (default), 7 or 8 (INT8 single-scan)."""
     flags = (F_CHECK_INPUT if check_input else 0) | (LAYOUT[layout] << LAYOUT_SHIFT)
+    if weights is not None:
+        # (the device is checked per decode call: planning calls never read the pairs)
+        if not isinstance(weights, torch.Tensor) or weights.dtype != torch.float32 or \
+                weights.dim() != 3 or weights.shape[2] != 2 or \
+                weights.shape[0] < 1 or not weights.is_contiguous():
+            raise ValueError("weights must be a contiguous float32 tensor [T][C][2], T >= 1")
     wp = None if weights is None else weights.data_ptr()
     wt = 0 if weights is None else int(weights.shape[0])
-    return DecodeParams(int(max_iter), float(alpha), float(beta), 1 if early_stop else 0,
-                        MSG[msg] if isinstance(msg, str) else int(msg),
-                        SCHED[sched] if isinstance(sched, str) else int(sched),
-                        float(llr_step), int(flags), wp, wt, int(weight_classes), int(msg_bits))
+    p = DecodeParams(int(max_iter), float(alpha), float(beta), 1 if early_stop else 0,
+                     MSG[msg] if isinstance(msg, str) else int(msg),
+                     SCHED[sched] if isinstance(sched, str) else int(sched),
+                     float(llr_step), int(flags), wp, wt, int(weight_classes), int(msg_bits))
+    p._weights = weights  # kept alive with the parameters and checked against the code per call
+    return p
 
 
 def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t, name: str, dtype, shape, device: int, optional: bool = False) -> None:
+    """Raise ValueError unless ``t`` is a contiguous ``dtype`` tensor of
+    exactly ``shape`` on cuda:``device`` (or None when ``optional``).  The
+    kernels index these buffers by the code's sizes, so a wrong shape or
+    device would otherwise be read or written out of bounds."""
+    if t is None:
+        if optional:
+            return
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if not t.is_cuda or t.device.index != device:
+        raise ValueError(f"{name} must be on cuda:{device} (the code's device), not {t.device}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, not {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, not {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
 
 
 class Code:
@@ -190,6 +230,28 @@ class Code:
         except Exception:
             pass
 
+    @property
+    def n_classes(self) -> int:
+        """Number of check-degree classes (distinct row degrees)."""
+        if getattr(self, "_n_classes", None) is None:
+            n = ctypes.c_int32()
+            _check(lib().ldpc_learn_classes(self._h, ctypes.byref(n), None))
+            self._n_classes = int(n.value)
+        return self._n_classes
+
+    def _check_weights(self, params: DecodeParams) -> None:
+        """The weights a DecodeParams points at must match the code: float32
+        [weight_iters][C][2] on its device, C = 1 or the code's classes."""
+        if not params.weights:
+            return
+        w = getattr(params, "_weights", None)
+        if w is None:
+            raise ValueError("params.weights must be set by make_params(weights=...) so that it can be checked")
+        C = 1 if params.weight_classes == 1 else self.n_classes
+        _need(w, "weights", torch.float32, (int(params.weight_iters), C, 2), self.device)
+        if w.data_ptr() != params.weights:
+            raise ValueError("params.weights does not point at the tensor make_params was given")
+
     def degree_classes(self) -> np.ndarray:
         """Check-degree classes of the learned decoder (distinct row degrees)."""
         n = ctypes.c_int32()
@@ -205,7 +267,17 @@ class Code:
 
     def learn_forward(self, llr, target, weights, ckpt, workspace, post_out=None):
         """Raw forward pass (include/ldpc_learn.h); returns the per-iteration loss [T]."""
+        if not isinstance(llr, torch.Tensor) or llr.dim() != 2:
+            raise ValueError("llr must be a float32 device tensor [F, N]")
+        F = int(llr.shape[0])
+        _need(llr, "llr", torch.float32, (F, self.N), self.device)
+        _need(target, "target", torch.uint8, (F, self.N), self.device, optional=True)
+        if not isinstance(weights, torch.Tensor) or weights.dim() != 3:
+            raise ValueError("weights must be a float32 device tensor [T][C][2]")
         T = int(weights.shape[0])
+        _need(weights, "weights", torch.float32, (T, self.n_classes, 2), self.device)
+        _need(post_out, "post_out", torch.float32, (F, self.N), self.device, optional=True)
+        _need(workspace, "workspace", torch.uint8, (workspace.numel(),), self.device)
         loss = torch.empty(T, dtype=torch.float32, device=llr.device)
         _check(lib().ldpc_learn_forward(self._h, int(llr.shape[0]), _ptr(llr), _ptr(target), T, _ptr(weights),
                                         int(ckpt), _ptr(workspace), workspace.numel(), _ptr(loss),
@@ -214,6 +286,12 @@ class Code:
 
     def learn_backward(self, n_frames, target, weights, ckpt, workspace):
         """Raw adjoint: d(sum of the forward's losses)/d(weights), [T][C][2]."""
+        F = int(n_frames)
+        _need(target, "target", torch.uint8, (F, self.N), self.device, optional=True)
+        if not isinstance(weights, torch.Tensor) or weights.dim() != 3:
+            raise ValueError("weights must be a float32 device tensor [T][C][2]")
+        _need(weights, "weights", torch.float32, (int(weights.shape[0]), self.n_classes, 2), self.device)
+        _need(workspace, "workspace", torch.uint8, (workspace.numel(),), self.device)
         grad = torch.empty_like(weights)
         _check(lib().ldpc_learn_backward(self._h, int(n_frames), _ptr(target), int(weights.shape[0]),
                                          _ptr(weights), int(ckpt), _ptr(workspace), workspace.numel(),
@@ -237,9 +315,15 @@ class Code:
         return out
 
     def info(self) -> dict:
+        """ldpc_code_query as a dict; histograms as lists, ``structure`` as
+        the set of names of its LDPC_STRUCT_* bits."""
         i = CodeInfo()
         _check(lib().ldpc_code_query(self._h, ctypes.byref(i)))
-        return {k: getattr(i, k) for k, _ in CodeInfo._fields_}
+        d = {k: getattr(i, k) for k, _ in CodeInfo._fields_}
+        d["row_deg_hist"] = list(i.row_deg_hist)
+        d["col_deg_hist"] = list(i.col_deg_hist)
+        d["structure"] = {n for b, n in STRUCT.items() if i.structure & b}
+        return d
 
     def workspace_size(self, n_frames: int, params: DecodeParams) -> int:
         b = ctypes.c_size_t()
@@ -259,13 +343,32 @@ class Code:
 
     def decode_into(self, llr, params: DecodeParams, hard, llr_out, iters, ok, workspace,
                     stream=None) -> None:
-        """Raw call: all tensors are caller-allocated device tensors."""
-        n_frames = llr.shape[0] if llr.dim() == 2 else llr.numel() // self.N
+        """Raw call: all tensors are caller-allocated device tensors on the
+        code's device: llr [F, N] (float32 for FP32 messages, int8 otherwise),
+        hard uint8 [F, N], llr_out float32 [F, N] or None, iters int32 [F],
+        ok uint8 [F], workspace uint8 (or None).  Checked here (ValueError)
+        before the library is called."""
+        self.check_io(llr, params, hard, llr_out, iters, ok, workspace)
+        n_frames = int(llr.shape[0])
         s = stream if stream is not None else torch.cuda.current_stream(llr.device)
         ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
         _check(lib().ldpc_decode_batch(self._h, int(n_frames), _ptr(llr), ctypes.byref(params),
                                        _ptr(hard), _ptr(llr_out), _ptr(iters), _ptr(ok),
                                        _ptr(workspace), ws_bytes, ctypes.c_void_p(s.cuda_stream)))
+
+    def check_io(self, llr, params: DecodeParams, hard, llr_out, iters, ok, workspace) -> None:
+        """Shape, dtype, contiguity and device of one decode call's buffers."""
+        if not isinstance(llr, torch.Tensor) or llr.dim() != 2:
+            raise ValueError(f"llr must be a device tensor [F, {self.N}]")
+        F = int(llr.shape[0])
+        _need(llr, "llr", torch.float32 if params.msg == MSG["fp32"] else torch.int8, (F, self.N), self.device)
+        _need(hard, "hard", torch.uint8, (F, self.N), self.device)
+        _need(llr_out, "llr_out", torch.float32, (F, self.N), self.device, optional=True)
+        _need(iters, "iters", torch.int32, (F,), self.device)
+        _need(ok, "ok", torch.uint8, (F,), self.device)
+        if workspace is not None:
+            _need(workspace, "workspace", torch.uint8, (workspace.numel(),), self.device)
+        self._check_weights(params)
 
     def autotune(self, n_frames: int, params: DecodeParams) -> dict:
         """Time every layout that can run these parameters and make AUTO use
@@ -296,20 +399,34 @@ class Code:
                with_llr=True, stream=None, weights=None, weight_classes=0, msg_bits=0) -> dict:
         """Decode a [F, N] device tensor (float32 or int8) and return device
         tensors ``hard``, ``llr``, ``iters``, ``ok``."""
-        if not llr.is_cuda:
+        if not isinstance(llr, torch.Tensor) or not llr.is_cuda:
             raise ValueError("llr must be a device tensor")
-        llr = llr.contiguous()
         if msg is None:
             msg = "fp32" if llr.dtype == torch.float32 else "int8"
         want = torch.float32 if msg == "fp32" else torch.int8
         if llr.dtype != want:
             raise ValueError(f"msg={msg} needs a {want} tensor")
+        if llr.dim() != 2 or llr.shape[1] != self.N or llr.device.index != self.device:
+            raise ValueError(f"llr must be [F, {self.N}] on cuda:{self.device}, not "
+                             f"{list(llr.shape)} on {llr.device}")
         p = make_params(max_iter, alpha, beta, early_stop, msg, sched, llr_step,
                         check_input, layout, weights, weight_classes, msg_bits)
+        cur = torch.cuda.current_stream(llr.device)
+        s = stream if stream is not None else cur
+        llr = llr.contiguous()  # on the current stream, like the caller's own writes to llr
+        if s != cur:
+            # the decode on `s` must see llr (and the copy just made) complete;
+            # outputs and workspace come from `s`'s pool, and the inputs are
+            # marked as used there so that the allocator does not reuse them early
+            s.wait_stream(cur)
+            llr.record_stream(s)
+            if weights is not None:
+                weights.record_stream(s)
         F = llr.shape[0]
-        out = self.alloc_outputs(F, llr.device, with_llr)
-        ws = self.alloc_workspace(F, p, llr.device)
-        self.decode_into(llr, p, out["hard"], out["llr"], out["iters"], out["ok"], ws, stream)
+        with torch.cuda.stream(s):
+            out = self.alloc_outputs(F, llr.device, with_llr)
+            ws = self.alloc_workspace(F, p, llr.device)
+        self.decode_into(llr, p, out["hard"], out["llr"], out["iters"], out["ok"], ws, s)
         return out
 
 
@@ -329,8 +446,11 @@ class MultiBatch:
         self._jobs = (Job * max(n, 1))()
         self.outputs = []
         for k, (code, llr, p) in enumerate(self.items):
+            if not isinstance(llr, torch.Tensor) or llr.dim() != 2:
+                raise ValueError(f"job {k}: llr must be a device tensor [F, {code.N}]")
             F = int(llr.shape[0])
             out = code.alloc_outputs(F, llr.device, with_llr)
+            code.check_io(llr, p, out["hard"], out["llr"], out["iters"], out["ok"], None)
             self.outputs.append(out)
             self._jobs[k] = Job(code._h.value, F, llr.data_ptr(), p, out["hard"].data_ptr(),
                                 None if out["llr"] is None else out["llr"].data_ptr(),

@@ -464,3 +464,106 @@ def test_decode_plan_errors(L):
     with pytest.raises(L.LdpcError):
         c.plan(10, fr)
     c.close()
+
+
+# ---------------------------------------------------------------------------
+# ldpc_code_query: degree histograms, block structure and per-frame storage.
+def _qc_from_base(base, Z):
+    """H from a base matrix of shifts (-1: empty block), Z x Z circulants."""
+    mb, nb = base.shape
+    rows = [[] for _ in range(mb * Z)]
+    for i in range(mb):
+        for j in range(nb):
+            s = base[i, j]
+            if s >= 0:
+                for r in range(Z):
+                    rows[i * Z + r].append(j * Z + (r + s) % Z)
+    return W.ParityCheck.from_rows(mb * Z, nb * Z, rows, "qc_small")
+
+
+@pytest.mark.parametrize("name", ["peg1008", "qc7493", "ira16200", "ira64800"])
+def test_query_histograms_and_storage(L, name):
+    """Histograms add up to M, N and E; single-scan keeps N stored
+    variable-side values where two-scan keeps N x mean column degree = E
+    (Sec. IV); addressing is halved; messages are b E bits with b <= 8 in
+    one byte, and the 1-bit form E sign bits plus a few bits per check
+    (Sec. V); the streaming traffic model follows from those sizes."""
+    code = {"peg1008": W.code_c0_peg1008, "qc7493": W.code_c1_qc7493, "ira16200": W.code_ira16200,
+            "ira64800": W.code_c2_ira64800}[name]()
+    i = L.Code.from_parity_check(code, device=-1).info()
+    M, N, E = code.M, code.N, code.E
+    rh, ch = np.array(i["row_deg_hist"]), np.array(i["col_deg_hist"])
+    np.testing.assert_array_equal(rh, np.bincount(code.row_degrees(), minlength=65))
+    np.testing.assert_array_equal(ch, np.bincount(code.col_degrees(), minlength=65))
+    assert rh.sum() == M and ch.sum() == N
+    assert (rh * np.arange(65)).sum() == E and (ch * np.arange(65)).sum() == E
+    assert i["var_values_single"] == N
+    assert i["var_values_two"] == E
+    assert i["var_values_two"] == pytest.approx(N * code.col_degrees().mean())
+    assert i["addr_bytes_two"] == 2 * i["addr_bytes_single"] == 8 * E
+    assert i["msg_bytes_int8"] * 8 == i["msg_bits_int8"] == 8 * E
+    assert i["msg_bytes_fp32"] == 4 * E and i["post_bytes_fp32"] == 4 * N and i["post_bytes_int"] == 2 * N
+    lg = int(np.ceil(np.log2(code.row_degrees().max())))
+    assert i["msg_bits_1bit"] == E + M * (5 + 5 + lg)
+    assert i["msg_bytes_1bit"] == (E + 7) // 8 + 2 * M
+    assert 8 * i["msg_bytes_1bit"] >= i["msg_bits_1bit"]  # the stored form holds the Sec. V state
+    assert i["stream_bytes_int8"] == 2 * E + 5 * N
+    assert i["stream_bytes_1bit"] == 2 * ((E + 7) // 8) + 4 * M + 5 * N
+    assert i["stream_bytes_fp32"] == 8 * E + 12 * N
+    assert i["stream_bytes_two_int8"] == 4 * E + 3 * N
+    assert i["stream_bytes_two_fp32"] == 16 * E + 8 * N
+    want = {"peg1008": (set(), 0, 0), "qc7493": ({"qc"}, 127, 0), "ira16200": ({"ira", "ira_groups"}, 0, 180),
+            "ira64800": ({"ira", "ira_groups"}, 0, 360)}[name]
+    assert (i["structure"], i["qc_lift"], i["ira_group"]) == want
+
+
+def test_query_structure_detection(L):
+    rng = np.random.default_rng(3)
+    base = rng.integers(-1, 13, size=(4, 9))
+    base[:, 0] = rng.integers(0, 13, size=4)  # no empty block column
+    code = _qc_from_base(base, 13)
+    i = L.Code.from_parity_check(code, device=-1).info()
+    assert i["structure"] == {"qc"} and i["qc_lift"] == 13
+    # one entry moved inside its block breaks the circulant: no QC lift of 13
+    rows = [list(code.col_idx[code.row_ptr[m]:code.row_ptr[m + 1]]) for m in range(code.M)]
+    c0 = rows[0][0]
+    alt = (c0 // 13) * 13 + (c0 % 13 + 1) % 13
+    if alt not in rows[0]:
+        rows[0][0] = alt
+        broken = W.ParityCheck.from_rows(code.M, code.N, rows, "qc_broken")
+        assert L.Code.from_parity_check(broken, device=-1).info()["qc_lift"] != 13
+    # columns permuted at random: no structure left
+    perm = rng.permutation(code.N)
+    shuffled = W.ParityCheck.from_rows(code.M, code.N, [perm[r] for r in rows], "qc_shuffled")
+    assert L.Code.from_parity_check(shuffled, device=-1).info()["structure"] == set()
+    # a small repeat-accumulate code: staircase and 36-column groups
+    ira = W.ira_code(720, 360, 36, {5: 5, 3: 5}, seed=11, name="ira720")
+    i = L.Code.from_parity_check(ira, device=-1).info()
+    assert i["structure"] == {"ira", "ira_groups"} and i["ira_group"] == 36
+    # swap two staircase columns: neither bit
+    rows = [list(ira.col_idx[ira.row_ptr[m]:ira.row_ptr[m + 1]]) for m in range(ira.M)]
+    a, b = ira.N - ira.M + 5, ira.N - ira.M + 9
+    sw = W.ParityCheck.from_rows(ira.M, ira.N, [[b if c == a else a if c == b else c for c in r] for r in rows],
+                                 "ira_swapped")
+    assert L.Code.from_parity_check(sw, device=-1).info()["structure"] == set()
+
+
+def test_binding_rejects_host_tensors(L):
+    """Buffers on the wrong device are refused before the library is called."""
+    import torch
+    code = W.code_c0_peg1008()
+    gc = L.Code.from_parity_check(code, device=-1)
+    x = torch.zeros((2, code.N), dtype=torch.int8)
+    o = {"hard": torch.zeros((2, code.N), dtype=torch.uint8), "llr": None,
+         "iters": torch.zeros(2, dtype=torch.int32), "ok": torch.zeros(2, dtype=torch.uint8)}
+    with pytest.raises(ValueError):
+        gc.decode_into(x, L.make_params(msg="int8"), o["hard"], o["llr"], o["iters"], o["ok"], None)
+    with pytest.raises(ValueError):
+        gc.decode(x, msg="int8")
+    for w in (torch.zeros((3, 1, 2), dtype=torch.float64), torch.zeros((3, 1, 3)), torch.zeros((0, 1, 2))):
+        with pytest.raises(ValueError):
+            L.make_params(msg="fp32", weights=w)
+    p = L.make_params(msg="fp32", weights=torch.zeros((3, 1, 2)), weight_classes=1)  # planning only
+    assert gc.workspace_size(300, p) > 0
+    with pytest.raises(ValueError):  # a host table cannot be decoded with
+        gc.decode_into(x.float(), p, o["hard"], o["llr"], o["iters"], o["ok"], None)

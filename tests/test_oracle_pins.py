@@ -387,3 +387,30 @@ def test_oracle_rejects_bad_input(orc):
     bad = W.ParityCheck(1, 3, np.array([0, 1], dtype=np.int32), np.array([0], dtype=np.int32))
     with pytest.raises(ValueError):
         orc.decode(bad, np.zeros((1, 3), dtype=np.int8), arith="int")
+
+
+# --------------------------------------------------------------------------
+# Offsets beyond every magnitude (Sec. III OMS: max(|L| - beta, 0) = 0 once
+# beta exceeds every minimum): all messages are zero, so every posterior
+# stays at Z(0), in every algorithm and arithmetic, including offsets whose
+# step count would not fit a 32-bit integer.
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("beta", [16.0, 1e6, 1e12, 3.4e38])
+@pytest.mark.parametrize("algo,arith", [("single_scan", "int"), ("one_bit", "int"), ("two_scan", "int"),
+                                        ("single_scan", "f32"), ("single_scan", "f64"),
+                                        ("two_scan", "f64")])
+def test_huge_offset_zeroes_every_message(orc, beta, algo, arith):
+    code = W.code_c0_peg1008()
+    llr = W.awgn_llr(code.N, 3, 1.5, code.design_rate, key=(0xB7A, 1))
+    x = W.quantize_llr(llr) if arith == "int" else llr
+    r = orc.decode(code, x, algo=algo, arith=arith, max_iter=4, alpha=0.8, beta=beta,
+                   early_stop=False, trace=True)
+    assert not np.any(r["L"])
+    z0 = x.astype(np.float64) * (0.5 if arith == "int" else 1.0)
+    np.testing.assert_array_equal(r["post"].astype(np.float64), z0.astype(r["post"].dtype).astype(np.float64))
+    if arith == "int":
+        for sched in ([[0.8, beta]], [[0.8, 0.0], [0.8, beta]]):
+            rs = orc.decode(code, x, algo=algo, arith="int", max_iter=3, sched=sched, early_stop=False,
+                            trace=True) if algo != "two_scan" else None
+            if rs is not None:
+                assert not np.any(rs["L"][:, len(sched) - 1:])
