@@ -3,12 +3,15 @@
 //   horizontal scan, Eq. (1): per check row, from the stored variable-to-check
 //     messages Z_mn (one per edge) compute and store L_mn (NMS/OMS applied);
 //   vertical scan, Eq. (2): per variable, Z_n = Z^(0)_n + sum L_mn over M(n)
-//     (ascending checks, through the variable-to-check index) and
-//     Z_mn = Z_n - L_mn written back to every edge (fixed point: saturated to
-//     +-31, which equals saturating the exclusion sum of Eq. 2).
+//     (ascending checks, through the variable-to-check index) and every Z_mn
+//     written back: fixed point as sat(Z_n - L_mn) to +-31, which equals
+//     saturating the exclusion sum of Eq. 2; binary32 as that exclusion sum
+//     itself, Z^(0)_n + the other L_m'n in ascending check order.
 // Per-edge state: Z_mn and L_mn, both int8 or binary32, [D][Mp] slot-major.
 // The posterior array Z_n is kept for the hard decision and the output.
 #include "ldpc_internal.h"
+
+#include <type_traits>
 
 namespace ldpc {
 namespace {
@@ -134,7 +137,14 @@ __global__ void __launch_bounds__(launch_bound_for(DMAX)) two_scan_kernel(Decode
             Zn[n] = (ZN)s;
             for (int e = e0; e < e1; ++e) {
                 const uint32_t slot = vc_slot[e];
-                Zmn[slot] = (T)S::ext(s, (A_t)L[slot]);
+                if constexpr (std::is_same<T, float>::value) {
+                    A_t v = (A_t)S::load_in(a.llr_in, fo + n);
+                    for (int e2 = e0; e2 < e1; ++e2)
+                        if (e2 != e) v = S::add(v, (A_t)L[vc_slot[e2]]);
+                    Zmn[slot] = (T)v;
+                } else {
+                    Zmn[slot] = (T)S::ext(s, (A_t)L[slot]);
+                }
             }
         }
         __syncthreads();

@@ -12,13 +12,16 @@
 //   horizontal (rows)     L_mn = prod sgn * norm(min |Z_mn'|) over n' != n,
 //                         from min1/argmin/min2 and the sign parity of the row
 //   vertical (variables)  Z_n = Z^(0)_n + sum of L_mn over M(n) (ascending
-//                         check order), then Z_mn = Z_n - L_mn for every edge
-//                         (saturated to the message range in fixed point)
+//                         check order), then every Z_mn as Eq. (2) writes it
+//                         (fixed point: sat(Z_n - L_mn), the saturated
+//                         exclusion sum exactly; binary32: its own sum
+//                         Z^(0)_n + the other L_m'n in ascending check order)
 // The vertical scan reaches the row-ordered arrays through the
 // variable-to-check index: the second addressing table that the single-scan
-// form does without.  Fixed point: 6-bit messages in int8, Z_n in int16;
-// binary32: Z_mn = Z_n - L_mn rounded once, which is exactly the single-scan
-// extrinsic.  Early stop and outputs as in the single-scan frames-across-lanes
+// form does without.  Fixed point: 6-bit messages in int8, Z_n in int16.
+// In binary32 the exclusion sums round differently from Z_n - L_mn (the
+// single-scan extrinsic), so the two schedules are not bitwise equal there.
+// Early stop and outputs as in the single-scan frames-across-lanes
 // decoder (syndrome of Z^(k) formed in the horizontal scan of iteration k+1).
 #include "fl_common.h"
 
@@ -290,8 +293,10 @@ __global__ void __launch_bounds__(kBlock) ts_vars(TsArgs a, int fail_row) {
     };
     for (int n = w / a.G; n < a.N; n += a.rwaves) {
         const int e0 = vp[n], e1 = vp[n + 1];
-        T s[V], cp[V];
+        T s[V], cp[V], z0v[V];
         ld_msg<INT, V>(b0, s, foe, (uint32_t)n * rowe);
+#pragma unroll
+        for (int c = 0; c < V; ++c) z0v[c] = s[c];
         if (FREEZE) ld_post<INT, V>(bn, cp, fc, (uint32_t)n * rowz);
         T l[8][V];
         uint32_t eo[8];
@@ -326,7 +331,60 @@ __global__ void __launch_bounds__(kBlock) ts_vars(TsArgs a, int fail_row) {
         // extrinsics: a variable of degree <= 8 still holds its messages and
         // their offsets in registers (out-of-range slots are dropped stores);
         // larger degrees read them again
-        if (e1 - e0 <= 8) {
+        if constexpr (!INT) {
+            // binary32, Eq. (2) as written: Z_mn = Z^(0)_n + the other L_m'n in
+            // ascending check order.  x[i] starts from the prefix Z^(0) + l[0..i-1]
+            // and adds l[i+1..]; degrees above 8 stream the other chunks again
+            if (e1 - e0 <= 8) {
+                const int deg = e1 - e0;
+                T pre[V];
+#pragma unroll
+                for (int c = 0; c < V; ++c) pre[c] = z0v[c];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    T x[V];
+#pragma unroll
+                    for (int c = 0; c < V; ++c) x[c] = pre[c];
+#pragma unroll
+                    for (int j = i + 1; j < 8; ++j)
+#pragma unroll
+                        for (int c = 0; c < V; ++c) x[c] = j < deg ? __fadd_rn(x[c], l[j][c]) : x[c];
+                    st_msg<INT, V>(bm, x, foe, eo[i]);
+#pragma unroll
+                    for (int c = 0; c < V; ++c) pre[c] = i < deg ? __fadd_rn(pre[c], l[i][c]) : pre[c];
+                }
+            } else {
+                for (int e = e0; e < e1; e += 8) {  // eight outputs at a time
+                    uint32_t oo[8];
+                    T x[8][V];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        oo[i] = e + i < e1 ? vcs[e + i] * rowe : kOutOfRange;
+#pragma unroll
+                        for (int c = 0; c < V; ++c) x[i][c] = z0v[c];
+                    }
+                    for (int e2 = e0; e2 < e1; e2 += 8) {  // every input chunk, ascending
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) {
+                            const uint32_t ce = vcs[e2 + j];
+                            eo[j] = e2 + j < e1 ? ce * rowe : kOutOfRange;
+                        }
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) ld_msg<INT, V>(bl, l[j], foe, eo[j]);
+#pragma unroll
+                        for (int i = 0; i < 8; ++i)
+#pragma unroll
+                            for (int j = 0; j < 8; ++j) {
+                                const bool use = e2 + j < e1 && e2 + j != e + i;
+#pragma unroll
+                                for (int c = 0; c < V; ++c) x[i][c] = use ? __fadd_rn(x[i][c], l[j][c]) : x[i][c];
+                            }
+                    }
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) st_msg<INT, V>(bm, x[i], foe, oo[i]);
+                }
+            }
+        } else if (e1 - e0 <= 8) {
 #pragma unroll
             for (int i = 0; i < 8; ++i) st_ext(s, l[i], eo[i]);
         } else {

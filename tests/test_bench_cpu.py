@@ -47,3 +47,21 @@ def test_measured_traffic_matches_its_profile(entry):
     cmd = next(line for line in text.splitlines() if line.startswith("rocprofv3 --kernel-trace"))
     assert (f"--msg {msg}" in cmd) if msg != "int8" else ("--msg" not in cmd or "--msg int8" in cmd)
     assert ("--sched two_scan" in cmd) == (sched == "two_scan")
+
+
+def test_cpu_baseline_fields():
+    """The CPU baseline reports the threads it used, the host's CPU count,
+    the single-thread rate and the oracle's single-scan / two-scan ratio
+    on the same frames."""
+    from paper_cs_0609090_amd import workloads as W
+    code = W.code_c0_peg1008()
+    q = W.quantize_llr(W.awgn_llr(code.N, 8, 1.0, code.design_rate, key=(0xC2, 0xBE)))
+    cb = bench.cpu_baseline(code, q, 8, 8)
+    threads, host = bench.host_threads()
+    assert cb["kind"] == "oracle" and cb["cores"] == threads and cb["host_cpus"] == host
+    assert 1 <= threads <= 16
+    assert cb["value"] > 0 and cb["single_thread"]["coded_gbps"] > 0
+    assert cb["two_scan_single_thread"]["coded_gbps"] > 0
+    w1, w2 = cb["single_thread"]["wall_s"], cb["two_scan_single_thread"]["wall_s"]
+    r = w2 / w1  # from the rounded walls: allow for the rounding
+    assert abs(cb["single_scan_over_two_scan"] - r) <= 0.002 + r * 1e-3 * (1 / w1 + 1 / w2)

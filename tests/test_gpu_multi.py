@@ -30,7 +30,7 @@ def L(torch_dev):
 
 ORACLE_VARIANT = {("int8", "single_scan"): ("single_scan", "int"), ("1bit", "single_scan"): ("one_bit", "int"),
                   ("fp32", "single_scan"): ("single_scan", "f32"), ("int8", "two_scan"): ("two_scan", "int"),
-                  ("fp32", "two_scan"): ("single_scan", "f32")}
+                  ("fp32", "two_scan"): ("two_scan", "f32")}
 
 
 def _host_llr(code, F, msg, seed):
