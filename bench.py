@@ -70,6 +70,10 @@ MEASURED_TRAFFIC = [
      "bytes": 105147.1e6, "profile": "profiles/fl_f32_ira64800_512f.md"},
     {"kernel": "reg1", "hash": "e7d86239f37f995e", "workload": ("int8", "single_scan", 512, 50),
      "bytes": 221.2e6, "profile": "profiles/ss_reg_int8_ira64800_512f.md"},
+    {"kernel": "two_scan_frames", "hash": "0f330c006512febe", "workload": ("int8", "two_scan", 512, 50),
+     "bytes": 29393.9e6, "profile": "profiles/ts_fl_int8_ira64800_512f.md"},
+    {"kernel": "two_scan_frames", "hash": "0f330c006512febe", "workload": ("fp32", "two_scan", 512, 50),
+     "bytes": 107937.4e6, "profile": "profiles/ts_fl_f32_ira64800_512f.md"},
 ]
 
 

@@ -27,12 +27,16 @@ ALGOS = ("two_scan", "single_scan", "one_bit")
 ARITHS = ("int", "f32", "f64")
 
 
-def build(force: bool = True) -> str:
-    """Compile liboracle.so with gcc (-O2, no FP contraction)."""
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile liboracle.so with gcc (-O2, no FP contraction).  ``sanitize``:
+    with AddressSanitizer and UndefinedBehaviorSanitizer (load it with gcc's
+    libasan preloaded: LD_PRELOAD=$(gcc -print-file-name=libasan.so))."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
+        san = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+               "-fno-omit-frame-pointer"] if sanitize else []
         cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
-               "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC[0], "-lm"]
+               "-fPIC", "-shared", "-Wall", *san, "-o", tmp, _SRC[0], "-lm"]
         subprocess.run(cmd, check=True, cwd=_HERE)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH

@@ -30,24 +30,38 @@ def sources() -> list[str]:
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
+# Host-side AddressSanitizer + UndefinedBehaviorSanitizer (the runtime's host
+# code only; device code is built as usual).  Load the result with clang's
+# ASan runtime preloaded, e.g.
+#   LD_PRELOAD=$(hipcc -print-file-name=libclang_rt.asan-x86_64.so) python -m pytest -m "not gpu"
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+_sanitize = False
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.basename(src)[:-4] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, *(SAN_FLAGS if _sanitize else []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
-    """Compile every csrc/*.hip and link libldpc.so; returns its path."""
+def build(jobs: int | None = None, verbose: bool = False, sanitize: bool = False) -> str:
+    """Compile every csrc/*.hip and link libldpc.so; returns its path.
+    ``sanitize``: instrument the host code with ASan and UBSan."""
+    global _sanitize
+    _sanitize = sanitize
     os.makedirs(OBJ, exist_ok=True)
     srcs = sources()
     jobs = jobs or min(len(srcs), os.cpu_count() or 4, 8)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
+           *(["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+              "-shared-libsan"] if sanitize else [])]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
@@ -64,5 +78,5 @@ def clean() -> None:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, sanitize="--sanitize" in sys.argv)
     sys.exit(0)

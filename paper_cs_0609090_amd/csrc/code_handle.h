@@ -91,4 +91,13 @@ ldpc_status decode_job(const ldpc_code *c, int32_t n_frames, const void *llr_in,
 // error state of the calling thread (ldpc_last_error), set by every entry point
 ldpc_status set_error(ldpc_status st, const std::string &msg);
 void clear_error();
+
+// Device allocations of the library's own buffers (code handles, the encoder,
+// autotuning trials).  Failure injection for tests of the error paths: with
+// the environment variable LDPC_FAIL_ALLOC=k (k >= 1), the k-th allocation
+// after the last reset_alloc_count() on the calling thread fails as an
+// out-of-memory error would, without touching the device.  Entry points that
+// allocate reset the count when they start.
+hipError_t dev_malloc(void **p, size_t bytes);
+void reset_alloc_count();
 }  // namespace ldpc

@@ -234,11 +234,12 @@ ldpc_status ldpc_autotune(ldpc_code *code, int32_t n_frames, const ldpc_decode_p
     int32_t *iters = nullptr;
     hipStream_t s = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t e = hipMalloc(&llr, cnt * (fp32 ? 4 : 1));
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&hard), cnt);
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&iters), 4 * (size_t)n_frames);
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&ok), (size_t)n_frames);
-    if (e == hipSuccess && ws_max > 0) e = hipMalloc(&ws, ws_max);
+    ldpc::reset_alloc_count();
+    hipError_t e = ldpc::dev_malloc(&llr, cnt * (fp32 ? 4 : 1));
+    if (e == hipSuccess) e = ldpc::dev_malloc(reinterpret_cast<void **>(&hard), cnt);
+    if (e == hipSuccess) e = ldpc::dev_malloc(reinterpret_cast<void **>(&iters), 4 * (size_t)n_frames);
+    if (e == hipSuccess) e = ldpc::dev_malloc(reinterpret_cast<void **>(&ok), (size_t)n_frames);
+    if (e == hipSuccess && ws_max > 0) e = ldpc::dev_malloc(&ws, ws_max);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);

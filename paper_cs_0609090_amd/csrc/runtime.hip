@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <tuple>
@@ -347,6 +348,21 @@ namespace ldpc {
 // error state of the calling thread, for the other entry points of the library
 ldpc_status set_error(ldpc_status st, const std::string &msg) { return fail(st, msg); }
 void clear_error() { g_err.clear(); }
+
+namespace {
+thread_local long g_alloc_count = 0;
+}
+void reset_alloc_count() { g_alloc_count = 0; }
+hipError_t dev_malloc(void **p, size_t bytes) {
+    ++g_alloc_count;
+    if (const char *f = std::getenv("LDPC_FAIL_ALLOC")) {
+        if (std::atol(f) == g_alloc_count) {
+            *p = nullptr;
+            return hipErrorOutOfMemory;
+        }
+    }
+    return hipMalloc(p, bytes);
+}
 }  // namespace ldpc
 
 namespace ldpc {
@@ -509,41 +525,17 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
             }
         }
     }
-    if (device < 0) {  // host-only handle: planning and queries, no decoding
-        c->lds_limit = kHostOnlyLds;
-        *out = c;
-        g_err.clear();
-        return LDPC_OK;
-    }
-    DeviceGuard g(device);
-    if (!g.ok) {
-        delete c;
-        return fail(LDPC_EDEVICE, "hipSetDevice failed");
-    }
-    int lds = 0, cus = 0;
-    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
-        c->lds_limit = lds;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
-        c->cu_count = cus;
-    hipError_t e1 = hipMalloc(&c->d_ell, slots * sizeof(uint32_t));
-    hipError_t e7 = hipMalloc(&c->d_row_ptr, ((size_t)M + 1) * sizeof(int32_t));
-    hipError_t e8 = hipMalloc(&c->d_row_ent, row_ent.size() * sizeof(uint32_t));
-    hipError_t e9 = hipMalloc(&c->d_vc_csr, vc_csr.size() * sizeof(uint32_t));
-    hipError_t e10 = hipMalloc(&c->d_row_cls, sizeof(int32_t) * std::max<size_t>(row_cls.size(), 1));
-    hipError_t e2 = hipMalloc(&c->d_vc_ptr, vc_ptr.size() * sizeof(int32_t));
-    hipError_t e3 = hipMalloc(&c->d_vc_slot, vc_slot.size() * sizeof(uint32_t));
+    // host-side layouts of the register kernels (built for host-only handles
+    // too, so that planning and the host checks cover the same code)
     std::vector<uint32_t> ell_reg;
-    hipError_t e4 = hipSuccess;
     if (c->regD > 0) {
         const size_t Mr = (size_t)c->regR * ldpc::kRegThreads;
         ell_reg.assign((size_t)c->regD * Mr, (uint32_t)c->dummy);
         for (int m = 0; m < M; ++m)
             for (int j = 0; j < row_ptr[m + 1] - row_ptr[m]; ++j)
                 ell_reg[(size_t)j * Mr + m] = (uint32_t)col_idx[row_ptr[m] + j];
-        e4 = hipMalloc(&c->d_ell_reg, ell_reg.size() * sizeof(uint32_t));
     }
     std::vector<uint32_t> pk_idx, pk_slot;
-    hipError_t e5 = hipSuccess, e6 = hipSuccess;
     if (c->pkD > 0) {
         // record {zold_a, zold_b, acc_a, acc_b} of slot j of rows a = p*T/S + t/S,
         // b = (p + R/2)*T/S + t/S (T threads, S lanes per row; lane t holds the
@@ -574,8 +566,36 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
                             r[2 + h] = (zacc_off + (nwords + (uint32_t)(t & 63)) * 4u) << 5;
                         }
                     }
-        e5 = hipMalloc(&c->d_pk_idx, pk_idx.size() * sizeof(uint32_t));
-        e6 = hipMalloc(&c->d_pk_slot, pk_slot.size() * sizeof(uint32_t));
+    }
+    if (device < 0) {  // host-only handle: planning and queries, no decoding
+        c->lds_limit = kHostOnlyLds;
+        *out = c;
+        g_err.clear();
+        return LDPC_OK;
+    }
+    DeviceGuard g(device);
+    if (!g.ok) {
+        delete c;
+        return fail(LDPC_EDEVICE, "hipSetDevice failed");
+    }
+    ldpc::reset_alloc_count();
+    int lds = 0, cus = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+        c->lds_limit = lds;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        c->cu_count = cus;
+    hipError_t e1 = ldpc::dev_malloc((void **)&c->d_ell, slots * sizeof(uint32_t));
+    hipError_t e7 = ldpc::dev_malloc((void **)&c->d_row_ptr, ((size_t)M + 1) * sizeof(int32_t));
+    hipError_t e8 = ldpc::dev_malloc((void **)&c->d_row_ent, row_ent.size() * sizeof(uint32_t));
+    hipError_t e9 = ldpc::dev_malloc((void **)&c->d_vc_csr, vc_csr.size() * sizeof(uint32_t));
+    hipError_t e10 = ldpc::dev_malloc((void **)&c->d_row_cls, sizeof(int32_t) * std::max<size_t>(row_cls.size(), 1));
+    hipError_t e2 = ldpc::dev_malloc((void **)&c->d_vc_ptr, vc_ptr.size() * sizeof(int32_t));
+    hipError_t e3 = ldpc::dev_malloc((void **)&c->d_vc_slot, vc_slot.size() * sizeof(uint32_t));
+    hipError_t e4 = hipSuccess, e5 = hipSuccess, e6 = hipSuccess;
+    if (!ell_reg.empty()) e4 = ldpc::dev_malloc((void **)&c->d_ell_reg, ell_reg.size() * sizeof(uint32_t));
+    if (!pk_idx.empty()) {
+        e5 = ldpc::dev_malloc((void **)&c->d_pk_idx, pk_idx.size() * sizeof(uint32_t));
+        e6 = ldpc::dev_malloc((void **)&c->d_pk_slot, pk_slot.size() * sizeof(uint32_t));
     }
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || e5 != hipSuccess ||
         e6 != hipSuccess || e7 != hipSuccess || e8 != hipSuccess || e9 != hipSuccess || e10 != hipSuccess) {

@@ -297,17 +297,30 @@ ldpc_status ensure_encoder(ldpc_code *c) {
         int prev = -1;
         (void)hipGetDevice(&prev);
         if (hipSetDevice(c->device) != hipSuccess) return set_error(LDPC_EDEVICE, "hipSetDevice failed");
-        hipError_t e = hipMalloc(&c->d_info_pos, sizeof(int32_t) * c->h_info_pos.size());
+        ldpc::reset_alloc_count();
+        bool oom = false;
+        hipError_t e = ldpc::dev_malloc((void **)&c->d_info_pos, sizeof(int32_t) * c->h_info_pos.size());
+        oom = e != hipSuccess;
         if (e == hipSuccess)
             e = hipMemcpy(c->d_info_pos, c->h_info_pos.data(), sizeof(int32_t) * c->h_info_pos.size(),
                           hipMemcpyHostToDevice);
         if (e == hipSuccess && !rows.empty()) {
-            e = hipMalloc(&c->d_enc_rows, sizeof(uint32_t) * rows.size());
+            e = ldpc::dev_malloc((void **)&c->d_enc_rows, sizeof(uint32_t) * rows.size());
+            oom = e != hipSuccess;
             if (e == hipSuccess)
                 e = hipMemcpy(c->d_enc_rows, rows.data(), sizeof(uint32_t) * rows.size(), hipMemcpyHostToDevice);
         }
+        if (e != hipSuccess) {  // leave the handle as it was: a later call builds the tables again
+            if (c->d_info_pos) (void)hipFree(c->d_info_pos);
+            if (c->d_enc_rows) (void)hipFree(c->d_enc_rows);
+            c->d_info_pos = nullptr;
+            c->d_enc_rows = nullptr;
+            (void)hipGetLastError();
+        }
         if (prev >= 0) (void)hipSetDevice(prev);
-        if (e != hipSuccess) return set_error(LDPC_EDEVICE, "encoder tables: device allocation or copy failed");
+        if (e != hipSuccess)
+            return oom ? set_error(LDPC_ENOMEM, "encoder tables: device allocation failed")
+                       : set_error(LDPC_EDEVICE, "encoder tables: copy to the device failed");
     }
     c->enc_built = true;
     return LDPC_OK;

@@ -219,3 +219,51 @@ def test_two_fields_per_word_accumulator(torch_dev, L, orc, msg, layout):
         if es:
             assert len(set(r["iters"].tolist())) > 2
     gc.close()
+
+
+# ---------------------------------------------------------------------------
+# Device allocation failures (injected from the host: LDPC_FAIL_ALLOC=k fails
+# the k-th device allocation of an entry point) are reported as LDPC_ENOMEM,
+# leave no half-built state behind, and the same call succeeds afterwards.
+def test_injected_allocation_failures(torch_dev, L, orc, monkeypatch):
+    torch = torch_dev
+    code = W.code_c0_peg1008()
+    free0 = torch.cuda.mem_get_info()[0]
+    first_ok = None
+    for k in range(1, 16):
+        monkeypatch.setenv("LDPC_FAIL_ALLOC", str(k))
+        try:
+            gc = L.Code.from_parity_check(code)
+        except L.LdpcError as e:
+            assert e.status == L.LDPC_ENOMEM, (k, str(e))
+            continue
+        gc.close()
+        first_ok = k
+        break
+    assert first_ok is not None and first_ok >= 8  # the handle's device tables, each failed in turn
+    monkeypatch.delenv("LDPC_FAIL_ALLOC")
+    torch.cuda.synchronize()
+    assert abs(torch.cuda.mem_get_info()[0] - free0) < (64 << 20)
+    gc = L.Code.from_parity_check(code)
+    q = W.quantize_llr(W.awgn_llr(code.N, 8, 2.0, code.design_rate, key=(0xFA, 1)))
+    g = _np(gc.decode(torch.from_numpy(q).cuda(), msg="int8", max_iter=10))
+    r = orc.decode(code, q, algo="single_scan", arith="int", max_iter=10)
+    np.testing.assert_array_equal(g["llr"], r["post"])
+    # the encoder's tables, built on first use: each allocation failed in turn
+    for k in (1, 2):
+        monkeypatch.setenv("LDPC_FAIL_ALLOC", str(k))
+        with pytest.raises(L.LdpcError) as ei:
+            gc.encoder_info()
+        assert ei.value.status == L.LDPC_ENOMEM
+    monkeypatch.delenv("LDPC_FAIL_ALLOC")
+    K = gc.encoder_info()["K"]
+    info = torch.randint(0, 2, (4, K), dtype=torch.uint8, device="cuda")
+    cw = gc.encode(info).cpu().numpy()
+    assert not code.syndrome(cw).any()
+    # autotuning's trial buffers
+    monkeypatch.setenv("LDPC_FAIL_ALLOC", "2")
+    with pytest.raises(L.LdpcError):
+        gc.autotune(16, L.make_params(msg="int8", max_iter=5))
+    monkeypatch.delenv("LDPC_FAIL_ALLOC")
+    assert gc.autotune(16, L.make_params(msg="int8", max_iter=5))["tried"] >= 2
+    gc.close()
