@@ -299,6 +299,27 @@ ldpc_status ldpc_decode_batch(const ldpc_code *code, int32_t n_frames, const voi
                               int32_t *iters_out, uint8_t *syndrome_ok, void *workspace,
                               size_t workspace_bytes, void *stream);
 
+/*
+ * ldpc_decode_batch for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc):
+ * the same decode, with the workspace taken from a static device array of
+ * LDPC_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends (its address is looked up once per device, when the
+ * first handle on that device is created).  The caller still owns every
+ * input and output buffer.  Calls no hipMalloc, hipFree or allocating
+ * routine; asynchronous on `stream` like ldpc_decode_batch.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind (the kernels initialise what they read), so calls that overlap in
+ * time on one GPU (different streams, threads or processes sharing it) race:
+ * order them on one stream.
+ * Errors: those of ldpc_decode_batch, and LDPC_EUNSUPPORTED when the call's
+ * ldpc_decode_workspace_size() exceeds LDPC_NOALLOC_SCRATCH_BYTES.
+ */
+#define LDPC_NOALLOC_SCRATCH_BYTES (128u << 20)
+ldpc_status ldpc_decode_batch_noalloc(const ldpc_code *code, int32_t n_frames, const void *llr_in,
+                                      const ldpc_decode_params *p, uint8_t *hard_out, float *llr_out,
+                                      int32_t *iters_out, uint8_t *syndrome_ok, void *stream);
+
 /* Message describing the last failure on the calling thread ("" if none). */
 const char *ldpc_last_error(void);
 

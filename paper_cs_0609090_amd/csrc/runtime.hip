@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -30,6 +31,37 @@ ldpc_status fail(ldpc_status st, const std::string &msg) {
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 using ldpc::DeviceGuard;
+
+}  // namespace
+
+// Workspace of ldpc_decode_batch_noalloc: a device global of the code object,
+// so every GPU the library runs on holds its own copy (at its own address)
+// until the process ends.  Host code never passes this name to a kernel (on
+// the host it is only a stand-in); it takes the device address that
+// hipGetSymbolAddress returns for the current device (resolve_scratch).
+static __device__ __align__(256) uint8_t scratch[LDPC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];  // device address of `scratch` per device ordinal (null: not yet)
+
+// With `device` current: the device address of that device's `scratch`,
+// looked up once per device and kept.
+ldpc_status resolve_scratch(int device, void **out) {
+    if (device < 0 || device >= kMaxDevices) return fail(LDPC_EUNSUPPORTED, "device ordinal above 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(LDPC_EDEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return LDPC_OK;
+}
 
 // Per-call layout plan (which state lives in LDS, which in the workspace).
 struct Plan {
@@ -391,19 +423,19 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
     if (N > (1 << 30)) return fail(LDPC_EUNSUPPORTED, "N too large");
     if (row_ptr[0] != 0 || (int64_t)row_ptr[M] != nnz) return fail(LDPC_EBADCODE, "row_ptr[0] != 0 or row_ptr[M] != nnz");
     int D = 0, dmin = 1 << 30;
-    std::vector<int32_t> scratch;
+    std::vector<int32_t> row_cols;
     for (int m = 0; m < M; ++m) {
         const int d = row_ptr[m + 1] - row_ptr[m];
         if (d < 0) return fail(LDPC_EBADCODE, "row_ptr decreases at row " + std::to_string(m));
         if (d < 2) return fail(LDPC_EBADCODE, "row " + std::to_string(m) + " has degree < 2");
         D = std::max(D, d);
         dmin = std::min(dmin, d);
-        scratch.assign(col_idx + row_ptr[m], col_idx + row_ptr[m + 1]);
-        std::sort(scratch.begin(), scratch.end());
+        row_cols.assign(col_idx + row_ptr[m], col_idx + row_ptr[m + 1]);
+        std::sort(row_cols.begin(), row_cols.end());
         for (int j = 0; j < d; ++j) {
-            if (scratch[j] < 0 || scratch[j] >= N)
+            if (row_cols[j] < 0 || row_cols[j] >= N)
                 return fail(LDPC_EBADCODE, "column index out of range in row " + std::to_string(m));
-            if (j > 0 && scratch[j] == scratch[j - 1])
+            if (j > 0 && row_cols[j] == row_cols[j - 1])
                 return fail(LDPC_EBADCODE, "duplicate column in row " + std::to_string(m));
         }
     }
@@ -578,6 +610,13 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
         delete c;
         return fail(LDPC_EDEVICE, "hipSetDevice failed");
     }
+    if (device < kMaxDevices) {  // the allocation-free entry point's scratch: resolved once per device
+        void *sp = nullptr;
+        if (resolve_scratch(device, &sp) != LDPC_OK) {
+            delete c;
+            return LDPC_EDEVICE;
+        }
+    }
     ldpc::reset_alloc_count();
     int lds = 0, cus = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
@@ -744,6 +783,30 @@ ldpc_status ldpc_decode_batch(const ldpc_code *c, int32_t n_frames, const void *
                               size_t workspace_bytes, void *stream) {
     return ldpc::decode_job(c, n_frames, llr_in, p, hard_out, llr_out, iters_out, syndrome_ok, workspace,
                             workspace_bytes, stream, true);
+}
+
+ldpc_status ldpc_decode_batch_noalloc(const ldpc_code *c, int32_t n_frames, const void *llr_in,
+                                      const ldpc_decode_params *p, uint8_t *hard_out, float *llr_out,
+                                      int32_t *iters_out, uint8_t *syndrome_ok, void *stream) {
+    if (!c) return fail(LDPC_EINVAL, "code is NULL");
+    size_t need = 0;
+    ldpc_status st = ldpc_decode_workspace_size(c, n_frames, p, &need);
+    if (st != LDPC_OK) return st;
+    if (need > (size_t)LDPC_NOALLOC_SCRATCH_BYTES)
+        return fail(LDPC_EUNSUPPORTED, "the call needs " + std::to_string(need) +
+                                           " bytes of workspace; the static scratch holds " +
+                                           std::to_string((size_t)LDPC_NOALLOC_SCRATCH_BYTES) +
+                                           " (use ldpc_decode_batch with a workspace, or fewer frames)");
+    if (c->device < 0) return fail(LDPC_EINVAL, "host-only handle (device < 0) cannot decode");
+    void *ws = nullptr;
+    if (need > 0) {
+        DeviceGuard g(c->device);
+        if (!g.ok) return fail(LDPC_EDEVICE, "hipSetDevice failed");
+        st = resolve_scratch(c->device, &ws);
+        if (st != LDPC_OK) return st;
+    }
+    return ldpc::decode_job(c, n_frames, llr_in, p, hard_out, llr_out, iters_out, syndrome_ok, ws,
+                            ws ? (size_t)LDPC_NOALLOC_SCRATCH_BYTES : 0, stream, true);
 }
 
 }  // extern "C"

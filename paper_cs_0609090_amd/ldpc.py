@@ -27,10 +27,11 @@ SCHED = {"single_scan": 0, "two_scan": 1}
 F_CHECK_INPUT = 0x1
 LAYOUT = {"auto": 0, "lds": 1, "hbm": 2, "reg": 3, "reg1": 4, "frames": 5}
 LAYOUT_SHIFT = 8
+NOALLOC_SCRATCH_BYTES = 128 << 20  # LDPC_NOALLOC_SCRATCH_BYTES
 
 EXPORTS = ("ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query",
            "ldpc_decode_workspace_size", "ldpc_decode_plan", "ldpc_decode_batch", "ldpc_last_error",
-           "ldpc_version",
+           "ldpc_version", "ldpc_decode_batch_noalloc",
            # include/ldpc_sim.h
            "ldpc_encoder_info", "ldpc_encode_batch", "ldpc_random_bits", "ldpc_channel_awgn",
            "ldpc_count_errors",
@@ -118,6 +119,8 @@ def lib():
         L.ldpc_decode_plan.argtypes = [vp, i32, ctypes.POINTER(DecodeParams), ctypes.POINTER(PlanInfo)]
         L.ldpc_decode_batch.argtypes = [vp, i32, vp, ctypes.POINTER(DecodeParams), vp, vp, vp,
                                         vp, vp, sz, vp]
+        L.ldpc_decode_batch_noalloc.argtypes = [vp, i32, vp, ctypes.POINTER(DecodeParams), vp, vp, vp,
+                                                vp, vp]
         u32, dbl = ctypes.c_uint32, ctypes.c_double
         L.ldpc_encoder_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), vp]
         L.ldpc_encode_batch.argtypes = [vp, i32, vp, vp, vp]
@@ -133,7 +136,8 @@ def lib():
         L.ldpc_autotune.argtypes = [vp, i32, ctypes.POINTER(DecodeParams), ctypes.POINTER(i32),
                                     ctypes.POINTER(ctypes.c_float), ctypes.POINTER(i32)]
         for f in ("ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query",
-                  "ldpc_decode_workspace_size", "ldpc_decode_plan", "ldpc_decode_batch", "ldpc_encoder_info",
+                  "ldpc_decode_workspace_size", "ldpc_decode_plan", "ldpc_decode_batch",
+                  "ldpc_decode_batch_noalloc", "ldpc_encoder_info",
                   "ldpc_encode_batch", "ldpc_random_bits", "ldpc_channel_awgn", "ldpc_count_errors",
                   "ldpc_learn_classes", "ldpc_learn_workspace_size", "ldpc_learn_forward",
                   "ldpc_learn_backward", "ldpc_multi_workspace_size", "ldpc_decode_multi",
@@ -355,6 +359,16 @@ class Code:
         _check(lib().ldpc_decode_batch(self._h, int(n_frames), _ptr(llr), ctypes.byref(params),
                                        _ptr(hard), _ptr(llr_out), _ptr(iters), _ptr(ok),
                                        _ptr(workspace), ws_bytes, ctypes.c_void_p(s.cuda_stream)))
+
+    def decode_noalloc_into(self, llr, params: DecodeParams, hard, llr_out, iters, ok, stream=None) -> None:
+        """ldpc_decode_batch_noalloc: as ``decode_into`` with no workspace
+        argument; the library takes it from its static per-device scratch of
+        NOALLOC_SCRATCH_BYTES (calls overlapping on one GPU race)."""
+        self.check_io(llr, params, hard, llr_out, iters, ok, None)
+        s = stream if stream is not None else torch.cuda.current_stream(llr.device)
+        _check(lib().ldpc_decode_batch_noalloc(self._h, int(llr.shape[0]), _ptr(llr), ctypes.byref(params),
+                                               _ptr(hard), _ptr(llr_out), _ptr(iters), _ptr(ok),
+                                               ctypes.c_void_p(s.cuda_stream)))
 
     def check_io(self, llr, params: DecodeParams, hard, llr_out, iters, ok, workspace) -> None:
         """Shape, dtype, contiguity and device of one decode call's buffers."""

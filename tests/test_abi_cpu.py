@@ -567,3 +567,25 @@ def test_binding_rejects_host_tensors(L):
     assert gc.workspace_size(300, p) > 0
     with pytest.raises(ValueError):  # a host table cannot be decoded with
         gc.decode_into(x.float(), p, o["hard"], o["llr"], o["iters"], o["ok"], None)
+
+
+def test_noalloc_entry_point_checks(L):
+    """ldpc_decode_batch_noalloc validates like ldpc_decode_batch, refuses a
+    call whose workspace exceeds its static scratch (before any device work)
+    and, like every decode, refuses host-only handles."""
+    lib = L.lib()
+    big = L.Code.from_parity_check(W.code_c2_ira64800(), device=-1)
+    small = L.Code.from_parity_check(W.code_c0_peg1008(), device=-1)
+    fp = L.make_params(max_iter=10, msg="fp32")
+    assert big.workspace_size(256, fp) > L.NOALLOC_SCRATCH_BYTES
+    st = lib.ldpc_decode_batch_noalloc(big._h, 256, None, ctypes.byref(fp), None, None, None, None, None)
+    assert st == L.LDPC_EUNSUPPORTED and b"static scratch" in lib.ldpc_last_error()
+    hbm = L.make_params(max_iter=10, msg="int8", layout="hbm")
+    assert 0 < small.workspace_size(200, hbm) <= L.NOALLOC_SCRATCH_BYTES
+    st = lib.ldpc_decode_batch_noalloc(small._h, 200, None, ctypes.byref(hbm), None, None, None, None, None)
+    assert st == L.LDPC_EINVAL and b"host-only" in lib.ldpc_last_error()
+    bad = L.make_params(max_iter=-1, msg="int8")
+    assert lib.ldpc_decode_batch_noalloc(small._h, 4, None, ctypes.byref(bad), None, None, None, None,
+                                         None) == L.LDPC_EINVAL
+    assert lib.ldpc_decode_batch_noalloc(None, 4, None, ctypes.byref(hbm), None, None, None, None,
+                                         None) == L.LDPC_EINVAL
