@@ -62,10 +62,10 @@ KERNELS = {
 # path's kernels), keyed by the hash of the kernel sources the counters were
 # taken on; any other source reports traffic as null.
 MEASURED_TRAFFIC = [
-    {"kernel": "packed", "hash": "e3050a905296e9d7", "workload": ("int8", "single_scan", 512, 50),
-     "bytes": 236.5e6, "profile": "profiles/ss_pk_int8_ira64800_512f.md"},
-    {"kernel": "packed", "hash": "e3050a905296e9d7", "workload": ("1bit", "single_scan", 512, 50),
-     "bytes": 235.9e6, "profile": "profiles/ss_pk_1bit_ira64800_512f.md"},
+    {"kernel": "packed", "hash": "aa7c9ca62e7b9a1d", "workload": ("int8", "single_scan", 512, 50),
+     "bytes": 235.4e6, "profile": "profiles/ss_pk_int8_ira64800_512f.md"},
+    {"kernel": "packed", "hash": "aa7c9ca62e7b9a1d", "workload": ("1bit", "single_scan", 512, 50),
+     "bytes": 235.8e6, "profile": "profiles/ss_pk_1bit_ira64800_512f.md"},
     {"kernel": "f32_frames", "hash": "1c5cdaa9c2275be3", "workload": ("fp32", "single_scan", 512, 50),
      "bytes": 105147.1e6, "profile": "profiles/fl_f32_ira64800_512f.md"},
     {"kernel": "reg1", "hash": "e7d86239f37f995e", "workload": ("int8", "single_scan", 512, 50),

@@ -31,6 +31,8 @@ struct ldpc_code {
     int32_t pkS = 1;                    // lanes per row (2: a row's slots split over a lane pair)
     int32_t pkBias = 0;  // accumulator field bias of the packed kernel
     uint32_t *d_pk_idx = nullptr;
+    uint32_t *d_pk_idx16 = nullptr;  // the records for int16 Z_old (8-bit messages; accumulator
+                                     // fields of 16 bits or more), else null
     uint32_t *d_pk_slot = nullptr;  // [N] posterior slot of each variable
     // frames-across-lanes binary32 path: CSR rows and, per edge, {variable,
     // position of the edge in variable-major order}

@@ -27,7 +27,8 @@ struct DevCode {
     const int32_t *vc_ptr;   // [N+1] edges of variable n: vc_slot[vc_ptr[n] .. vc_ptr[n+1])
     const uint32_t *vc_slot; // [E] slot index (j*Mp + m) of each edge, ascending m
     const uint32_t *ell_reg; // [regD][regR*1024] index for the register-resident kernel (or null)
-    const uint32_t *pk_idx;  // [pkR/2][pkD][1024] x {slot_a, slot_b, acc_a, acc_b} for the packed kernel (or null)
+    const uint32_t *pk_idx;  // [pkR/2][pkD][T] x {zold_a, zold_b, acc_a, acc_b} LDS byte addresses for the packed
+                             // kernel (or null); the set for 16-bit Z_old with 8-bit messages
     const uint32_t *pk_slot; // [N] posterior slot of each variable (packed kernel)
 };
 
@@ -106,7 +107,9 @@ hipError_t launch_ss_f32_fl(const DecodeArgs &a, const int32_t *row_ptr, const u
                             const int32_t *row_cls, int n_classes, hipStream_t s);
 hipError_t launch_two_scan(const DecodeArgs &a, int msg, const LaunchCfg &cfg, hipStream_t s);
 hipError_t launch_ss_reg(const DecodeArgs &a, int msg, int D, int R, int P, size_t lds, hipStream_t s);
-hipError_t launch_ss_pk(const DecodeArgs &a, int D, int R, int T, int S, bool onebit, size_t lds, hipStream_t s);
+// qb: message bits (6; 7 and 8 for INT8 with one or two accumulator fields per word)
+hipError_t launch_ss_pk(const DecodeArgs &a, int D, int R, int T, int S, bool onebit, int qb, size_t lds,
+                        hipStream_t s);
 void pk_shapes(int *out, int cap, int *count);   // (D, R, T, lanes per row) quadruples
 bool reg_shape_available(int D, int R, int P);
 void reg_shapes(int *out, int cap, int *count);  // (D, R, P) triples

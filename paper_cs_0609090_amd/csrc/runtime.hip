@@ -136,8 +136,15 @@ ldpc_status plan_layout(const ldpc_code *c, const ldpc_decode_params *p, uint32_
     if (p->weights && p->msg != LDPC_MSG_FP32 && p->weight_classes == 0 && c->learn_classes > 1)
         return fail(LDPC_EUNSUPPORTED,
                     "per-class pairs are FP32 only; fixed point takes one pair per iteration (weight_classes = 1)");
-    if (qmax != kQmax6 && reg_layout)
-        return fail(LDPC_EUNSUPPORTED, "7-8 bit messages run on the LDS/HBM kernel only");
+    // 7-8 bit messages: the packed kernel when its accumulator words hold one or
+    // two fields (the 10-bit fields of three per word are sized for 6 bits),
+    // else the generic LDS/HBM kernel
+    const bool wide_pk_ok = p->msg == LDPC_MSG_INT8 && c->pkD > 0 && c->regP <= 2;
+    if (qmax != kQmax6 && layout == LDPC_LAYOUT_REG1)
+        return fail(LDPC_EUNSUPPORTED, "7-8 bit messages: no one-row register kernel (use REG, LDS or HBM)");
+    if (qmax != kQmax6 && layout == LDPC_LAYOUT_REG && !wide_pk_ok)
+        return fail(LDPC_EUNSUPPORTED, "7-8 bit messages: this code's packed accumulator has 10-bit fields "
+                                       "(three per word); use the LDS/HBM kernel");
     // AUTO for fixed point (measured on MI355X, 50 iterations): the packed
     // two-rows-per-lane kernel pays off from 16 rows per thread (M > 8192),
     // from 8 rows per thread for rows of up to 7 slots (two frames per CU) and
@@ -149,15 +156,19 @@ ldpc_status plan_layout(const ldpc_code *c, const ldpc_decode_params *p, uint32_
     const bool small_pk = c->pkD > 0 && c->pkT <= 256;  // packed shape with small workgroups
     const bool wide_pk = c->pkD * c->pkS > 8 && 5 * c->D >= 4 * c->pkD * c->pkS;  // wide rows filling >= 80% of the slots
     const bool small_auto = layout == LDPC_LAYOUT_AUTO && c->M <= 1024 && !small_pk;
-    if (p->sched == LDPC_SINGLE_SCAN && p->msg != LDPC_MSG_FP32 && !small_auto && qmax == kQmax6 &&
-        (layout == LDPC_LAYOUT_AUTO || reg_layout)) {
+    if (p->sched == LDPC_SINGLE_SCAN && p->msg != LDPC_MSG_FP32 && !small_auto &&
+        (qmax == kQmax6 || wide_pk_ok) && (layout == LDPC_LAYOUT_AUTO || reg_layout)) {
         const bool packed = c->pkD > 0 && layout != LDPC_LAYOUT_REG1 &&
                             (layout == LDPC_LAYOUT_REG || c->pkR >= 16 || wide_pk || small_pk ||
                              (c->pkR >= 8 && (p->msg == LDPC_MSG_1BIT || c->pkD <= 7)));
-        const bool ok = packed || c->regD > 0;
-        if (ok) {
+        const bool ok = packed || (c->regD > 0 && qmax == kQmax6);
+        // int16 Z_old for 8-bit messages
+        const size_t zold = align_up(nz * (qmax > 63 ? 2 : 1), 16);
+        const size_t zacc_pk = align_up(4 * ((size_t)c->dummy / c->regP + 1 + 64), 16);
+        if (ok && packed && zold + zacc_pk + aux > limit) {
+            if (reg_layout) return fail(LDPC_EUNSUPPORTED, "the packed kernel's LDS state does not fit");
+        } else if (ok) {
             pl->family = packed ? 4 : 3;
-            const size_t zold = align_up(nz, 16);
             // the packed kernel adds 64 private accumulator words for padding slots
             const size_t zacc = align_up(4 * ((size_t)c->dummy / c->regP + 1 + (packed ? 64 : 0)), 16);
             pl->zpack = c->regP;
@@ -567,7 +578,7 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
             for (int j = 0; j < row_ptr[m + 1] - row_ptr[m]; ++j)
                 ell_reg[(size_t)j * Mr + m] = (uint32_t)col_idx[row_ptr[m] + j];
     }
-    std::vector<uint32_t> pk_idx, pk_slot;
+    std::vector<uint32_t> pk_idx, pk_idx16, pk_slot;
     if (c->pkD > 0) {
         // record {zold_a, zold_b, acc_a, acc_b} of slot j of rows a = p*T/S + t/S,
         // b = (p + R/2)*T/S + t/S (T threads, S lanes per row; lane t holds the
@@ -575,29 +586,37 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
         // and (LDS byte address of the accumulator word << 5) | field shift
         const int T = c->pkT, RP = c->pkR / 2, Dk = c->pkD, Pk = c->regP, S = c->pkS;
         const int fbits = Pk == 1 ? 32 : (Pk == 2 ? 16 : 10);
-        const uint32_t zacc_off = (uint32_t)align_up((size_t)c->dummy + 1, 16);
         const uint32_t nwords = (uint32_t)c->dummy / (uint32_t)Pk + 1;
-        pk_slot = pk_slot_assignment(M, N, row_ptr, col_idx, Dk, c->pkR, T, S, Pk, zacc_off);
-        pk_idx.assign((size_t)RP * Dk * T * 4, 0u);
-        auto acc_of_slot = [&](uint32_t sl) -> uint32_t {
-            const uint32_t w = sl / (uint32_t)Pk, fld = sl % (uint32_t)Pk;
-            return ((zacc_off + w * 4u) << 5) | (fld * (uint32_t)fbits);
-        };
-        for (int pp = 0; pp < RP; ++pp)
-            for (int j = 0; j < Dk; ++j)
-                for (int t = 0; t < T; ++t)
-                    for (int h = 0; h < 2; ++h) {
-                        const int m = (pp + h * RP) * (T / S) + t / S, jr = (t % S) * Dk + j;
-                        uint32_t *r = &pk_idx[(((size_t)pp * Dk + j) * T + t) * 4];
-                        if (m < M && jr < row_ptr[m + 1] - row_ptr[m]) {
-                            const uint32_t sl = pk_slot[col_idx[row_ptr[m] + jr]];
-                            r[h] = sl;
-                            r[2 + h] = acc_of_slot(sl);
-                        } else {  // padding: shared Z_old byte, a private accumulator word per lane
-                            r[h] = (uint32_t)c->dummy;
-                            r[2 + h] = (zacc_off + (nwords + (uint32_t)(t & 63)) * 4u) << 5;
+        pk_slot = pk_slot_assignment(M, N, row_ptr, col_idx, Dk, c->pkR, T, S, Pk,
+                                     (uint32_t)align_up((size_t)c->dummy + 1, 16));
+        // zb: bytes per stored Z_old (1; 2 for the int16 Z_old of 8-bit messages,
+        // whose accumulator words then start after the wider Z_old array)
+        auto build = [&](std::vector<uint32_t> &rec, uint32_t zb) {
+            const uint32_t zacc_off = (uint32_t)align_up(((size_t)c->dummy + 1) * zb, 16);
+            auto acc_of_slot = [&](uint32_t sl) -> uint32_t {
+                const uint32_t w = sl / (uint32_t)Pk, fld = sl % (uint32_t)Pk;
+                return ((zacc_off + w * 4u) << 5) | (fld * (uint32_t)fbits);
+            };
+            rec.assign((size_t)RP * Dk * T * 4, 0u);
+            for (int pp = 0; pp < RP; ++pp)
+                for (int j = 0; j < Dk; ++j)
+                    for (int t = 0; t < T; ++t)
+                        for (int h = 0; h < 2; ++h) {
+                            const int m = (pp + h * RP) * (T / S) + t / S, jr = (t % S) * Dk + j;
+                            uint32_t *r = &rec[(((size_t)pp * Dk + j) * T + t) * 4];
+                            if (m < M && jr < row_ptr[m + 1] - row_ptr[m]) {
+                                const uint32_t sl = pk_slot[col_idx[row_ptr[m] + jr]];
+                                r[h] = sl * zb;
+                                r[2 + h] = acc_of_slot(sl);
+                            } else {  // padding: shared Z_old, a private accumulator word per lane
+                                r[h] = (uint32_t)c->dummy * zb;
+                                r[2 + h] = (zacc_off + (nwords + (uint32_t)(t & 63)) * 4u) << 5;
+                            }
                         }
-                    }
+        };
+        build(pk_idx, 1);
+        // 7-8 bit messages need accumulator fields of 16 bits or more
+        if (Pk <= 2) build(pk_idx16, 2);
     }
     if (device < 0) {  // host-only handle: planning and queries, no decoding
         c->lds_limit = kHostOnlyLds;
@@ -635,6 +654,8 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
     if (!pk_idx.empty()) {
         e5 = ldpc::dev_malloc((void **)&c->d_pk_idx, pk_idx.size() * sizeof(uint32_t));
         e6 = ldpc::dev_malloc((void **)&c->d_pk_slot, pk_slot.size() * sizeof(uint32_t));
+        if (e5 == hipSuccess && !pk_idx16.empty())
+            e5 = ldpc::dev_malloc((void **)&c->d_pk_idx16, pk_idx16.size() * sizeof(uint32_t));
     }
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || e5 != hipSuccess ||
         e6 != hipSuccess || e7 != hipSuccess || e8 != hipSuccess || e9 != hipSuccess || e10 != hipSuccess) {
@@ -655,6 +676,8 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
                                    hipMemcpyHostToDevice) != hipSuccess) ||
         (c->d_pk_idx && hipMemcpy(c->d_pk_idx, pk_idx.data(), pk_idx.size() * sizeof(uint32_t),
                                   hipMemcpyHostToDevice) != hipSuccess) ||
+        (c->d_pk_idx16 && hipMemcpy(c->d_pk_idx16, pk_idx16.data(), pk_idx16.size() * sizeof(uint32_t),
+                                    hipMemcpyHostToDevice) != hipSuccess) ||
         (c->d_pk_slot && hipMemcpy(c->d_pk_slot, pk_slot.data(), pk_slot.size() * sizeof(uint32_t),
                                    hipMemcpyHostToDevice) != hipSuccess)) {
         ldpc_code_destroy(c);
@@ -683,6 +706,7 @@ ldpc_status ldpc_code_destroy(ldpc_code *code) {
     if (code->d_enc_rows) (void)hipFree(code->d_enc_rows);
     if (code->d_ell_reg) (void)hipFree(code->d_ell_reg);
     if (code->d_pk_idx) (void)hipFree(code->d_pk_idx);
+    if (code->d_pk_idx16) (void)hipFree(code->d_pk_idx16);
     if (code->d_pk_slot) (void)hipFree(code->d_pk_slot);
     delete code;
     return LDPC_OK;
@@ -858,7 +882,7 @@ ldpc_status decode_job(const ldpc_code *c, int32_t n_frames, const void *llr_in,
     a.c.vc_ptr = c->d_vc_ptr;
     a.c.vc_slot = c->d_vc_slot;
     a.c.ell_reg = c->d_ell_reg;
-    a.c.pk_idx = c->d_pk_idx;
+    a.c.pk_idx = qmax_of(p) > 63 ? c->d_pk_idx16 : c->d_pk_idx;  // int16 Z_old for 8-bit messages
     a.c.pk_slot = c->d_pk_slot;
     a.n_frames = n_frames;
     a.max_iter = p->max_iter;
@@ -899,7 +923,8 @@ ldpc_status decode_job(const ldpc_code *c, int32_t n_frames, const void *llr_in,
     else if (pl.family == 3)
         e = ldpc::launch_ss_reg(a, p->msg, c->regD, c->regR, c->regP, pl.cfg.lds, s);
     else if (pl.family == 4)
-        e = ldpc::launch_ss_pk(a, c->pkD, c->pkR, c->pkT, c->pkS, p->msg == LDPC_MSG_1BIT, pl.cfg.lds, s);
+        e = ldpc::launch_ss_pk(a, c->pkD, c->pkR, c->pkT, c->pkS, p->msg == LDPC_MSG_1BIT,
+                               p->msg_bits ? p->msg_bits : 6, pl.cfg.lds, s);
     else if (pl.family == 1)
         e = ldpc::launch_ss_f32(a, pl.cfg, s);
     else if (pl.family == 6)

@@ -47,7 +47,27 @@ namespace ldpc {
 namespace {
 
 constexpr uint32_t kRsrcWord3 = 0x00020000u;  // raw buffer, gfx9 family
-constexpr int kZB = 63;  // bias of the stored Z_old bytes and messages
+constexpr int kZB = 63;  // bias of the stored Z_old bytes and messages (6-bit)
+
+// Message width b (Sec. V: b = 6..8 bits): extrinsics saturate to Q =
+// 2^(b-1) - 1 and the stored Z_old to 2Q (sat_Q(sat_2Q(Z) - L) = sat_Q(Z - L)
+// for |L| <= Q).  Z_old and the messages are stored with the same bias ZB, so
+// one subtraction of stored values gives Z_old - L.  6 bits: Z_old + 63 in a
+// byte (1..125), messages + 63; 7 bits: Z_old + 127 in a byte (1..253),
+// messages + 127; 8 bits: Z_old + 127 as int16 (-127..381), messages + 127
+// (0..254).  HBIT: the bit of a stored value (plus HADD) that is set exactly
+// when Z_old > 0, for the fused hard-decision parity.
+template <int QB>
+struct Width {
+    static constexpr int Q = (1 << (QB - 1)) - 1;
+    static constexpr int ZMAX = 2 * Q;
+    static constexpr int ZB = QB == 6 ? 63 : 127;
+    static constexpr bool Z16 = QB == 8;
+    static constexpr uint32_t HADD = QB == 8 ? 0x00800080u : 0u;
+    static constexpr uint32_t HMASK = QB == 6 ? 0x00400040u : QB == 7 ? 0x00800080u : 0x01000100u;
+    static constexpr uint32_t ZB2 = (uint32_t)ZB * 0x00010001u;
+    static constexpr uint32_t ZB4 = (uint32_t)ZB * 0x01010101u;
+};
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 typedef short i16x2 __attribute__((ext_vector_type(2)));
@@ -57,6 +77,29 @@ typedef short i16x2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(3))) uint8_t lds_u8_t;
 typedef __attribute__((address_space(3))) uint32_t lds_u32_t;
 __device__ __forceinline__ uint32_t lds_byte(uint32_t addr) { return *(lds_u8_t *)(size_t)addr; }
+typedef __attribute__((address_space(3))) uint16_t lds_u16_t;
+__device__ __forceinline__ uint32_t lds_half(uint32_t addr) { return *(lds_u16_t *)(size_t)addr; }
+
+
+// The stored Z_old of slot `sl` (Z + ZB) as a signed value, and its store.
+template <int QB>
+__device__ __forceinline__ int zold_get(const uint8_t *zold, uint32_t sl) {
+    if (Width<QB>::Z16) return (int)reinterpret_cast<const int16_t *>(zold)[sl];
+    return (int)zold[sl];
+}
+template <int QB>
+__device__ __forceinline__ void zold_put(uint8_t *zold, uint32_t sl, int v) {
+    if (Width<QB>::Z16)
+        reinterpret_cast<int16_t *>(zold)[sl] = (int16_t)v;
+    else
+        zold[sl] = (uint8_t)v;
+}
+// The same read by LDS byte address (the records hold byte addresses).
+template <int QB>
+__device__ __forceinline__ int zold_at(const uint8_t *lds, uint32_t addr) {
+    if (Width<QB>::Z16) return (int)*reinterpret_cast<const int16_t *>(lds + addr);
+    return (int)lds[addr];
+}
 __device__ __forceinline__ void lds_add(uint32_t addr, uint32_t v) {
     __hip_atomic_fetch_add((lds_u32_t *)(size_t)addr, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
@@ -66,10 +109,11 @@ __device__ __forceinline__ i16x2 as_i(uint32_t v) { return __builtin_bit_cast(i1
 __device__ __forceinline__ uint32_t bits(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
 __device__ __forceinline__ uint32_t bits(i16x2 v) { return __builtin_bit_cast(uint32_t, v); }
 
-// 128 - 256 beta in both 16-bit halves (beta in steps, capped at 32: past 31
-// every normalised magnitude is 0 either way)
+// 128 - 256 beta in both 16-bit halves (beta in steps, capped at Q + 1: past
+// Q every normalised magnitude is 0 either way; -32640 at Q = 127 still fits)
+template <int QB>
 __device__ __forceinline__ uint32_t rounding_offset(int b) {
-    return (uint32_t)(uint16_t)(int16_t)(128 - 256 * min(b, 32)) * 0x00010001u;
+    return (uint32_t)(uint16_t)(int16_t)(128 - 256 * min(b, Width<QB>::Q + 1)) * 0x00010001u;
 }
 
 // the same register of the partner lane (lane ^ 1): DPP quad_perm [1,0,3,2]
@@ -130,19 +174,23 @@ constexpr int pk_waves_per_eu() {
 // LANES per row: with 2 the lanes 2u and 2u + 1 hold slots 0..D-1 and
 // D..2D-1 of the same two rows, and combine their minima, sign parities and
 // syndrome shares with one DPP exchange per row pair.
-template <int D, int R, bool ONEBIT, bool FUSED, int T, int LANES>
+template <int D, int R, bool ONEBIT, bool FUSED, int T, int LANES, int QB>
 __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(pk_waves_per_eu<D, R, T>())))
 ss_pk_kernel(DecodeArgs a) {
     static_assert(LANES == 1 || LANES == 2, "one or two lanes per row");
+    static_assert(QB == 6 || !ONEBIT, "the 1-bit state holds 6-bit magnitudes");
+    using Wd = Width<QB>;
+    constexpr int kB = Wd::ZB;  // bias of stored Z_old values and messages
     constexpr int kT = T;  // threads per workgroup (one frame)
     static_assert(R % 2 == 0, "rows are processed in pairs");
     constexpr int RP = R / 2;        // row pairs per thread
     constexpr int W = (D + 1) / 2;   // registers per row pair: two slots (4 bytes) each
     constexpr int NS = (D + 7) / 8;  // 1-bit state registers per row pair: eight slots each
     // B-or-A choice per slot: a mask and a bit-select (the 1-bit state keeps
-    // the mask; measured faster for rows wider than 8 slots), else one
-    // multiply-add and a max (fewer instructions, faster for short rows)
-    constexpr bool kMaskSelect = ONEBIT || D > 8;
+    // the mask; measured faster for rows wider than 8 slots; 8-bit messages,
+    // where B can reach 127), else one multiply-add and a max (fewer
+    // instructions, faster for short rows)
+    constexpr bool kMaskSelect = ONEBIT || D > 8 || QB == 8;
     extern __shared__ __align__(16) uint8_t lds[];
     const int tid = threadIdx.x;
     const int f = blockIdx.x;
@@ -161,18 +209,34 @@ ss_pk_kernel(DecodeArgs a) {
     const int nwords = (int)(dummy / (uint32_t)P) + 1;
 
     const uint32_t *__restrict__ slot_of = a.c.pk_slot;
-    for (int n = tid; n <= (int)dummy; n += kT) {
-        if (n < N)
-            zold[slot_of[n]] = (uint8_t)(kZB + min(max((int)z0[n], -kQmax), kQmax));
-        else  // unused slots read as zero; the dummy slot as the largest magnitude
-            zold[n] = (uint8_t)(kZB + (n == (int)dummy ? kZoldMax : 0));
+    // Z_old from the channel LLRs: the loads of kU variables per thread are
+    // issued before any of their stores, so the latency of the first touch of
+    // z0 (and of the slot table) is paid once per kU variables, not per variable
+    constexpr int kU = 8;
+    for (int n0 = tid; n0 <= (int)dummy; n0 += kU * kT) {
+        int zin[kU];
+        uint32_t sl[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {  // unconditional (in-range) loads: no branch between them
+            const int nc = min(n0 + u * kT, N - 1);
+            zin[u] = (int)z0[nc];
+            sl[u] = slot_of[nc];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int n = n0 + u * kT;
+            if (n < N)
+                zold_put<QB>(zold, sl[u], kB + min(max(zin[u], -Wd::Q), Wd::Q));
+            else if (n <= (int)dummy)  // unused slots read as zero; the dummy slot as the largest magnitude
+                zold_put<QB>(zold, n, kB + (n == (int)dummy ? Wd::ZMAX : 0));
+        }
     }
     __syncthreads();
     for (int w = tid; w < nwords; w += kT) {
         uint32_t v = 0;
         for (int i = 0; i < P; ++i) {
             const int sl = w * P + i;
-            const int z = sl < N ? (int)zold[sl] - kZB : 0;
+            const int z = sl < N ? zold_get<QB>(zold, sl) - kB : 0;
             v |= (uint32_t)(z + biasP) << (i * bitsP);
         }
         zacc[w] = v;
@@ -203,13 +267,13 @@ ss_pk_kernel(DecodeArgs a) {
         for (int k = 0; k < NS; ++k) St[p][k] = 0u;
         Ab[p] = 0x3F3F3F3Fu;  // A = B = 0
 #pragma unroll
-        for (int i = 0; i < (ONEBIT ? 1 : W); ++i) Lw[p][i] = 0x3F3F3F3Fu;
+        for (int i = 0; i < (ONEBIT ? 1 : W); ++i) Lw[p][i] = Wd::ZB4;  // L = 0
     }
     __syncthreads();
 
     const uint32_t tid16 = (uint32_t)tid * 16u;
     uint32_t a8x2 = (uint32_t)a.a8 * 0x00010001u;  // normalisation pair, both 16-bit halves
-    uint32_t c8x2 = rounding_offset(a.b_int);
+    uint32_t c8x2 = rounding_offset<QB>(a.b_int);
     // +-64 in both halves, opaque so that the products by it stay multiply-adds
     // (a constant power of two would become a shift and a separate add)
     uint32_t k64 = 0x00400040u, kn64 = 0xFFC0FFC0u;
@@ -233,7 +297,7 @@ ss_pk_kernel(DecodeArgs a) {
             int a8i, bi;
             sched_pair(a, it, a8i, bi);
             a8x2 = (uint32_t)a8i * 0x00010001u;
-            c8x2 = rounding_offset(bi);
+            c8x2 = rounding_offset<QB>(bi);
         }
 #pragma unroll
         for (int p = 0; p < RP; ++p) {
@@ -247,6 +311,7 @@ ss_pk_kernel(DecodeArgs a) {
 #pragma unroll
             for (int j = 0; j < D; ++j)
                 rc[j] = __builtin_amdgcn_raw_buffer_load_b128(rec, tid16, it0 + (uint32_t)((p * D + j) * kT * 16), 0);
+
             uint32_t acc_a[D], acc_b[D], t2[D], lo2[D], mg2[D], h2[D];
             u16x2 min1 = {0xFFFF, 0xFFFF}, min2 = {0xFFFF, 0xFFFF};
             uint32_t Sp[NS], LUTa = 0, LUTb = 0;
@@ -265,10 +330,14 @@ ss_pk_kernel(DecodeArgs a) {
                 const uint32_t na = r4[0], nb = r4[1];
                 acc_a[j] = r4[2];
                 acc_b[j] = r4[3];
-                const u16x2 zv = {(unsigned short)lds_byte(na), (unsigned short)lds_byte(nb)};
+                // two loads and one permute: the _d16_hi loads that would fill the
+                // high half directly zero the low half on parts with SRAM ECC
+                const u16x2 zv = Wd::Z16 ? (u16x2){(unsigned short)lds_half(na), (unsigned short)lds_half(nb)}
+                                         : (u16x2){(unsigned short)lds_byte(na), (unsigned short)lds_byte(nb)};
                 const uint32_t z2 = bits(zv);
-                // FUSED: bit 6 / 22 clear iff Z_old <= 0 (stored Z + 63 <= 63)
-                if (FUSED) h2[j] = z2;
+                // FUSED: bit HMASK of the stored value (plus HADD) clear iff
+                // Z_old <= 0 (6 bits: Z + 63 <= 63, bit 6)
+                if (FUSED) h2[j] = Wd::HADD ? bits(as_u(z2) + as_u(Wd::HADD)) : z2;
                 uint32_t l2;
                 if (ONEBIT) {
                     // L_old = s * (slot held the minimum ? B : A) + 63 (Eqs. 4-5
@@ -320,8 +389,8 @@ ss_pk_kernel(DecodeArgs a) {
             // the rounding constant (128 - 256 beta, beta capped at 32 where A
             // and B are 0 anyway) and an arithmetic shift: the sum stays within
             // +-8064, so the 16-bit halves hold it exactly
-            const u16x2 m1 = __builtin_elementwise_min(min1, (u16x2){31, 31});
-            const u16x2 m2 = __builtin_elementwise_min(min2, (u16x2){31, 31});
+            const u16x2 m1 = __builtin_elementwise_min(min1, (u16x2){Wd::Q, Wd::Q});
+            const u16x2 m2 = __builtin_elementwise_min(min2, (u16x2){Wd::Q, Wd::Q});
             const i16x2 Am = __builtin_elementwise_max(as_i(bits(m1 * as_u(a8x2) + as_u(c8x2))) >> (i16x2){8, 8},
                                                        (i16x2){0, 0});
             const i16x2 Bm = __builtin_elementwise_max(as_i(bits(m2 * as_u(a8x2) + as_u(c8x2))) >> (i16x2){8, 8},
@@ -357,7 +426,7 @@ ss_pk_kernel(DecodeArgs a) {
                     const uint32_t mag = __builtin_amdgcn_bitop3_b32(nsel, A2, B2, 0xCA);  // nsel ? A : B
                     // own sign +-1, then L_new + 63 in one multiply-add
                     const i16x2 sg = (as_i(t2[j]) >> (i16x2){15, 15}) | (i16x2){1, 1};
-                    lb = as_i(mag) * sg + (i16x2){kZB, kZB};
+                    lb = as_i(mag) * sg + (i16x2){kB, kB};
                     if (ONEBIT) {  // keep the own-extrinsic sign and the minimum flag
                         const uint32_t sneg = bits(as_i(t2[j]) >> (i16x2){15, 15});
                         uint32_t &S = Sn[j >> 3];
@@ -370,7 +439,7 @@ ss_pk_kernel(DecodeArgs a) {
                     // sign +-1 per half: own extrinsic's sign XOR the row parity
                     const uint32_t sg = __builtin_amdgcn_bitop3_b32(
                         bits(as_i(t2[j]) >> (i16x2){15, 15}), mn1, 0x00010001u, 0xBE);  // (a ^ b) | c
-                    lb = mag * as_i(sg) + (i16x2){kZB, kZB};
+                    lb = mag * as_i(sg) + (i16x2){kB, kB};
                 }
                 nl[j] = bits(lb);
                 const uint32_t d = bits(lb - as_i(lo2[j]));
@@ -393,20 +462,20 @@ ss_pk_kernel(DecodeArgs a) {
 #pragma unroll
                 for (int i = 0; i < W; ++i) {
                     const uint32_t lo = nl[2 * i];
-                    const uint32_t hi = (2 * i + 1 < D) ? nl[2 * i + 1] : 0x003F003Fu;
+                    const uint32_t hi = (2 * i + 1 < D) ? nl[2 * i + 1] : Wd::ZB2;
                     Lw[p][i] = __builtin_amdgcn_perm(hi, lo, 0x06040200u);
                     asm volatile("" : "+v"(Lw[p][i]));
                 }
             }
         }
-        if (FUSED && it >= 2 && (zodd & 0x00400040u)) flag[1 + (it & 1)] = 1;
+        if (FUSED && it >= 2 && (zodd & Wd::HMASK)) flag[1 + (it & 1)] = 1;
         __syncthreads();
         if (FUSED && it >= 2 && flag[1 + (it & 1)] == 0) {  // Z^(it-1) is a codeword
             conv_prev = true;
             break;
         }
         if (tid == 0) *flag = 0;
-        if (P == 3) {
+        if (QB == 6 && P == 3) {
             if (biasP == 319)
                 refresh3<319, kT>(zacc, zold, N, nwords, tid);
             else
@@ -418,7 +487,7 @@ ss_pk_kernel(DecodeArgs a) {
                     const int n = w * P + i;
                     if (n < N) {
                         const int z = (P == 1) ? (int)v : (int)((v >> (i * bitsP)) & maskP) - biasP;
-                        zold[n] = (uint8_t)(kZB + min(max(z, -kZoldMax), kZoldMax));
+                        zold_put<QB>(zold, n, kB + min(max(z, -Wd::ZMAX), Wd::ZMAX));
                     }
                 }
             }
@@ -431,8 +500,8 @@ ss_pk_kernel(DecodeArgs a) {
                 for (int j = 0; j < D; ++j) {
                     const auto r4 = __builtin_amdgcn_raw_buffer_load_b128(
                         rec, tid16, (uint32_t)((p * D + j) * kT * 16), 0);
-                    pa ^= zold[r4[0]] <= kZB ? 1 : 0;
-                    pb ^= zold[r4[1]] <= kZB ? 1 : 0;
+                    pa ^= zold_at<QB>(lds, r4[0]) <= kB ? 1 : 0;
+                    pb ^= zold_at<QB>(lds, r4[1]) <= kB ? 1 : 0;
                 }
                 if (LANES == 2) {
                     pa ^= (int)partner((uint32_t)pa);
@@ -457,8 +526,8 @@ ss_pk_kernel(DecodeArgs a) {
             for (int j = 0; j < D; ++j) {
                 const auto r4 = __builtin_amdgcn_raw_buffer_load_b128(
                     rec, tid16, (uint32_t)((p * D + j) * kT * 16), 0);
-                pa ^= zold[r4[0]] <= kZB ? 1 : 0;
-                pb ^= zold[r4[1]] <= kZB ? 1 : 0;
+                pa ^= zold_at<QB>(lds, r4[0]) <= kB ? 1 : 0;
+                pb ^= zold_at<QB>(lds, r4[1]) <= kB ? 1 : 0;
             }
             if (LANES == 2) {
                 pa ^= (int)partner((uint32_t)pa);
@@ -469,16 +538,26 @@ ss_pk_kernel(DecodeArgs a) {
         __syncthreads();
         ok = (*flag == 0);
     }
-    if (FUSED && conv_prev) {  // decisions of Z^(iters) from its saturated copy
-        for (int n = tid; n < N; n += kT) a.hard_out[(size_t)f * N + n] = zold[slot_of[n]] <= kZB ? 1 : 0;
-    } else for (int n = tid; n < N; n += kT) {
-        const uint32_t sl = slot_of[n];
-        const uint32_t w = (P == 1) ? sl : (P == 2 ? sl >> 1 : sl / 3u);
-        const int i = (int)(sl - w * (uint32_t)P);
-        const uint32_t v = zacc[w];
-        const int z = (P == 1) ? (int)v : (int)((v >> (i * bitsP)) & maskP) - biasP;
-        a.hard_out[(size_t)f * N + n] = z <= 0 ? 1 : 0;
-        if (a.llr_out) a.llr_out[(size_t)f * N + n] = (float)((double)z * a.step);
+    // outputs, kU variables per thread and step (slot-table loads first)
+    for (int n0 = tid; n0 < N; n0 += kU * kT) {
+        uint32_t sl[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) sl[u] = slot_of[min(n0 + u * kT, N - 1)];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int n = n0 + u * kT;
+            if (n >= N) continue;
+            if (FUSED && conv_prev) {  // decisions of Z^(iters) from its saturated copy
+                a.hard_out[(size_t)f * N + n] = zold_get<QB>(zold, sl[u]) <= kB ? 1 : 0;
+            } else {
+                const uint32_t w = (P == 1) ? sl[u] : (P == 2 ? sl[u] >> 1 : sl[u] / 3u);
+                const int i = (int)(sl[u] - w * (uint32_t)P);
+                const uint32_t v = zacc[w];
+                const int z = (P == 1) ? (int)v : (int)((v >> (i * bitsP)) & maskP) - biasP;
+                a.hard_out[(size_t)f * N + n] = z <= 0 ? 1 : 0;
+                if (a.llr_out) a.llr_out[(size_t)f * N + n] = (float)((double)z * a.step);
+            }
+        }
     }
     if (tid == 0) {
         a.iters_out[f] = iters;
@@ -486,9 +565,9 @@ ss_pk_kernel(DecodeArgs a) {
     }
 }
 
-template <int D, int R, bool ONEBIT, bool FUSED, int T, int S>
+template <int D, int R, bool ONEBIT, bool FUSED, int T, int S, int QB>
 hipError_t launch_one(const DecodeArgs &a, size_t lds, hipStream_t s) {
-    auto kern = ss_pk_kernel<D, R, ONEBIT, FUSED, T, S>;
+    auto kern = ss_pk_kernel<D, R, ONEBIT, FUSED, T, S, QB>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -539,18 +618,28 @@ void pk_shapes(int *out, int cap, int *count) {
 
 namespace {
 template <int D, int R, int T, int S>
-hipError_t launch_shape(const DecodeArgs &a, bool onebit, size_t lds, hipStream_t s) {
+hipError_t launch_shape(const DecodeArgs &a, bool onebit, int qb, size_t lds, hipStream_t s) {
     // the fused check needs at least one iteration and no posterior output
     const bool fused = a.early_stop && a.llr_out == nullptr && a.max_iter >= 1;
-    if (onebit)
-        return fused ? launch_one<D, R, true, true, T, S>(a, lds, s) : launch_one<D, R, true, false, T, S>(a, lds, s);
-    return fused ? launch_one<D, R, false, true, T, S>(a, lds, s) : launch_one<D, R, false, false, T, S>(a, lds, s);
+    if (onebit) {
+        if (qb != 6) return hipErrorInvalidValue;
+        return fused ? launch_one<D, R, true, true, T, S, 6>(a, lds, s)
+                     : launch_one<D, R, true, false, T, S, 6>(a, lds, s);
+    }
+    if (qb == 7)
+        return fused ? launch_one<D, R, false, true, T, S, 7>(a, lds, s)
+                     : launch_one<D, R, false, false, T, S, 7>(a, lds, s);
+    if (qb == 8)
+        return fused ? launch_one<D, R, false, true, T, S, 8>(a, lds, s)
+                     : launch_one<D, R, false, false, T, S, 8>(a, lds, s);
+    return fused ? launch_one<D, R, false, true, T, S, 6>(a, lds, s) : launch_one<D, R, false, false, T, S, 6>(a, lds, s);
 }
 }  // namespace
 
-hipError_t launch_ss_pk(const DecodeArgs &a, int D, int R, int T, int S, bool onebit, size_t lds, hipStream_t s) {
+hipError_t launch_ss_pk(const DecodeArgs &a, int D, int R, int T, int S, bool onebit, int qb, size_t lds,
+                        hipStream_t s) {
 #define X(d, r, t, l) \
-    if (D == d && R == r && T == t && S == l) return launch_shape<d, r, t, l>(a, onebit, lds, s);
+    if (D == d && R == r && T == t && S == l) return launch_shape<d, r, t, l>(a, onebit, qb, lds, s);
     LDPC_PK_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;

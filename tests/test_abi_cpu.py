@@ -355,17 +355,28 @@ def test_schedule_and_width_validation(L):
     for bits in (5, 9, -1):
         assert status(small, msg="int8", msg_bits=bits) == L.LDPC_EINVAL
     for kw in (dict(msg="1bit", msg_bits=7), dict(msg="int8", sched="two_scan", msg_bits=7),
-               dict(msg="fp32", msg_bits=8), dict(msg="int8", msg_bits=7, layout="reg"),
-               dict(msg="int8", msg_bits=8, layout="reg1"), dict(msg="int8", msg_bits=7, layout="frames")):
+               dict(msg="fp32", msg_bits=8), dict(msg="int8", msg_bits=8, layout="reg1"),
+               dict(msg="int8", msg_bits=7, layout="frames")):
         assert status(big, **kw) == L.LDPC_EUNSUPPORTED, kw
+    # the packed register kernel takes 7-8 bits where the accumulator has one
+    # field per word (the 16200-bit code), not with three 10-bit fields (64800)
+    for bits in (7, 8):
+        assert status(big, msg="int8", msg_bits=bits, layout="reg") == L.LDPC_OK
+        assert status(huge, msg="int8", msg_bits=bits, layout="reg") == L.LDPC_EUNSUPPORTED
+        assert big.plan(64, L.make_params(msg="int8", msg_bits=bits))["kernel"] == "packed"
+        assert small.plan(64, L.make_params(msg="int8", msg_bits=bits))["kernel"] == "packed"
+    # 8-bit messages keep Z_old as int16: two bytes per variable on chip
+    lds6 = big.plan(64, L.make_params(msg="int8"))["lds_bytes"]
+    lds7 = big.plan(64, L.make_params(msg="int8", msg_bits=7))["lds_bytes"]
+    lds8 = big.plan(64, L.make_params(msg="int8", msg_bits=8))["lds_bytes"]
+    assert lds6 == lds7 and lds8 - lds6 >= W.code_ira16200().N
     # wider messages widen the posterior accumulator (|Z| <= Q (d_v + 1)): for
     # the 64800-bit code (d_v = 8) 7 bits need 16-bit fields, which with Z_old
     # no longer fit in LDS
     assert status(huge, msg="int8", msg_bits=6, layout="hbm") == L.LDPC_OK
     for bits in (7, 8):
         assert status(huge, msg="int8", msg_bits=bits) == L.LDPC_EUNSUPPORTED
-    # AUTO with 7-8 bit messages leaves the register kernels for the LDS
-    # kernel (the 16200-bit code's messages still fit on chip at 7 bits)
+    # the 16200-bit code's messages still fit on chip at 7 bits in the LDS kernel
     assert big.workspace_size(4, L.make_params(msg="int8", msg_bits=7)) == \
         big.workspace_size(4, L.make_params(msg="int8", msg_bits=7, layout="lds")) == 0
     # schedules: one pair per iteration on every single-scan path; per-class

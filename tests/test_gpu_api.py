@@ -115,7 +115,8 @@ def test_explicit_stream(torch_dev, L, orc):
 
 # ---------------------------------------------------------------------------
 # Autotuning keyed by message width: a layout tuned for 6-bit messages does not
-# leak into 7- or 8-bit calls (which only the LDS/HBM kernel runs), and a 7-bit
+# leak into 7- or 8-bit calls (which the one-row register kernel cannot run:
+# they keep the built-in choice, the packed kernel on this code), and a 7-bit
 # tune does not move 6-bit calls off their own choice.
 def test_autotune_then_other_width(torch_dev, L, orc):
     torch = torch_dev
@@ -131,7 +132,7 @@ def test_autotune_then_other_width(torch_dev, L, orc):
     for bits, step in ((7, 0.25), (8, 0.125)):
         q = W.quantize_llr(llr, step=step, qmax=(1 << (bits - 1)) - 1)
         pb = L.make_params(msg="int8", max_iter=12, msg_bits=bits, llr_step=step)
-        assert gc.plan(F, pb)["layout"] in ("lds", "hbm")
+        assert gc.plan(F, pb)["kernel"] == "packed"
         g = _np(gc.decode(torch.from_numpy(q).cuda(), msg="int8", max_iter=12, msg_bits=bits, llr_step=step,
                           early_stop=True))
         r = orc.decode(code, q, algo="single_scan", arith="int", max_iter=12, qbits=bits, step=step,
@@ -142,7 +143,7 @@ def test_autotune_then_other_width(torch_dev, L, orc):
     # a 7-bit tune: 6-bit AUTO keeps the 6-bit tuned layout
     p7 = L.make_params(msg="int8", max_iter=12, msg_bits=7, llr_step=0.25)
     t7 = gc.autotune(F, p7)
-    assert t7["layout"] in ("lds", "hbm")
+    assert t7["layout"] in ("reg", "lds", "hbm")
     assert gc.plan(F, p6)["layout"] == t6["layout"]
     assert before6["kernel"] in ("packed", "reg1")
     q6 = W.quantize_llr(llr)

@@ -76,9 +76,12 @@ def test_schedule(torch_dev, L, orc, name, msg, layout, early_stop, with_llr):
         assert not np.array_equal(g["llr"], c["llr"])
 
 
+# AUTO runs the packed register kernel on these three codes (one accumulator
+# field per word); "hbm" forces the generic kernel
 WIDTH_CASES = [("peg1008", 7, "auto", 0.25), ("peg1008", 8, "auto", 0.125), ("peg1008", 7, "hbm", 0.5),
-               ("peg1008", 8, "hbm", 0.25), ("ira16200", 7, "auto", 0.25), ("ira16200", 8, "hbm", 0.125),
-               ("qc7493", 8, "auto", 0.125)]
+               ("peg1008", 8, "hbm", 0.25), ("ira16200", 7, "auto", 0.25), ("ira16200", 8, "auto", 0.125),
+               ("ira16200", 8, "hbm", 0.125), ("qc7493", 7, "auto", 0.25), ("qc7493", 8, "auto", 0.125),
+               ("peg1008", 7, "reg", 0.5), ("ira16200", 7, "reg", 0.5), ("qc7493", 8, "reg", 0.25)]
 
 
 @pytest.mark.parametrize("early_stop,with_llr", [(False, True), (True, True), (True, False)])
@@ -91,6 +94,39 @@ def test_message_width(torch_dev, L, orc, name, bits, layout, step, early_stop, 
     if step < 0.5:  # finer steps: the inputs themselves use the wider range
         assert np.abs(x).max() > 31
     _run(torch_dev, L, orc, code, x, "int8", layout, early_stop, with_llr, step, bits=bits, max_iter=20)
+
+
+@pytest.mark.parametrize("name", ["peg1008", "ira16200", "qc7493"])
+@pytest.mark.parametrize("bits", [7, 8])
+def test_width_plan_is_packed(torch_dev, L, name, bits):
+    gcode = L.Code.from_parity_check(CODES[name]())
+    for msg_bits in (6, bits):
+        p = L.make_params(msg="int8", msg_bits=msg_bits)
+        assert gcode.plan(64, p)["kernel"] == "packed"
+    gcode.close()
+
+
+@pytest.mark.parametrize("bits,step,beta", [(7, 0.25, 9.0), (8, 0.125, 5.0), (8, 0.125, 15.9),
+                                            (8, 0.125, 40.0)])
+def test_width_large_offsets_packed(torch_dev, L, orc, bits, step, beta):
+    """Offsets past 32 steps (the 6-bit cap, below the wider Q) and past Q
+    itself (every message zero) on the packed kernel, against the oracle."""
+    torch = torch_dev
+    code = CODES["ira16200"]()
+    Q = (1 << (bits - 1)) - 1
+    x = _inputs(code, 24, step, Q, seed=4)
+    gcode = L.Code.from_parity_check(code)
+    assert gcode.plan(24, L.make_params(msg="int8", msg_bits=bits))["kernel"] == "packed"
+    out = gcode.decode(torch.from_numpy(x).cuda(), max_iter=8, alpha=0.9, beta=beta, early_stop=False,
+                       msg="int8", llr_step=step, msg_bits=bits)
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    gcode.close()
+    r = orc.decode(code, x, algo="single_scan", arith="int", max_iter=8, alpha=0.9, beta=beta, early_stop=False,
+                   step=step, qbits=bits)
+    for k, rk in (("iters", "iters"), ("ok", "ok"), ("hard", "hard"), ("llr", "post")):
+        np.testing.assert_array_equal(g[k], r[rk], err_msg=k)
+    if beta / step > Q:  # every message zero: the posteriors stay the channel values
+        np.testing.assert_array_equal(g["llr"], (x.astype(np.float64) * step).astype(np.float32))
 
 
 @pytest.mark.parametrize("bits", [7, 8])
