@@ -62,6 +62,19 @@ ldpc_status ldpc_learn_backward(const ldpc_code *code, int32_t n_frames, const u
                                 const float *weights, int32_t ckpt, void *workspace, size_t workspace_bytes,
                                 float *grad, void *stream);
 
+/*
+ * The same adjoint for the objective sum_t w_t loss_t: loss_weights is a
+ * host array of T finite weights (read during the call), or NULL for all
+ * ones (ldpc_learn_backward).  Weighting the early iterations more trains the
+ * pairs towards decoding in fewer iterations (the paper indexes lambda and
+ * beta by the iteration, Sec. III; the objective is this library's).
+ * LDPC_EINVAL for a non-finite weight.
+ */
+ldpc_status ldpc_learn_backward_weighted(const ldpc_code *code, int32_t n_frames, const uint8_t *target,
+                                         int32_t T, const float *weights, int32_t ckpt, void *workspace,
+                                         size_t workspace_bytes, const float *loss_weights, float *grad,
+                                         void *stream);
+
 #ifdef __cplusplus
 }
 #endif

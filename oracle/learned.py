@@ -13,7 +13,9 @@ x < 0; the minimum's position is the lowest index among equal values.
 
 Loss: BCE of the posteriors against the transmitted bits x, summed over
 iterations, frames and bits:  sum_t sum_f sum_n softplus(s * Z^(t)_n) with
-s = 2x - 1 (bit 0 wants Z > 0).
+s = 2x - 1 (bit 0 wants Z > 0).  The adjoint also takes a weight w_t per
+iteration (the objective sum_t w_t loss_t; all ones by default), for
+objectives that favour decoding in fewer iterations.
 
 Adjoint: reverse mode through the unrolled graph.  L^(t)_mn depends on the
 extrinsics only through the minimising position k(n) (away from ties and
@@ -127,11 +129,13 @@ def forward(code, llr, weights, target=None, dtype=np.float64):
     return {"loss": np.array(losses), "Z": np.stack(Zs), "L": np.stack(Ls)}
 
 
-def adjoint(code, llr, weights, target=None):
-    """Gradient of the summed loss with respect to the weights, [T, C, 2]."""
+def adjoint(code, llr, weights, target=None, loss_weights=None):
+    """Gradient of sum_t w_t loss_t with respect to the weights, [T, C, 2]
+    (w_t = loss_weights[t - 1], all ones if None)."""
     fw = forward(code, llr, weights, target)
     W = np.asarray(weights, dtype=np.float64)
     T, C = W.shape[0], W.shape[1]
+    lw = np.ones(T) if loss_weights is None else np.asarray(loss_weights, dtype=np.float64)
     Zs, Ls = fw["Z"], fw["L"]
     F, N = Zs.shape[1], Zs.shape[2]
     ci = np.asarray(code.col_idx)
@@ -144,7 +148,7 @@ def adjoint(code, llr, weights, target=None):
     tbar_next = np.zeros((F, E))   # adjoint of t^(t+1) per edge
     for t in range(T, 0, -1):
         # Z^(t): its own loss term, and every t^(t+1)_mn = Z^(t)_n - L^(t)_mn
-        Zbar = s * _sigmoid(s * Zs[t])
+        Zbar = lw[t - 1] * s * _sigmoid(s * Zs[t])
         np.add.at(Zbar.T, ci, tbar_next.T)
         # L^(t)_mn feeds Z^(t)_n (+) and t^(t+1)_mn (-)
         Lbar = Zbar[:, ci] - tbar_next

@@ -25,6 +25,7 @@
 #include "code_handle.h"
 #include "fl_common.h"
 
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -143,10 +144,12 @@ __global__ void __launch_bounds__(kBlock) lrn_var(LrnArgs a, const float *__rest
     if (lane == 0) atomicAdd(loss, acc);
 }
 
-// Adjoint of the variable pass of iteration t: Zbar from the loss and from
-// tbar (the extrinsic adjoints of iteration t+1, null at t = T); writes Lbar.
+// Adjoint of the variable pass of iteration t: Zbar from the loss (weighted
+// by lw, the objective's weight of iteration t) and from tbar (the extrinsic
+// adjoints of iteration t+1, null at t = T); writes Lbar.
 __global__ void __launch_bounds__(kBlock) lrn_var_bwd(LrnArgs a, const float *__restrict__ zt,
-                                                      const float *__restrict__ tbar, float *__restrict__ Lbar) {
+                                                      const float *__restrict__ tbar, float *__restrict__ Lbar,
+                                                      float lw) {
     const int lane = threadIdx.x & 63;
     const int w = wave_id();
     if (w >= a.rwaves * a.G) return;
@@ -161,7 +164,7 @@ __global__ void __launch_bounds__(kBlock) lrn_var_bwd(LrnArgs a, const float *__
         const int e0 = vp[n], e1 = vp[n + 1];
         const float z = zb.ldf(fo, o);
         const float sg = (a.tgt && a.tgt[(size_t)n * a.Fp + f]) ? 1.0f : -1.0f;
-        float zbar = real ? sg * sigmoid_f(sg * z) : 0.0f;
+        float zbar = real ? lw * (sg * sigmoid_f(sg * z)) : 0.0f;
         if (tbar) {
             for (int e = e0; e < e1; ++e) zbar += tb.ldf(fo, (uint32_t)e * rowb);
         }
@@ -374,8 +377,9 @@ void forward_steps(const Ctx &x, int t_from, int t_to, float *loss, hipStream_t 
     }
 }
 
+// lw: host [T] weights of the iterations' losses in the objective, or null (all 1)
 template <int DMAX>
-void backward_all(const Ctx &x, float *grad, hipStream_t s) {
+void backward_all(const Ctx &x, float *grad, const float *lw, hipStream_t s) {
     const int T = x.a.T, k = x.ckpt;
     float *lbar = reinterpret_cast<float *>(x.ws + x.lay.lbar);
     float *tbar = reinterpret_cast<float *>(x.ws + x.lay.tbar);
@@ -389,7 +393,7 @@ void backward_all(const Ctx &x, float *grad, hipStream_t s) {
         }
         for (int t = t1; t > t0; --t) {
             hipLaunchKernelGGL(lrn_var_bwd, dim3(x.grid), dim3(kBlock), 0, s, x.a, x.Z(t),
-                               have_tbar ? tbar : nullptr, lbar);
+                               have_tbar ? tbar : nullptr, lbar, lw ? lw[t - 1] : 1.0f);
             hipLaunchKernelGGL((lrn_check_bwd<DMAX>), dim3(x.grid), dim3(kBlock), 0, s, x.a, x.Z(t - 1),
                                x.Lm(t - 1), lbar, tbar, grad, t, t > 1 ? 1 : 0);
             have_tbar = true;
@@ -457,6 +461,19 @@ ldpc_status ldpc_learn_forward(const ldpc_code *code, int32_t n_frames, const fl
 ldpc_status ldpc_learn_backward(const ldpc_code *code, int32_t n_frames, const uint8_t *target, int32_t T,
                                 const float *weights, int32_t ckpt, void *workspace, size_t workspace_bytes,
                                 float *grad, void *stream) {
+    return ldpc_learn_backward_weighted(code, n_frames, target, T, weights, ckpt, workspace, workspace_bytes,
+                                        nullptr, grad, stream);
+}
+
+ldpc_status ldpc_learn_backward_weighted(const ldpc_code *code, int32_t n_frames, const uint8_t *target,
+                                         int32_t T, const float *weights, int32_t ckpt, void *workspace,
+                                         size_t workspace_bytes, const float *loss_weights, float *grad,
+                                         void *stream) {
+    if (loss_weights && T > 0) {
+        for (int t = 0; t < T; ++t)
+            if (!std::isfinite(loss_weights[t]))
+                return set_error(LDPC_EINVAL, "loss_weights must be finite");
+    }
     ldpc::Ctx x;
     ldpc_status st = ldpc::make_ctx(code, n_frames, T, ckpt, weights, workspace, workspace_bytes, &x);
     if (st != LDPC_OK) return st;
@@ -466,11 +483,11 @@ ldpc_status ldpc_learn_backward(const ldpc_code *code, int32_t n_frames, const u
     const int64_t ng = (int64_t)T * x.a.C * 2;
     hipLaunchKernelGGL(ldpc::fill_zero, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, s, grad, ng);
     if (code->D <= 8)
-        ldpc::backward_all<8>(x, grad, s);
+        ldpc::backward_all<8>(x, grad, loss_weights, s);
     else if (code->D <= 16)
-        ldpc::backward_all<16>(x, grad, s);
+        ldpc::backward_all<16>(x, grad, loss_weights, s);
     else
-        ldpc::backward_all<32>(x, grad, s);
+        ldpc::backward_all<32>(x, grad, loss_weights, s);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(LDPC_EDEVICE, std::string("launch failed: ") + hipGetErrorString(e));
     return LDPC_OK;

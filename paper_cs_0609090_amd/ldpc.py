@@ -37,7 +37,7 @@ EXPORTS = ("ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query",
            "ldpc_count_errors",
            # include/ldpc_learn.h
            "ldpc_learn_classes", "ldpc_learn_workspace_size", "ldpc_learn_forward",
-           "ldpc_learn_backward",
+           "ldpc_learn_backward", "ldpc_learn_backward_weighted",
            # include/ldpc_multi.h
            "ldpc_multi_workspace_size", "ldpc_decode_multi", "ldpc_autotune")
 LAYOUT_NAME = {v: k for k, v in LAYOUT.items()}
@@ -131,6 +131,7 @@ def lib():
         L.ldpc_learn_workspace_size.argtypes = [vp, i32, i32, i32, ctypes.POINTER(sz)]
         L.ldpc_learn_forward.argtypes = [vp, i32, vp, vp, i32, vp, i32, vp, sz, vp, vp, vp]
         L.ldpc_learn_backward.argtypes = [vp, i32, vp, i32, vp, i32, vp, sz, vp, vp]
+        L.ldpc_learn_backward_weighted.argtypes = [vp, i32, vp, i32, vp, i32, vp, sz, vp, vp, vp]
         L.ldpc_multi_workspace_size.argtypes = [ctypes.POINTER(Job), i32, ctypes.POINTER(sz)]
         L.ldpc_decode_multi.argtypes = [ctypes.POINTER(Job), i32, vp, sz, vp]
         L.ldpc_autotune.argtypes = [vp, i32, ctypes.POINTER(DecodeParams), ctypes.POINTER(i32),
@@ -140,7 +141,8 @@ def lib():
                   "ldpc_decode_batch_noalloc", "ldpc_encoder_info",
                   "ldpc_encode_batch", "ldpc_random_bits", "ldpc_channel_awgn", "ldpc_count_errors",
                   "ldpc_learn_classes", "ldpc_learn_workspace_size", "ldpc_learn_forward",
-                  "ldpc_learn_backward", "ldpc_multi_workspace_size", "ldpc_decode_multi",
+                  "ldpc_learn_backward", "ldpc_learn_backward_weighted", "ldpc_multi_workspace_size",
+                  "ldpc_decode_multi",
                   "ldpc_autotune"):
             getattr(L, f).restype = ctypes.c_int
         L.ldpc_last_error.restype = ctypes.c_char_p
@@ -288,8 +290,10 @@ class Code:
                                         _ptr(post_out), _stream()))
         return loss
 
-    def learn_backward(self, n_frames, target, weights, ckpt, workspace):
-        """Raw adjoint: d(sum of the forward's losses)/d(weights), [T][C][2]."""
+    def learn_backward(self, n_frames, target, weights, ckpt, workspace, loss_weights=None):
+        """Raw adjoint: d(sum_t w_t loss_t)/d(weights), [T][C][2]; w_t from
+        ``loss_weights`` (a sequence of T finite numbers, copied to the host),
+        all ones if None."""
         F = int(n_frames)
         _need(target, "target", torch.uint8, (F, self.N), self.device, optional=True)
         if not isinstance(weights, torch.Tensor) or weights.dim() != 3:
@@ -297,9 +301,16 @@ class Code:
         _need(weights, "weights", torch.float32, (int(weights.shape[0]), self.n_classes, 2), self.device)
         _need(workspace, "workspace", torch.uint8, (workspace.numel(),), self.device)
         grad = torch.empty_like(weights)
-        _check(lib().ldpc_learn_backward(self._h, int(n_frames), _ptr(target), int(weights.shape[0]),
-                                         _ptr(weights), int(ckpt), _ptr(workspace), workspace.numel(),
-                                         _ptr(grad), _stream()))
+        T = int(weights.shape[0])
+        lw = None
+        if loss_weights is not None:
+            lw = np.ascontiguousarray(np.asarray(loss_weights, dtype=np.float32).reshape(-1))
+            if lw.size != T:
+                raise ValueError(f"loss_weights must hold T = {T} values, not {lw.size}")
+        _check(lib().ldpc_learn_backward_weighted(self._h, int(n_frames), _ptr(target), T,
+                                                  _ptr(weights), int(ckpt), _ptr(workspace), workspace.numel(),
+                                                  None if lw is None else lw.ctypes.data_as(ctypes.c_void_p),
+                                                  _ptr(grad), _stream()))
         return grad
 
     def encoder_info(self) -> dict:

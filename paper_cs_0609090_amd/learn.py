@@ -28,21 +28,25 @@ from . import ldpc
 
 
 class LearnedMinSum(torch.autograd.Function):
-    """Summed loss of the unrolled decoder; gradients only for the weights."""
+    """Loss of the unrolled decoder, sum_t w_t loss_t (w_t = ``loss_weights``,
+    a host sequence of T numbers, or all ones); gradients only for the weights."""
 
     @staticmethod
-    def forward(ctx, weights, gcode, llr, target, ckpt, workspace):
+    def forward(ctx, weights, gcode, llr, target, ckpt, workspace, loss_weights=None):
         w = weights.detach().contiguous()
         loss_t = gcode.learn_forward(llr, target, w, ckpt, workspace)
         ctx.gcode, ctx.target, ctx.ckpt, ctx.workspace, ctx.n = gcode, target, ckpt, workspace, llr.shape[0]
+        ctx.lw = None if loss_weights is None else [float(v) for v in loss_weights]
         ctx.save_for_backward(w)
-        return loss_t.sum()
+        if ctx.lw is None:
+            return loss_t.sum()
+        return (loss_t * torch.tensor(ctx.lw, dtype=loss_t.dtype, device=loss_t.device)).sum()
 
     @staticmethod
     def backward(ctx, g):
         (w,) = ctx.saved_tensors
-        grad = ctx.gcode.learn_backward(ctx.n, ctx.target, w, ctx.ckpt, ctx.workspace)
-        return grad * g, None, None, None, None, None
+        grad = ctx.gcode.learn_backward(ctx.n, ctx.target, w, ctx.ckpt, ctx.workspace, loss_weights=ctx.lw)
+        return grad * g, None, None, None, None, None, None
 
 
 def _frames(gcode, K, n, ebn0_lo, ebn0_hi, key, offset, rng):
@@ -65,12 +69,14 @@ def init_weights(n_classes: int, T: int, alpha: float = 0.8, beta: float = 0.0) 
 
 def train(gcode, T: int = 20, steps: int = 1024, batch: int = 1024, ebn0=(1.5, 2.5), lr: float = 0.01,
           ckpt: int = 5, key=(0x7EA, 1), seed: int = 0, log_every: int = 64, init=(0.8, 0.0),
-          tie_classes: bool = False):
+          tie_classes: bool = False, loss_decay: float = 1.0):
     """Adam on the [T][C][2] pairs; returns (weights [T][C][2], log).  With
     ``tie_classes`` one pair per iteration is shared by every class (its
-    gradient is the sum of the classes').  The log holds the training loss
-    and the loss of one fixed validation batch (frames outside the training
-    stream), both per bit and iteration."""
+    gradient is the sum of the classes').  ``loss_decay`` g weights iteration
+    t's loss by g^(t-1) (normalised to sum T; 1 = the plain sum): g < 1
+    rewards posteriors that are right early, i.e. fewer iterations.  The log
+    holds the training objective and that of one fixed validation batch
+    (frames outside the training stream), both per bit and iteration."""
     C = len(gcode.degree_classes())
     K = gcode.encoder_info()["K"]
     param = init_weights(1 if tie_classes else C, T, *init).requires_grad_(True)
@@ -79,6 +85,11 @@ def train(gcode, T: int = 20, steps: int = 1024, batch: int = 1024, ebn0=(1.5, 2
     def full():
         return param.expand(T, C, 2) if tie_classes else param
     ws = torch.empty(gcode.learn_workspace_size(batch, T, ckpt), dtype=torch.uint8, device="cuda")
+    lw = None
+    if loss_decay != 1.0:
+        g = loss_decay ** np.arange(T, dtype=np.float64)
+        lw = (g * (T / g.sum())).tolist()
+    lw_t = None if lw is None else torch.tensor(lw, dtype=torch.float32, device="cuda")
     rng = np.random.default_rng(seed)
     vllr, vcw = _frames(gcode, K, batch, ebn0[0], ebn0[1], key, 1 << 28, np.random.default_rng(seed + 1))
     log = []
@@ -86,7 +97,7 @@ def train(gcode, T: int = 20, steps: int = 1024, batch: int = 1024, ebn0=(1.5, 2
     t0 = time.time()
     for step in range(steps):
         llr, cw = _frames(gcode, K, batch, ebn0[0], ebn0[1], key, step * batch, rng)
-        loss = LearnedMinSum.apply(full(), gcode, llr, cw, ckpt, ws) * scale
+        loss = LearnedMinSum.apply(full(), gcode, llr, cw, ckpt, ws, lw) * scale
         opt.zero_grad()
         loss.backward()
         opt.step()
@@ -95,7 +106,8 @@ def train(gcode, T: int = 20, steps: int = 1024, batch: int = 1024, ebn0=(1.5, 2
             param[:, :, 1].clamp_(0.0, 4.0)
         if step % log_every == 0 or step == steps - 1:
             with torch.no_grad():
-                vl = float(gcode.learn_forward(vllr, vcw, full().detach().contiguous(), ckpt, ws).sum()) * scale
+                vlt = gcode.learn_forward(vllr, vcw, full().detach().contiguous(), ckpt, ws)
+                vl = float(vlt.sum() if lw_t is None else (vlt * lw_t).sum()) * scale
             log.append({"step": step, "loss": float(loss.detach()), "val_loss": vl, "s": time.time() - t0})
     return full().detach().contiguous(), log
 
@@ -159,12 +171,14 @@ def main(argv=None):
                     help="constant normalisations the learned decoder is compared with")
     ap.add_argument("--tie-classes", action="store_true",
                     help="one pair per iteration shared by all check-degree classes")
+    ap.add_argument("--loss-decay", type=float, default=1.0,
+                    help="weight iteration t's loss by g^(t-1) (g < 1 favours early decoding)")
     args = ap.parse_args(argv)
     code = FER.CODES[args.code]()
     gcode = ldpc.Code.from_parity_check(code)
     w, log = train(gcode, T=args.T, steps=args.steps, batch=args.batch, lr=args.lr, ckpt=args.ckpt,
                    ebn0=(args.ebn0_lo, args.ebn0_hi), init=(args.init_alpha, args.init_beta),
-                   tie_classes=args.tie_classes)
+                   tie_classes=args.tie_classes, loss_decay=args.loss_decay)
     for r in log:
         print(json.dumps({"train": r}), flush=True)
     if args.save:

@@ -87,6 +87,34 @@ def test_gradient_matches_oracle_adjoint(torch_dev, L, name, F, T):
     np.testing.assert_allclose(grads[2], grads[0], rtol=1e-5, atol=1e-6 * scale)
 
 
+def test_weighted_objective_gradient_matches_oracle(torch_dev, L):
+    """Adjoint of sum_t w_t loss_t (iteration weights, some zero) against the
+    oracle's weighted binary64 adjoint, and through LearnedMinSum."""
+    torch = torch_dev
+    from paper_cs_0609090_amd.learn import LearnedMinSum
+    code, w, llr, tgt = _case("irregular", 66, 5, 5)
+    lw = [2.5, 0.0, 1.0, 0.5, 0.0]
+    gc = L.Code.from_parity_check(code)
+    ws = torch.empty(gc.learn_workspace_size(66, 5, 2), dtype=torch.uint8, device="cuda")
+    wd, td, xd = _dev(torch, w), _dev(torch, tgt), _dev(torch, llr)
+    gc.learn_forward(xd, td, wd, 2, ws)
+    g = gc.learn_backward(66, td, wd, 2, ws, loss_weights=lw).cpu().numpy()
+    ref, fw = LO.adjoint(code, llr.astype(np.float64), w.astype(np.float64), tgt, loss_weights=lw)
+    scale = np.abs(ref).max()
+    np.testing.assert_allclose(g, ref, rtol=2e-3, atol=2e-3 * scale)
+    assert np.all(g[4] == 0.0)  # the last iteration's loss has weight 0
+    p = wd.clone().requires_grad_(True)
+    obj = LearnedMinSum.apply(p, gc, xd, td, 2, ws, lw)
+    obj.backward()
+    np.testing.assert_allclose(float(obj), float(np.dot(lw, fw["loss"])), rtol=1e-4)
+    np.testing.assert_allclose(p.grad.cpu().numpy(), g, rtol=1e-6, atol=1e-7 * scale)
+    with pytest.raises(ValueError):
+        gc.learn_backward(66, td, wd, 2, ws, loss_weights=lw[:4])
+    with pytest.raises(L.LdpcError):
+        gc.learn_backward(66, td, wd, 2, ws, loss_weights=[1.0, float("nan"), 1.0, 1.0, 1.0])
+    gc.close()
+
+
 def _syndrome_ok(code, hard):
     rp, ci = np.asarray(code.row_ptr), np.asarray(code.col_idx)
     rows = np.repeat(np.arange(code.M), np.diff(rp))

@@ -77,6 +77,36 @@ def test_adjoint_matches_finite_differences(seed):
     assert np.all(np.abs(grad[:, :, 0]).sum(axis=1) > 0)
 
 
+def test_weighted_adjoint_matches_finite_differences():
+    """The adjoint of sum_t w_t loss_t (iteration weights, some zero) against
+    central differences of that same weighted sum of the forward's losses."""
+    rng = np.random.default_rng(7)
+    code = W.random_small_code(10, 24, (3, 6), seed=47)
+    _, _, levels = LO.degree_classes(code)
+    C, T, F = len(levels), 5, 3
+    llr = rng.normal(1.0, 2.0, size=(F, code.N))
+    target = rng.integers(0, 2, size=(F, code.N))
+    w = np.stack([rng.uniform(0.6, 1.0, size=(T, C)), rng.uniform(0.0, 0.4, size=(T, C))], axis=2)
+    lw = np.array([3.0, 0.0, 1.5, 0.25, 0.0])
+    grad, _ = LO.adjoint(code, llr, w, target, loss_weights=lw)
+    eps = 1e-6
+    num = np.zeros_like(w)
+    for i in np.ndindex(*w.shape):
+        wp, wm = w.copy(), w.copy()
+        wp[i] += eps
+        wm[i] -= eps
+        num[i] = (lw @ LO.forward(code, llr, wp, target)["loss"] - lw @ LO.forward(code, llr, wm, target)["loss"]) / (
+            2 * eps)
+    np.testing.assert_allclose(grad, num, rtol=2e-5, atol=2e-5 * np.abs(num).max())
+    # the last iteration's loss has weight 0: its own pairs get no gradient
+    assert np.all(grad[T - 1] == 0.0)
+    # linear in the iteration weights
+    g1, _ = LO.adjoint(code, llr, w, target, loss_weights=np.eye(T)[0])
+    g3, _ = LO.adjoint(code, llr, w, target, loss_weights=np.eye(T)[2])
+    g4, _ = LO.adjoint(code, llr, w, target, loss_weights=np.eye(T)[3])
+    np.testing.assert_allclose(grad, 3.0 * g1 + 1.5 * g3 + 0.25 * g4, rtol=1e-12, atol=1e-12 * np.abs(grad).max())
+
+
 def test_loss_of_the_transmitted_word_direction():
     """Raising every a when the decoder is confidently right lowers the loss
     (messages grow in the direction of the codeword)."""
