@@ -62,10 +62,10 @@ KERNELS = {
 # path's kernels), keyed by the hash of the kernel sources the counters were
 # taken on; any other source reports traffic as null.
 MEASURED_TRAFFIC = [
-    {"kernel": "packed", "hash": "aa7c9ca62e7b9a1d", "workload": ("int8", "single_scan", 512, 50),
-     "bytes": 235.4e6, "profile": "profiles/ss_pk_int8_ira64800_512f.md"},
-    {"kernel": "packed", "hash": "aa7c9ca62e7b9a1d", "workload": ("1bit", "single_scan", 512, 50),
-     "bytes": 235.8e6, "profile": "profiles/ss_pk_1bit_ira64800_512f.md"},
+    {"kernel": "packed", "hash": "5a380e8235b91a4e", "workload": ("int8", "single_scan", 512, 50),
+     "bytes": 238.9e6, "profile": "profiles/ss_pk_int8_ira64800_512f.md"},
+    {"kernel": "packed", "hash": "5a380e8235b91a4e", "workload": ("1bit", "single_scan", 512, 50),
+     "bytes": 235.9e6, "profile": "profiles/ss_pk_1bit_ira64800_512f.md"},
     {"kernel": "f32_frames", "hash": "1c5cdaa9c2275be3", "workload": ("fp32", "single_scan", 512, 50),
      "bytes": 105147.1e6, "profile": "profiles/fl_f32_ira64800_512f.md"},
     {"kernel": "reg1", "hash": "e7d86239f37f995e", "workload": ("int8", "single_scan", 512, 50),
@@ -209,6 +209,8 @@ def main():
     ap.add_argument("--msg", default="int8", choices=["int8", "1bit", "fp32"])
     ap.add_argument("--sched", default="single_scan", choices=["single_scan", "two_scan"])
     ap.add_argument("--layout", default="auto", choices=["auto", "lds", "hbm", "reg", "reg1", "frames"])
+    ap.add_argument("--msg-bits", type=int, default=6, choices=[6, 7, 8],
+                    help="fixed-point message width (int8 only; the LLR step halves per extra bit)")
     ap.add_argument("--cpu-frames", type=int, default=192)
     ap.add_argument("--cpu-single-frames", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -236,14 +238,16 @@ def main():
     log(f"[bench] generating {F} frames of N={N} at {ebn0} dB")
     key = (0xC2, 0xBE) if args.code == "ira64800" else (0xBE, sorted(CODES).index(args.code))
     llr = W.awgn_llr(N, F, ebn0, code.design_rate, key=key)
-    q = W.quantize_llr(llr)
+    step = 0.5 / (1 << (args.msg_bits - 6))
+    q = W.quantize_llr(llr, step=step, qmax=(1 << (args.msg_bits - 1)) - 1)
     gcode = ldpc.Code.from_parity_check(code, device=0)
     xq = torch.from_numpy(q).to(dev)
     xf = torch.from_numpy(llr).to(dev)
 
     def run(msg, sched, steps, warmup, layout="auto", early_stop=False, with_llr=True):
+        bits = args.msg_bits if msg == "int8" else 0
         p = ldpc.make_params(max_iter=max_iter, alpha=alpha, early_stop=early_stop, msg=msg,
-                             sched=sched, layout=layout)
+                             sched=sched, layout=layout, msg_bits=bits, llr_step=step)
         x = xf if msg == "fp32" else xq
         wall, per, out = time_decode(torch, gcode, ldpc, x, p, steps, warmup, with_llr)
         iters = out["iters"].to(torch.int64).sum().item()
@@ -260,11 +264,12 @@ def main():
     alg_ops = (ALG_OPS_PER_EDGE * E + ALG_OPS_PER_ROW * M) * r["iters"]
     achieved_alu = alg_ops / r["kernel_s"] / 1e12
     plan = gcode.plan(F, ldpc.make_params(max_iter=max_iter, alpha=alpha, early_stop=False, msg=args.msg,
-                                          sched=args.sched, layout=args.layout))
+                                          sched=args.sched, layout=args.layout,
+                                          msg_bits=args.msg_bits if args.msg == "int8" else 0))
     srcs, bound = KERNELS[plan["kernel"]]
     h = source_hash(srcs)
     traffic = next((t["bytes"] for t in MEASURED_TRAFFIC if t["kernel"] == plan["kernel"] and t["hash"] == h
-                    and t["workload"] == (args.msg, args.sched, F, max_iter)
+                    and t["workload"] == (args.msg, args.sched, F, max_iter) and args.msg_bits == 6
                     and t.get("code", "ira64800") == args.code), None)
     kernel_desc = {"kernel": plan["kernel"], "sources": list(srcs), "threads": plan["threads"]}
     if plan["frames_per_lane"]:
@@ -283,14 +288,15 @@ def main():
         "vs_baseline": None,
         "dtype": {"int8": "int8", "1bit": "1bit+int8", "fp32": "f32"}[args.msg],
         "data": f"synthetic: seeded Philox4x32-10 BPSK/AWGN LLRs, seeded {args.code} code",
-        "config": {"workload": f"{args.code}_r{code.N - code.M}/{code.N}_{F}frames_{ebn0}dB_{args.msg}_"
-                               f"{args.sched}_max{max_iter}_noearlystop"
-                               if args.code != "ira64800" else
-                               f"ira64800_r1/2_{F}frames_{ebn0}dB_{args.msg}_{args.sched}_"
-                               f"max{max_iter}_noearlystop",
+        "config": {"workload": (f"{args.code}_r{code.N - code.M}/{code.N}_{F}frames_{ebn0}dB_{args.msg}_"
+                                f"{args.sched}_max{max_iter}_noearlystop"
+                                if args.code != "ira64800" else
+                                f"ira64800_r1/2_{F}frames_{ebn0}dB_{args.msg}_{args.sched}_"
+                                f"max{max_iter}_noearlystop") + (f"_{args.msg_bits}bit" if args.msg_bits != 6 else ""),
                    "N": N, "M": M, "E": E, "frames": F, "max_iter": max_iter,
                    "early_stop": False, "alpha": alpha, "ebn0_db": ebn0,
-                   "msg": args.msg, "sched": args.sched, "layout": args.layout},
+                   "msg": args.msg, "sched": args.sched, "layout": args.layout,
+                   **({"msg_bits": args.msg_bits, "llr_step": step} if args.msg_bits != 6 else {})},
         "edge_updates_per_s": r["eups"],
     }
     if bound == "alu":

@@ -46,6 +46,27 @@ ldpc_status ldpc_decode_multi(const ldpc_job *jobs, int32_t n_jobs, void *worksp
                               void *stream);
 
 /*
+ * The same jobs in ONE persistent launch: 1024-thread workgroups, one per
+ * CU, take work items from a device counter until none is left; a work item
+ * is 1024 / T frames of one job (T: threads of the code's packed register
+ * shape, 256, 512 or 1024), each frame in its own LDS region, the frames of
+ * an item sharing the workgroup's barriers (a frame that has stopped idles
+ * until the item's last frame stops).  Jobs with the longest frames
+ * (edges x max_iter) are taken first.  Results equal ldpc_decode_multi's.
+ * Every job with frames must run the packed kernel in 6-bit int8
+ * single-scan (AUTO or REG layout; LDPC_EUNSUPPORTED otherwise); at most 8
+ * jobs with frames.  Early stop folds into the gathers (as in
+ * ldpc_decode_batch) only when every job has early_stop, no posterior
+ * output and max_iter >= 1; otherwise every job takes the separate
+ * syndrome pass.  Workspace: ldpc_multi_persistent_workspace_size() bytes
+ * (the work-item counter, zeroed by a kernel before the launch, so the call
+ * is capturable); allocates nothing, never synchronises.
+ */
+ldpc_status ldpc_multi_persistent_workspace_size(const ldpc_job *jobs, int32_t n_jobs, size_t *bytes);
+ldpc_status ldpc_decode_multi_persistent(const ldpc_job *jobs, int32_t n_jobs, void *workspace,
+                                         size_t workspace_bytes, void *stream);
+
+/*
  * Time every layout that can run (msg, sched) of *p on this code (REG, REG1,
  * LDS, HBM, FRAMES; each on n_frames zero-LLR frames with early stop off and
  * p->max_iter iterations, best of 3 after a warm-up), allocating device

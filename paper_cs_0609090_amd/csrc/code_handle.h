@@ -33,6 +33,12 @@ struct ldpc_code {
     uint32_t *d_pk_idx = nullptr;
     uint32_t *d_pk_idx16 = nullptr;  // the records for int16 Z_old (8-bit messages; accumulator
                                      // fields of 16 bits or more), else null
+    // persistent multi-code launch: frames per 1024-thread workgroup (0: not
+    // supported), LDS bytes of one frame's region, and the records of every
+    // region one set after another (null when one region: d_pk_idx serves)
+    int32_t pkGroups = 0;
+    uint32_t pkRegion = 0;
+    uint32_t *d_pk_grp = nullptr;
     uint32_t *d_pk_slot = nullptr;  // [N] posterior slot of each variable
     // frames-across-lanes binary32 path: CSR rows and, per edge, {variable,
     // position of the edge in variable-major order}
@@ -89,6 +95,14 @@ struct DeviceGuard {
 ldpc_status decode_job(const ldpc_code *c, int32_t n_frames, const void *llr_in, const ldpc_decode_params *p,
                        uint8_t *hard_out, float *llr_out, int32_t *iters_out, uint8_t *syndrome_ok,
                        void *workspace, size_t workspace_bytes, void *stream, bool launch);
+
+struct PersistJob;
+// One job of a persistent multi-code launch: the checks of decode_job, then
+// that the call runs the 6-bit int8 packed kernel with a shape the persistent
+// kernel holds; fills the job's arguments (items and order are the caller's).
+ldpc_status persist_job(const ldpc_code *c, int32_t n_frames, const void *llr_in, const ldpc_decode_params *p,
+                        uint8_t *hard_out, float *llr_out, int32_t *iters_out, uint8_t *syndrome_ok,
+                        PersistJob *out);
 
 // error state of the calling thread (ldpc_last_error), set by every entry point
 ldpc_status set_error(ldpc_status st, const std::string &msg);

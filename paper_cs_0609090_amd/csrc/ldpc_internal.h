@@ -111,6 +111,26 @@ hipError_t launch_ss_reg(const DecodeArgs &a, int msg, int D, int R, int P, size
 hipError_t launch_ss_pk(const DecodeArgs &a, int D, int R, int T, int S, bool onebit, int qb, size_t lds,
                         hipStream_t s);
 void pk_shapes(int *out, int cap, int *count);   // (D, R, T, lanes per row) quadruples
+
+// Persistent multi-code launch of the packed kernel (ldpc_decode_multi_persistent).
+constexpr int kPersistThreads = 1024;  // threads per workgroup
+constexpr int kMaxPersistJobs = 8;
+struct PersistJob {
+    DecodeArgs a;          // the job's decode arguments
+    const uint32_t *recs;  // per-edge records of the workgroup's frame regions: region g at recs + g * rec_words
+    uint32_t rec_words;    // 32-bit words of one region's records
+    uint32_t region;       // LDS bytes of one frame's region (multiple of 16)
+    int32_t shape;         // pk_shape_id() of the job's packed shape
+    int32_t first;         // first work item of the job (items are numbered job after job)
+};
+struct PersistArgs {
+    PersistJob job[kMaxPersistJobs];
+    int32_t njobs, nitems;  // jobs in use; work items in all (an item: kPersistThreads / T frames of a job)
+    int32_t *counter;       // device work-item counter (zeroed by the launcher)
+    uint32_t off_item;      // LDS byte offset of the word that hands a work item to the workgroup
+};
+int pk_shape_id(int D, int R, int T, int S);  // index of an instantiated packed shape, -1 if none
+hipError_t launch_ss_pk_persist(const PersistArgs &pa, bool fused, size_t lds, int grid, hipStream_t s);
 bool reg_shape_available(int D, int R, int P);
 void reg_shapes(int *out, int cap, int *count);  // (D, R, P) triples
 constexpr int kRegThreads = 1024;

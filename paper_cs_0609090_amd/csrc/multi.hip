@@ -193,6 +193,84 @@ ldpc_status ldpc_decode_multi(const ldpc_job *jobs, int32_t n_jobs, void *worksp
     return LDPC_OK;
 }
 
+ldpc_status ldpc_multi_persistent_workspace_size(const ldpc_job *jobs, int32_t n_jobs, size_t *bytes) {
+    if (!bytes) return ldpc::set_error(LDPC_EINVAL, "bytes is NULL");
+    std::vector<size_t> off;
+    size_t total = 0;
+    ldpc_status st = job_layout(jobs, n_jobs, &off, &total);
+    if (st != LDPC_OK) return st;
+    *bytes = 256;  // the work-item counter
+    return LDPC_OK;
+}
+
+ldpc_status ldpc_decode_multi_persistent(const ldpc_job *jobs, int32_t n_jobs, void *workspace,
+                                         size_t workspace_bytes, void *stream) {
+    std::vector<size_t> off;
+    size_t total = 0;
+    ldpc_status st = job_layout(jobs, n_jobs, &off, &total);
+    if (st != LDPC_OK) return st;
+    if (!workspace || workspace_bytes < 256)
+        return ldpc::set_error(LDPC_EINVAL, "workspace missing or smaller than "
+                                            "ldpc_multi_persistent_workspace_size()");
+    if (reinterpret_cast<uintptr_t>(workspace) & 255u)
+        return ldpc::set_error(LDPC_EINVAL, "workspace must be 256-byte aligned");
+    std::vector<int> active;
+    for (int j = 0; j < n_jobs; ++j)
+        if (jobs[j].n_frames > 0) active.push_back(j);
+    if ((int)active.size() > ldpc::kMaxPersistJobs)
+        return ldpc::set_error(LDPC_EUNSUPPORTED, "the persistent launch takes at most 8 jobs with frames");
+    ldpc::PersistArgs pa{};
+    size_t lds = 0;
+    bool fused = true;
+    for (size_t k = 0; k < active.size(); ++k) {
+        const ldpc_job &b = jobs[active[k]];
+        st = ldpc::persist_job(b.code, b.n_frames, b.llr_in, &b.params, b.hard_out, b.llr_out, b.iters_out,
+                               b.syndrome_ok, &pa.job[k]);
+        if (st != LDPC_OK) return ldpc::set_error(st, job_prefix(active[k]) + ldpc_last_error());
+        lds = std::max(lds, (size_t)b.code->pkGroups * b.code->pkRegion);
+        fused = fused && b.params.early_stop && b.llr_out == nullptr && b.params.max_iter >= 1;
+    }
+    for (int j = 0; j < n_jobs; ++j)  // jobs without frames are validated too
+        if (jobs[j].n_frames == 0) {
+            const ldpc_job &b = jobs[j];
+            ldpc::PersistJob tmp;
+            st = ldpc::persist_job(b.code, 0, b.llr_in, &b.params, b.hard_out, b.llr_out, b.iters_out,
+                                   b.syndrome_ok, &tmp);
+            if (st != LDPC_OK) return ldpc::set_error(st, job_prefix(j) + ldpc_last_error());
+        }
+    if (active.empty()) return LDPC_OK;
+    const ldpc_code *c0 = jobs[active[0]].code;
+    if (lds + 16 > (size_t)c0->lds_limit)
+        return ldpc::set_error(LDPC_EUNSUPPORTED, "the jobs' LDS regions do not fit one workgroup");
+    // longest frames first (so the last items are short), work items job after job
+    std::vector<int> order(active.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        const ldpc_job &a = jobs[active[x]], &b = jobs[active[y]];
+        return (double)a.code->E * a.params.max_iter > (double)b.code->E * b.params.max_iter;
+    });
+    ldpc::PersistArgs sorted{};
+    int items = 0;
+    for (size_t k = 0; k < order.size(); ++k) {
+        sorted.job[k] = pa.job[order[k]];
+        sorted.job[k].first = items;
+        const int G = jobs[active[order[k]]].code->pkGroups;
+        items += (jobs[active[order[k]]].n_frames + G - 1) / G;
+    }
+    sorted.njobs = (int)order.size();
+    sorted.nitems = items;
+    sorted.counter = static_cast<int32_t *>(workspace);
+    sorted.off_item = (uint32_t)((lds + 15) / 16 * 16);
+    ldpc::DeviceGuard g(c0->device);
+    if (!g.ok) return ldpc::set_error(LDPC_EDEVICE, "hipSetDevice failed");
+    const int grid = std::min(items, std::max(c0->cu_count, 1));
+    hipError_t e = ldpc::launch_ss_pk_persist(sorted, fused, sorted.off_item + 16, grid,
+                                             static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return ldpc::set_error(LDPC_EDEVICE, std::string("persistent launch: ") + hipGetErrorString(e));
+    ldpc::clear_error();
+    return LDPC_OK;
+}
+
 ldpc_status ldpc_autotune(ldpc_code *code, int32_t n_frames, const ldpc_decode_params *p, int32_t *best_layout,
                           float *best_ms, int32_t *n_tried) {
     if (!code || !p || !best_layout) return ldpc::set_error(LDPC_EINVAL, "NULL argument");

@@ -578,7 +578,7 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
             for (int j = 0; j < row_ptr[m + 1] - row_ptr[m]; ++j)
                 ell_reg[(size_t)j * Mr + m] = (uint32_t)col_idx[row_ptr[m] + j];
     }
-    std::vector<uint32_t> pk_idx, pk_idx16, pk_slot;
+    std::vector<uint32_t> pk_idx, pk_idx16, pk_grp, pk_slot;
     if (c->pkD > 0) {
         // record {zold_a, zold_b, acc_a, acc_b} of slot j of rows a = p*T/S + t/S,
         // b = (p + R/2)*T/S + t/S (T threads, S lanes per row; lane t holds the
@@ -617,6 +617,30 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
         build(pk_idx, 1);
         // 7-8 bit messages need accumulator fields of 16 bits or more
         if (Pk <= 2) build(pk_idx16, 2);
+        // the persistent launch: 1024 / T frames per workgroup, each in its
+        // own LDS region of the 6-bit plan's size; one record set per region
+        // (the records hold absolute LDS addresses)
+        const size_t region = align_up((size_t)c->dummy + 1, 16) +
+                              align_up(4 * ((size_t)c->dummy / Pk + 1 + 64), 16) + 16;
+        const int G = ldpc::kPersistThreads % T == 0 ? ldpc::kPersistThreads / T : 0;
+        if (G >= 1 && (size_t)G * region + 16 <= (size_t)lds_dev) {
+            c->pkGroups = G;
+            c->pkRegion = (uint32_t)region;
+            if (G > 1) {
+                std::vector<uint32_t> one;
+                build(one, 1);
+                pk_grp.reserve(one.size() * G);
+                for (int g = 0; g < G; ++g) {
+                    const uint32_t off = (uint32_t)(g * region);
+                    for (size_t i = 0; i < one.size(); i += 4) {
+                        pk_grp.push_back(one[i] + off);
+                        pk_grp.push_back(one[i + 1] + off);
+                        pk_grp.push_back(one[i + 2] + (off << 5));
+                        pk_grp.push_back(one[i + 3] + (off << 5));
+                    }
+                }
+            }
+        }
     }
     if (device < 0) {  // host-only handle: planning and queries, no decoding
         c->lds_limit = kHostOnlyLds;
@@ -656,6 +680,8 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
         e6 = ldpc::dev_malloc((void **)&c->d_pk_slot, pk_slot.size() * sizeof(uint32_t));
         if (e5 == hipSuccess && !pk_idx16.empty())
             e5 = ldpc::dev_malloc((void **)&c->d_pk_idx16, pk_idx16.size() * sizeof(uint32_t));
+        if (e5 == hipSuccess && !pk_grp.empty())
+            e5 = ldpc::dev_malloc((void **)&c->d_pk_grp, pk_grp.size() * sizeof(uint32_t));
     }
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || e5 != hipSuccess ||
         e6 != hipSuccess || e7 != hipSuccess || e8 != hipSuccess || e9 != hipSuccess || e10 != hipSuccess) {
@@ -678,6 +704,8 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
                                   hipMemcpyHostToDevice) != hipSuccess) ||
         (c->d_pk_idx16 && hipMemcpy(c->d_pk_idx16, pk_idx16.data(), pk_idx16.size() * sizeof(uint32_t),
                                     hipMemcpyHostToDevice) != hipSuccess) ||
+        (c->d_pk_grp && hipMemcpy(c->d_pk_grp, pk_grp.data(), pk_grp.size() * sizeof(uint32_t),
+                                  hipMemcpyHostToDevice) != hipSuccess) ||
         (c->d_pk_slot && hipMemcpy(c->d_pk_slot, pk_slot.data(), pk_slot.size() * sizeof(uint32_t),
                                    hipMemcpyHostToDevice) != hipSuccess)) {
         ldpc_code_destroy(c);
@@ -707,6 +735,7 @@ ldpc_status ldpc_code_destroy(ldpc_code *code) {
     if (code->d_ell_reg) (void)hipFree(code->d_ell_reg);
     if (code->d_pk_idx) (void)hipFree(code->d_pk_idx);
     if (code->d_pk_idx16) (void)hipFree(code->d_pk_idx16);
+    if (code->d_pk_grp) (void)hipFree(code->d_pk_grp);
     if (code->d_pk_slot) (void)hipFree(code->d_pk_slot);
     delete code;
     return LDPC_OK;
@@ -835,44 +864,12 @@ ldpc_status ldpc_decode_batch_noalloc(const ldpc_code *c, int32_t n_frames, cons
 
 }  // extern "C"
 
-namespace ldpc {
-
-ldpc_status decode_job(const ldpc_code *c, int32_t n_frames, const void *llr_in, const ldpc_decode_params *p,
-                       uint8_t *hard_out, float *llr_out, int32_t *iters_out, uint8_t *syndrome_ok,
-                       void *workspace, size_t workspace_bytes, void *stream, bool launch) {
-    if (!c) return fail(LDPC_EINVAL, "code is NULL");
-    if (n_frames < 0) return fail(LDPC_EINVAL, "n_frames < 0");
-    ldpc_status st = validate_params(p);
-    if (st != LDPC_OK) return st;
-    if (n_frames > 0 && (!llr_in || !hard_out || !iters_out || !syndrome_ok))
-        return fail(LDPC_EINVAL, "llr_in, hard_out, iters_out and syndrome_ok are required");
-    Plan pl;
-    st = make_plan(c, p, &pl);
-    if (st != LDPC_OK) return st;
-    const size_t check_off = align_up(decode_workspace(c, p, pl, n_frames), 256);
-    const size_t need = total_workspace(c, p, pl, n_frames);
-    if (need > 0 && (!workspace || workspace_bytes < need))
-        return fail(LDPC_EINVAL, "workspace missing or smaller than ldpc_decode_workspace_size()");
-    if (workspace && (reinterpret_cast<uintptr_t>(workspace) & 255u))
-        return fail(LDPC_EINVAL, "workspace must be 256-byte aligned");
-    if (c->device < 0) return fail(LDPC_EINVAL, "host-only handle (device < 0) cannot decode");
-    if (n_frames == 0 || !launch) return LDPC_OK;
-
-    DeviceGuard g(c->device);
-    if (!g.ok) return fail(LDPC_EDEVICE, "hipSetDevice failed");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-
-    if (p->flags & LDPC_F_CHECK_INPUT) {
-        int32_t *bad = reinterpret_cast<int32_t *>(static_cast<uint8_t *>(workspace) + check_off);
-        hipError_t e = ldpc::launch_check_input(llr_in, (int64_t)n_frames * c->N, p->msg, qmax_of(p), bad, s);
-        int32_t hbad = 0;
-        if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return fail(LDPC_EDEVICE, std::string("input check failed: ") + hipGetErrorString(e));
-        if (hbad) return fail(LDPC_EINVAL, "llr_in holds non-finite or out-of-range values");
-    }
-
-    ldpc::DecodeArgs a{};
+namespace {
+// The kernel arguments of one decode call (plan already made).
+void fill_args(const ldpc_code *c, int32_t n_frames, const void *llr_in, const ldpc_decode_params *p, const Plan &pl,
+               uint8_t *hard_out, float *llr_out, int32_t *iters_out, uint8_t *syndrome_ok, void *workspace,
+               ldpc::DecodeArgs *out) {
+    ldpc::DecodeArgs &a = *out;
     a.c.M = c->M;
     a.c.N = c->N;
     a.c.Mp = c->Mp;
@@ -916,6 +913,48 @@ ldpc_status decode_job(const ldpc_code *c, int32_t n_frames, const void *llr_in,
     a.wsched_T = p->weight_iters;
     a.qmax = qmax_of(p);
     a.zmax = 2 * a.qmax;
+}
+}  // namespace
+
+namespace ldpc {
+
+ldpc_status decode_job(const ldpc_code *c, int32_t n_frames, const void *llr_in, const ldpc_decode_params *p,
+                       uint8_t *hard_out, float *llr_out, int32_t *iters_out, uint8_t *syndrome_ok,
+                       void *workspace, size_t workspace_bytes, void *stream, bool launch) {
+    if (!c) return fail(LDPC_EINVAL, "code is NULL");
+    if (n_frames < 0) return fail(LDPC_EINVAL, "n_frames < 0");
+    ldpc_status st = validate_params(p);
+    if (st != LDPC_OK) return st;
+    if (n_frames > 0 && (!llr_in || !hard_out || !iters_out || !syndrome_ok))
+        return fail(LDPC_EINVAL, "llr_in, hard_out, iters_out and syndrome_ok are required");
+    Plan pl;
+    st = make_plan(c, p, &pl);
+    if (st != LDPC_OK) return st;
+    const size_t check_off = align_up(decode_workspace(c, p, pl, n_frames), 256);
+    const size_t need = total_workspace(c, p, pl, n_frames);
+    if (need > 0 && (!workspace || workspace_bytes < need))
+        return fail(LDPC_EINVAL, "workspace missing or smaller than ldpc_decode_workspace_size()");
+    if (workspace && (reinterpret_cast<uintptr_t>(workspace) & 255u))
+        return fail(LDPC_EINVAL, "workspace must be 256-byte aligned");
+    if (c->device < 0) return fail(LDPC_EINVAL, "host-only handle (device < 0) cannot decode");
+    if (n_frames == 0 || !launch) return LDPC_OK;
+
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(LDPC_EDEVICE, "hipSetDevice failed");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    if (p->flags & LDPC_F_CHECK_INPUT) {
+        int32_t *bad = reinterpret_cast<int32_t *>(static_cast<uint8_t *>(workspace) + check_off);
+        hipError_t e = ldpc::launch_check_input(llr_in, (int64_t)n_frames * c->N, p->msg, qmax_of(p), bad, s);
+        int32_t hbad = 0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return fail(LDPC_EDEVICE, std::string("input check failed: ") + hipGetErrorString(e));
+        if (hbad) return fail(LDPC_EINVAL, "llr_in holds non-finite or out-of-range values");
+    }
+
+    ldpc::DecodeArgs a{};
+    fill_args(c, n_frames, llr_in, p, pl, hard_out, llr_out, iters_out, syndrome_ok, workspace, &a);
 
     hipError_t e;
     if (pl.family == 0)
@@ -936,6 +975,37 @@ ldpc_status decode_job(const ldpc_code *c, int32_t n_frames, const void *llr_in,
     else
         e = ldpc::launch_two_scan(a, p->msg, pl.cfg, s);
     if (e != hipSuccess) return fail(LDPC_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return LDPC_OK;
+}
+
+
+ldpc_status persist_job(const ldpc_code *c, int32_t n_frames, const void *llr_in, const ldpc_decode_params *p,
+                        uint8_t *hard_out, float *llr_out, int32_t *iters_out, uint8_t *syndrome_ok,
+                        PersistJob *out) {
+    if (!c) return fail(LDPC_EINVAL, "code is NULL");
+    ldpc_status st = validate_params(p);
+    if (st != LDPC_OK) return st;
+    if (p->msg != LDPC_MSG_INT8 || p->sched != LDPC_SINGLE_SCAN || qmax_of(p) != kQmax6)
+        return fail(LDPC_EUNSUPPORTED, "the persistent launch runs 6-bit int8 single-scan only");
+    Plan pl;
+    st = make_plan(c, p, &pl);
+    if (st != LDPC_OK) return st;
+    const int shape = pk_shape_id(c->pkD, c->pkR, c->pkT, c->pkS);
+    if (pl.family != 4 || c->pkGroups < 1 || shape < 0)
+        return fail(LDPC_EUNSUPPORTED, "the persistent launch needs the packed kernel with a shape of 256, 512 "
+                                       "or 1024 threads (this call plans another kernel)");
+    // the remaining checks of a decode call (the packed kernel needs no workspace)
+    st = decode_job(c, n_frames, llr_in, p, hard_out, llr_out, iters_out, syndrome_ok, nullptr, 0, nullptr, false);
+    if (st != LDPC_OK) return st;
+    if ((size_t)c->pkRegion != align_up(pl.cfg.lds, 16))
+        return fail(LDPC_EUNSUPPORTED, "persistent launch: LDS region mismatch");
+    PersistJob &j = *out;
+    j = PersistJob{};
+    fill_args(c, n_frames, llr_in, p, pl, hard_out, llr_out, iters_out, syndrome_ok, nullptr, &j.a);
+    j.recs = c->pkGroups > 1 ? c->d_pk_grp : c->d_pk_idx;
+    j.rec_words = (uint32_t)((size_t)(c->pkR / 2) * c->pkD * c->pkT * 4);
+    j.region = c->pkRegion;
+    j.shape = shape;
     return LDPC_OK;
 }
 

@@ -174,9 +174,24 @@ constexpr int pk_waves_per_eu() {
 // LANES per row: with 2 the lanes 2u and 2u + 1 hold slots 0..D-1 and
 // D..2D-1 of the same two rows, and combine their minima, sign parities and
 // syndrome shares with one DPP exchange per row pair.
-template <int D, int R, bool ONEBIT, bool FUSED, int T, int LANES, int QB>
-__global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(pk_waves_per_eu<D, R, T>())))
-ss_pk_kernel(DecodeArgs a) {
+// One frame decoded by T threads.  LOCK: the workgroup holds several such
+// groups that share its barriers (the persistent multi-code kernel), so a
+// group whose frame has stopped (or that has no frame: live = false) keeps
+// taking part in every barrier until all groups of the workgroup are done.
+//  f      frame index in the batch of `a`
+//  lds    LDS of the workgroup (address 0: the per-edge records hold absolute
+//         LDS addresses, so the kernel declares no LDS but this dynamic
+//         array); base: byte offset of this group's region
+//  rec_p  the per-edge records of this group's region
+//  vote   LOCK: two words of the workgroup's LDS outside every region, and
+//         whether this thread is the workgroup's first (it clears them);
+//         the workgroup-wide "any group still active" vote goes through them
+//         (a library reduction such as __syncthreads_or would add LDS of its
+//         own ahead of the dynamic array and move it off address 0)
+template <int D, int R, bool ONEBIT, bool FUSED, int T, int LANES, int QB, bool LOCK>
+__device__ __forceinline__ void pk_frame(const DecodeArgs &a, int f, bool live, uint8_t *lds, uint32_t base,
+                                         const uint32_t *rec_p, int tid, int *vote = nullptr,
+                                         bool wg_first = false) {
     static_assert(LANES == 1 || LANES == 2, "one or two lanes per row");
     static_assert(QB == 6 || !ONEBIT, "the 1-bit state holds 6-bit magnitudes");
     using Wd = Width<QB>;
@@ -191,18 +206,17 @@ ss_pk_kernel(DecodeArgs a) {
     // where B can reach 127), else one multiply-add and a max (fewer
     // instructions, faster for short rows)
     constexpr bool kMaskSelect = ONEBIT || D > 8 || QB == 8;
-    extern __shared__ __align__(16) uint8_t lds[];
-    const int tid = threadIdx.x;
-    const int f = blockIdx.x;
     const int N = a.c.N;
     const int P = a.zpack;
     const uint32_t dummy = (uint32_t)a.c.dummy;
-    uint8_t *zold = lds;  // Z_old + 63 at LDS offset 0 (the planner places it there)
-    uint32_t *zacc = reinterpret_cast<uint32_t *>(lds + a.off_zacc);
-    int *flag = reinterpret_cast<int *>(lds + a.off_aux);  // [0]: separate check, [1], [2]: fused
-    const int8_t *__restrict__ z0 = static_cast<const int8_t *>(a.llr_in) + (size_t)f * N;
-    const __amdgpu_buffer_rsrc_t rec = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)a.c.pk_idx, (short)0, RP * D * kT * 16, kRsrcWord3);
+    uint8_t *zold = lds + base;  // Z_old + 63 at the start of the region (the planner places it there)
+    uint32_t *zacc = reinterpret_cast<uint32_t *>(lds + base + a.off_zacc);
+    int *flag = reinterpret_cast<int *>(lds + base + a.off_aux);  // [0]: separate check, [1], [2]: fused
+    // an idle group (no frame) reads frame 0's input and writes nothing
+    const int8_t *__restrict__ z0 = static_cast<const int8_t *>(a.llr_in) + (size_t)(live ? f : 0) * N;
+    const __amdgpu_buffer_rsrc_t rec =
+        __builtin_amdgcn_make_buffer_rsrc((void *)rec_p, (short)0, RP * D * kT * 16, kRsrcWord3);
+    bool done = LOCK && !live;  // LOCK: this group has finished (or never had a frame)
     const int bitsP = (P == 1) ? 32 : (P == 2 ? 16 : 10);
     const int biasP = a.zbias;
     const uint32_t maskP = (P == 1) ? 0xFFFFFFFFu : ((1u << bitsP) - 1u);
@@ -245,6 +259,10 @@ ss_pk_kernel(DecodeArgs a) {
         flag[0] = 0;
         flag[1] = 0;
         flag[2] = 0;
+    }
+    if (LOCK && wg_first) {
+        vote[0] = 0;
+        vote[1] = 0;
     }
 
     // Message state of each row pair.
@@ -292,13 +310,16 @@ ss_pk_kernel(DecodeArgs a) {
         // rows; flag[1 + (it & 1)] is set by this iteration and read after its
         // first barrier, the other one (read last iteration) is cleared here
         uint32_t zodd = 0;
-        if (FUSED && tid == 0) flag[1 + ((it + 1) & 1)] = 0;
+        if (FUSED && tid == 0 && !done) flag[1 + ((it + 1) & 1)] = 0;
         if (a.wsched) {  // per-iteration pair (Sec. III's lambda_k, beta_k)
             int a8i, bi;
             sched_pair(a, it, a8i, bi);
             a8x2 = (uint32_t)a8i * 0x00010001u;
             c8x2 = rounding_offset<QB>(bi);
         }
+        // (a constant trip count keeps the loop unrolled: the per-row-pair
+        // register arrays stay registers)
+        if (!(LOCK && done))
 #pragma unroll
         for (int p = 0; p < RP; ++p) {
             __builtin_amdgcn_sched_barrier(0);
@@ -470,9 +491,24 @@ ss_pk_kernel(DecodeArgs a) {
         }
         if (FUSED && it >= 2 && (zodd & Wd::HMASK)) flag[1 + (it & 1)] = 1;
         __syncthreads();
-        if (FUSED && it >= 2 && flag[1 + (it & 1)] == 0) {  // Z^(it-1) is a codeword
+        if (FUSED && it >= 2 && !done && flag[1 + (it & 1)] == 0) {  // Z^(it-1) is a codeword
             conv_prev = true;
-            break;
+            if (!LOCK) break;
+            done = true;
+        }
+        if constexpr (LOCK) {  // every group of the workgroup has finished?
+            if (!done && tid == 0) atomicOr(&vote[it & 1], 1);
+            __syncthreads();
+            const bool any = vote[it & 1] != 0;
+            // the other word was last read in the previous iteration, before
+            // its second barrier, and is next set after the next first barrier
+            if (wg_first) vote[(it + 1) & 1] = 0;
+            if (!any) break;
+        }
+        if (LOCK && done) {
+            __syncthreads();
+            if (!FUSED && a.early_stop) __syncthreads();
+            continue;
         }
         if (tid == 0) *flag = 0;
         if (QB == 6 && P == 3) {
@@ -512,16 +548,20 @@ ss_pk_kernel(DecodeArgs a) {
             __syncthreads();
             if (*flag == 0) {
                 converged = true;
-                break;
+                if (!LOCK) break;
+                done = true;
             }
         }
     }
     int ok = 1;
-    if (!converged && !conv_prev) {
+    // LOCK: every group takes the barriers of the final check; only groups
+    // with a frame that has not stopped at a codeword do its work
+    const bool check = !converged && !conv_prev && (!LOCK || live);
+    if (LOCK || check) {
         __syncthreads();
-        if (tid == 0) *flag = 0;
+        if (tid == 0 && check) *flag = 0;
         __syncthreads();
-        for (int p = 0; p < RP; ++p) {
+        for (int p = 0; p < RP && check; ++p) {
             int pa = 0, pb = 0;
             for (int j = 0; j < D; ++j) {
                 const auto r4 = __builtin_amdgcn_raw_buffer_load_b128(
@@ -536,8 +576,9 @@ ss_pk_kernel(DecodeArgs a) {
             if (pa | pb) atomicOr(flag, 1);
         }
         __syncthreads();
-        ok = (*flag == 0);
+        if (check) ok = (*flag == 0);
     }
+    if (LOCK && !live) return;
     // outputs, kU variables per thread and step (slot-table loads first)
     for (int n0 = tid; n0 < N; n0 += kU * kT) {
         uint32_t sl[kU];
@@ -563,6 +604,14 @@ ss_pk_kernel(DecodeArgs a) {
         a.iters_out[f] = iters;
         a.ok_out[f] = (uint8_t)ok;
     }
+}
+
+// One workgroup per frame.
+template <int D, int R, bool ONEBIT, bool FUSED, int T, int LANES, int QB>
+__global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(pk_waves_per_eu<D, R, T>())))
+ss_pk_kernel(DecodeArgs a) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    pk_frame<D, R, ONEBIT, FUSED, T, LANES, QB, false>(a, blockIdx.x, true, lds, 0u, a.c.pk_idx, threadIdx.x);
 }
 
 template <int D, int R, bool ONEBIT, bool FUSED, int T, int S, int QB>
@@ -600,6 +649,19 @@ hipError_t launch_one(const DecodeArgs &a, size_t lds, hipStream_t s) {
     X(8, 32, 1024, 1)       \
     X(21, 4, 768, 1)        \
     X(11, 12, 512, 2)
+
+// Index of a shape in LDPC_PK_SHAPES (compile time).
+constexpr int pk_shape_index(int d, int r, int t, int l) {
+    int i = 0;
+#define X(dd, rr, tt, ll)                             \
+    if (d == (dd) && r == (rr) && t == (tt) && l == (ll)) \
+        return i;                                     \
+    ++i;
+    LDPC_PK_SHAPES(X)
+#undef X
+    return -1;
+}
+#define PK_SHAPE_ID(d, r, t, l) pk_shape_index(d, r, t, l)
 
 void pk_shapes(int *out, int cap, int *count) {
     int i = 0;
@@ -643,6 +705,86 @@ hipError_t launch_ss_pk(const DecodeArgs &a, int D, int R, int T, int S, bool on
     LDPC_PK_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;
+}
+
+
+// Persistent multi-code decoding: one launch of 1024-thread workgroups, one
+// per CU, that take work items from a counter until none is left.  A work
+// item is 1024 / T frames of one job (T: the threads of the job's packed
+// shape), one frame per group of T threads in its own LDS region, the groups
+// sharing the workgroup's barriers (pk_frame with LOCK); items are numbered
+// job after job, so the jobs given first (the longest) are taken first.
+namespace {
+
+// One work item of shape (D, R, T, LANES): a separate function per shape,
+// so that each shape's code keeps its own register allocation (inlined into
+// one kernel, the register allocator spilled every shape's code to the
+// largest one's budget); the call happens once per work item.
+template <int D, int R, bool FUSED, int T, int LANES>
+__device__ __noinline__ void pk_item(const PersistJob *J, int item, uint8_t *lds, int *vote, int tid) {
+    const int g = tid / T;
+    const int f = (item - J->first) * (kPersistThreads / T) + g;
+    const DecodeArgs a = J->a;
+    pk_frame<D, R, false, FUSED, T, LANES, 6, true>(a, f, f < a.n_frames, lds, (uint32_t)g * J->region,
+                                                    J->recs + (size_t)g * J->rec_words, tid % T, vote, tid == 0);
+}
+
+template <bool FUSED>
+__global__ void __launch_bounds__(kPersistThreads) ss_pk_persist(PersistArgs pa) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    int *item_sh = reinterpret_cast<int *>(lds + pa.off_item);
+    int *vote = item_sh + 1;  // two words after the item word
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) *item_sh = atomicAdd(pa.counter, 1);
+        __syncthreads();
+        const int item = *item_sh;
+        __syncthreads();  // read by every thread before the next item overwrites it
+        if (item >= pa.nitems) break;
+        int k = 0;
+        while (k + 1 < pa.njobs && item >= pa.job[k + 1].first) ++k;
+        const PersistJob *J = &pa.job[k];
+        switch (J->shape) {
+#define X(d, r, t, l)                                                   \
+    case PK_SHAPE_ID(d, r, t, l):                                       \
+        if constexpr (kPersistThreads % (t) == 0) pk_item<d, r, FUSED, t, l>(J, item, lds, vote, tid); \
+        break;
+            LDPC_PK_SHAPES(X)
+#undef X
+        default:
+            break;
+        }
+    }
+}
+
+__global__ void zero_counter(int32_t *c) { *c = 0; }
+
+}  // namespace
+
+int pk_shape_id(int D, int R, int T, int S) {
+#define X(d, r, t, l) \
+    if (D == d && R == r && T == t && S == l) return PK_SHAPE_ID(d, r, t, l);
+    LDPC_PK_SHAPES(X)
+#undef X
+    return -1;
+}
+
+hipError_t launch_ss_pk_persist(const PersistArgs &pa, bool fused, size_t lds, int grid, hipStream_t s) {
+    auto kern = fused ? ss_pk_persist<true> : ss_pk_persist<false>;
+    {  // the records hold absolute LDS addresses: the kernel must have no static LDS
+        hipFuncAttributes fa{};
+        hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(kern));
+        if (e != hipSuccess) return e;
+        if (fa.sharedSizeBytes != 0) return hipErrorInvalidDeviceFunction;
+    }
+    hipLaunchKernelGGL(zero_counter, dim3(1), dim3(1), 0, s, pa.counter);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPersistThreads), lds, s, pa);
+    return hipGetLastError();
 }
 
 }  // namespace ldpc

@@ -39,7 +39,8 @@ EXPORTS = ("ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query",
            "ldpc_learn_classes", "ldpc_learn_workspace_size", "ldpc_learn_forward",
            "ldpc_learn_backward", "ldpc_learn_backward_weighted",
            # include/ldpc_multi.h
-           "ldpc_multi_workspace_size", "ldpc_decode_multi", "ldpc_autotune")
+           "ldpc_multi_workspace_size", "ldpc_decode_multi", "ldpc_autotune",
+           "ldpc_multi_persistent_workspace_size", "ldpc_decode_multi_persistent")
 LAYOUT_NAME = {v: k for k, v in LAYOUT.items()}
 KERNEL_NAME = {0: "generic_int", 1: "generic_f32", 2: "two_scan", 3: "reg1", 4: "packed",
                5: "f32_frames", 6: "two_scan_frames"}  # ldpc_kernel
@@ -134,6 +135,8 @@ def lib():
         L.ldpc_learn_backward_weighted.argtypes = [vp, i32, vp, i32, vp, i32, vp, sz, vp, vp, vp]
         L.ldpc_multi_workspace_size.argtypes = [ctypes.POINTER(Job), i32, ctypes.POINTER(sz)]
         L.ldpc_decode_multi.argtypes = [ctypes.POINTER(Job), i32, vp, sz, vp]
+        L.ldpc_multi_persistent_workspace_size.argtypes = [ctypes.POINTER(Job), i32, ctypes.POINTER(sz)]
+        L.ldpc_decode_multi_persistent.argtypes = [ctypes.POINTER(Job), i32, vp, sz, vp]
         L.ldpc_autotune.argtypes = [vp, i32, ctypes.POINTER(DecodeParams), ctypes.POINTER(i32),
                                     ctypes.POINTER(ctypes.c_float), ctypes.POINTER(i32)]
         for f in ("ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query",
@@ -142,7 +145,7 @@ def lib():
                   "ldpc_encode_batch", "ldpc_random_bits", "ldpc_channel_awgn", "ldpc_count_errors",
                   "ldpc_learn_classes", "ldpc_learn_workspace_size", "ldpc_learn_forward",
                   "ldpc_learn_backward", "ldpc_learn_backward_weighted", "ldpc_multi_workspace_size",
-                  "ldpc_decode_multi",
+                  "ldpc_decode_multi", "ldpc_multi_persistent_workspace_size", "ldpc_decode_multi_persistent",
                   "ldpc_autotune"):
             getattr(L, f).restype = ctypes.c_int
         L.ldpc_last_error.restype = ctypes.c_char_p
@@ -461,11 +464,14 @@ def _stream():
 
 class MultiBatch:
     """Several (code, llr, params) jobs decoded together by ldpc_decode_multi
-    (include/ldpc_multi.h).  Outputs and the shared workspace are allocated
-    once here; ``run()`` only enqueues, so it can be captured into a graph
-    (after one eager ``run()``, which creates the library's stream pool)."""
+    (include/ldpc_multi.h), or with ``persistent=True`` by
+    ldpc_decode_multi_persistent (one launch).  Outputs and the shared
+    workspace are allocated once here; ``run()`` only enqueues, so it can be
+    captured into a graph (after one eager ``run()``, which creates the
+    library's stream pool)."""
 
-    def __init__(self, items, with_llr: bool = False):
+    def __init__(self, items, with_llr: bool = False, persistent: bool = False):
+        self.persistent = persistent
         self.items = list(items)  # (Code, llr device tensor, DecodeParams); kept alive here
         n = len(self.items)
         self._jobs = (Job * max(n, 1))()
@@ -481,7 +487,8 @@ class MultiBatch:
                                 None if out["llr"] is None else out["llr"].data_ptr(),
                                 out["iters"].data_ptr(), out["ok"].data_ptr())
         b = ctypes.c_size_t()
-        _check(lib().ldpc_multi_workspace_size(self._jobs, n, ctypes.byref(b)))
+        size_fn = lib().ldpc_multi_persistent_workspace_size if persistent else lib().ldpc_multi_workspace_size
+        _check(size_fn(self._jobs, n, ctypes.byref(b)))
         self.workspace_bytes = int(b.value)
         dev = self.items[0][1].device if n else "cuda"
         self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=dev) \
@@ -489,8 +496,9 @@ class MultiBatch:
 
     def run(self, stream=None) -> None:
         s = stream if stream is not None else torch.cuda.current_stream()
-        _check(lib().ldpc_decode_multi(self._jobs, len(self.items), _ptr(self.workspace),
-                                       self.workspace_bytes, ctypes.c_void_p(s.cuda_stream)))
+        fn = lib().ldpc_decode_multi_persistent if self.persistent else lib().ldpc_decode_multi
+        _check(fn(self._jobs, len(self.items), _ptr(self.workspace), self.workspace_bytes,
+                  ctypes.c_void_p(s.cuda_stream)))
 
 
 def random_bits(n_frames: int, n_bits: int, key=(0x5EED, 0), stream_id: int = 0,

@@ -10,6 +10,8 @@ Timed, each on inputs already in device memory:
   sequential  the four ldpc_decode_batch calls one after another on one stream
   multi       one ldpc_decode_multi call (jobs forked onto library streams)
   graph       a HIP graph holding that call, replayed
+  persistent  one ldpc_decode_multi_persistent call (a single launch of
+              1024-thread workgroups taking work items from a counter)
 
     python -m paper_cs_0609090_amd.mixed --reps 20 [--autotune] [--no-early-stop]
 """
@@ -90,11 +92,17 @@ def measure(reps: int = 20, warmup: int = 3, scale: float = 1.0, early_stop: boo
     t_multi = _time(mb.run, reps, warmup)
     same = all(torch.equal(a, o["iters"]) and torch.equal(h, o["hard"])
                for a, h, o in zip(iters_seq, hard_seq, mb.outputs))
+    mp = ldpc.MultiBatch(mb.items, with_llr=False, persistent=True)
+    t_pers = _time(mp.run, reps, warmup)
+    same_p = all(torch.equal(a, o["iters"]) and torch.equal(h, o["hard"])
+                 for a, h, o in zip(iters_seq, hard_seq, mp.outputs))
     res = {"workload": "mixed: " + ", ".join(f"{int(x.shape[0])}x{n}" for (n, _, _), (_, x, _) in
                                               zip(MIX, mb.items)),
            "coded_bits": bits, "early_stop": early_stop, "ms_sequential": t_seq, "ms_multi": t_multi,
            "gbps_sequential": bits / t_seq / 1e6, "gbps_multi": bits / t_multi / 1e6,
-           "multi_equals_sequential": bool(same), "tuned": tuned}
+           "multi_equals_sequential": bool(same), "tuned": tuned,
+           "ms_persistent": t_pers, "gbps_persistent": bits / t_pers / 1e6,
+           "persistent_equals_sequential": bool(same_p)}
     if graph:
         g = torch.cuda.CUDAGraph()
         s = torch.cuda.Stream()

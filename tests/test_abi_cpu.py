@@ -600,3 +600,26 @@ def test_noalloc_entry_point_checks(L):
                                          None) == L.LDPC_EINVAL
     assert lib.ldpc_decode_batch_noalloc(None, 4, None, ctypes.byref(hbm), None, None, None, None,
                                          None) == L.LDPC_EINVAL
+
+
+def test_persistent_multi_host_checks(L):
+    """ldpc_multi_persistent_workspace_size is the 256-byte counter for valid
+    jobs and fails like ldpc_multi_workspace_size on invalid ones; a call
+    without a workspace is refused before anything else."""
+    codes = [W.code_c0_peg1008(), W.code_c1_qc7493(), W.code_ira16200()]
+    hs = [_host_code(L, c) for c in codes]
+    p = L.make_params(msg="int8")
+    jobs = (L.Job * 3)()
+    for k, h in enumerate(hs):
+        jobs[k] = _job(L, h, 100, p)
+    got = ctypes.c_size_t()
+    assert L.lib().ldpc_multi_persistent_workspace_size(jobs, 3, ctypes.byref(got)) == L.LDPC_OK
+    assert got.value == 256
+    bad = L.make_params(msg="int8", max_iter=-1)
+    jobs[1] = _job(L, hs[1], 100, bad)
+    assert L.lib().ldpc_multi_persistent_workspace_size(jobs, 3, ctypes.byref(got)) == L.LDPC_EINVAL
+    assert b"job 1" in L.lib().ldpc_last_error()
+    jobs[1] = _job(L, hs[1], 100, p)
+    assert L.lib().ldpc_decode_multi_persistent(jobs, 3, None, 0, None) == L.LDPC_EINVAL
+    for h in hs:
+        L.lib().ldpc_code_destroy(h)

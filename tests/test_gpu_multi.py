@@ -47,9 +47,10 @@ def _np(out):
     return {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
 
 
-def _check_jobs(torch, L, orc, spec, max_iter, early_stop, samples, with_llr=True):
-    """spec: (code, frames, msg, sched, layout).  Runs the mixed call, the
-    separate calls and the oracle on sampled frames."""
+def _check_jobs(torch, L, orc, spec, max_iter, early_stop, samples, with_llr=True, persistent=False):
+    """spec: (code, frames, msg, sched, layout).  Runs the mixed call (or the
+    persistent one-launch form), the separate calls and the oracle on
+    sampled frames."""
     torch.cuda.synchronize()
     items, hosts, gcs = [], [], []
     for k, (code, F, msg, sched, layout) in enumerate(spec):
@@ -59,7 +60,8 @@ def _check_jobs(torch, L, orc, spec, max_iter, early_stop, samples, with_llr=Tru
         items.append((gc, _dev(torch, x), p))
         hosts.append(x)
         gcs.append(gc)
-    mb = L.MultiBatch(items, with_llr=with_llr)
+    mb = L.MultiBatch(items, with_llr=with_llr, persistent=persistent)
+    print(f"[multi] persistent={persistent} jobs={[(c.name, F, m) for c, F, m, _, _ in spec]}", flush=True)
     mb.run()
     torch.cuda.synchronize()
     got = [_np(o) for o in mb.outputs]
@@ -187,4 +189,90 @@ def test_single_and_empty_calls(torch_dev, L, orc):
     mb0 = L.MultiBatch([])
     mb0.run()
     torch.cuda.synchronize()
+    gc.close()
+
+
+# ---------------------------------------------------------------------------
+# One persistent launch (ldpc_decode_multi_persistent): workgroups of 1024
+# threads hold 1024 / T frames of one job (PEG code: 4 frames of 256 threads;
+# QC code: 2 of 512; IRA codes: 1 of 1024) and take work items from a counter.
+@pytest.mark.parametrize("early_stop,with_llr", [(True, False), (True, True), (False, True)])
+def test_persistent_mixed_codes(torch_dev, L, orc, early_stop, with_llr):
+    """Frame counts that leave groups of the last work item idle (301 = 4 x
+    75 + 1 PEG frames, 71 QC frames), a job without frames, and results equal
+    to separate calls and to the oracle; with posteriors or without early stop
+    every job takes the separate syndrome pass, else the fused one."""
+    spec = [(W.code_c0_peg1008(), 301, "int8", "single_scan", "auto"),
+            (W.code_c1_qc7493(), 71, "int8", "single_scan", "auto"),
+            (W.code_c0_peg1008(), 0, "int8", "single_scan", "auto"),
+            (W.code_ira16200(), 21, "int8", "single_scan", "reg"),
+            (W.code_c2_ira64800(), 3, "int8", "single_scan", "auto")]
+    got = _check_jobs(torch_dev, L, orc, spec, max_iter=30, early_stop=early_stop, samples=5, with_llr=with_llr,
+                      persistent=True)
+    if early_stop:
+        assert len(set(got[0]["iters"].tolist())) > 3
+
+
+def test_persistent_full_workload(torch_dev, L, orc):
+    """The full mixed workload in one persistent launch: every frame equals
+    its separate call, sampled frames equal the oracle."""
+    spec = [(W.code_c0_peg1008(), 8192, "int8", "single_scan", "auto"),
+            (W.code_c1_qc7493(), 2048, "int8", "single_scan", "auto"),
+            (W.code_ira16200(), 256, "int8", "single_scan", "auto"),
+            (W.code_c2_ira64800(), 128, "int8", "single_scan", "auto")]
+    _check_jobs(torch_dev, L, orc, spec, max_iter=50, early_stop=True, samples=3, with_llr=False, persistent=True)
+
+
+def test_persistent_graph_replays(torch_dev, L):
+    """The persistent launch (counter reset kernel + decode kernel) captured
+    into a graph: every replay equals the eager call."""
+    torch = torch_dev
+    spec = [(W.code_c0_peg1008(), 257), (W.code_ira16200(), 9), (W.code_c1_qc7493(), 33)]
+    items, gcs = [], []
+    for k, (code, F) in enumerate(spec):
+        gc = L.Code.from_parity_check(code)
+        items.append((gc, _dev(torch, _host_llr(code, F, "int8", 400 + k)),
+                      L.make_params(max_iter=25, early_stop=True, msg="int8")))
+        gcs.append(gc)
+    mb = L.MultiBatch(items, with_llr=False, persistent=True)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        mb.run()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    ref = [{k: (v.clone() if v is not None else None) for k, v in o.items()} for o in mb.outputs]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        mb.run()
+    for rep in range(3):
+        for o in mb.outputs:
+            for v in o.values():
+                if v is not None:
+                    v.zero_()
+        torch.randn(1 << 20, device="cuda").sum().item()
+        g.replay()
+        torch.cuda.synchronize()
+        for k, (o, r) in enumerate(zip(mb.outputs, ref)):
+            for key in o:
+                if o[key] is not None:
+                    assert torch.equal(o[key], r[key]), f"replay {rep} job {k} {key}"
+    for gc in gcs:
+        gc.close()
+
+
+def test_persistent_refuses_other_kernels(torch_dev, L):
+    """Jobs that do not run the 6-bit int8 packed kernel are refused before
+    anything is launched."""
+    torch = torch_dev
+    code = W.code_c0_peg1008()
+    gc = L.Code.from_parity_check(code)
+    x8 = torch.zeros((8, code.N), dtype=torch.int8, device="cuda")
+    xf = torch.zeros((8, code.N), dtype=torch.float32, device="cuda")
+    for x, kw in ((xf, dict(msg="fp32")), (x8, dict(msg="1bit")), (x8, dict(msg="int8", layout="hbm")),
+                  (x8, dict(msg="int8", msg_bits=7)), (x8, dict(msg="int8", sched="two_scan"))):
+        mb = L.MultiBatch([(gc, x, L.make_params(**kw))], persistent=True)
+        with pytest.raises(L.LdpcError) as ei:
+            mb.run()
+        assert ei.value.status == L.LDPC_EUNSUPPORTED, kw
     gc.close()
