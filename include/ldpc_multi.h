@@ -73,13 +73,52 @@ ldpc_status ldpc_decode_multi_persistent(const ldpc_job *jobs, int32_t n_jobs, v
  * memory for the trial, and make AUTO use the fastest one for this (msg,
  * sched, msg_bits) on this handle from now on.  A later AUTO call whose
  * parameters the tuned layout cannot run (another frame count's workspace
- * form, say) falls back to the built-in policy.  Synchronises the device.
+ * form, say) falls back to the built-in policy.
+ *
+ * When REG runs the packed two-rows-per-lane kernel (ldpc_code_info's
+ * pk_slots > 0), REG is timed with each packed shape worth trying: per
+ * threads-per-workgroup and lanes-per-row pair (which set the frames a CU
+ * holds), the instantiated shape covering the code with the fewest slots and
+ * rows, the handle's own shape first.  If REG wins, its fastest shape becomes
+ * the handle's (ldpc_code_query reports it), else the handle keeps its own.
+ * The packed shape belongs to the handle: it serves every later call that
+ * runs the packed kernel, whatever its parameters (results do not depend on
+ * it; the built-in AUTO policy and ldpc_decode_multi_persistent, which needs
+ * a shape of 256, 512 or 1024 threads, read it).  Changing it replaces the
+ * handle's device arrays, so no other call may use the handle while
+ * ldpc_autotune runs.  Synchronises the device.  On an error the handle
+ * keeps a valid packed shape.
  *  best_layout  out: LDPC_LAYOUT_* chosen.
  *  best_ms      out: its time per call in milliseconds (may be NULL).
- *  n_tried      out: layouts timed (may be NULL).
+ *  n_tried      out: configurations timed, (layout, packed shape) pairs
+ *               (may be NULL).
  */
 ldpc_status ldpc_autotune(ldpc_code *code, int32_t n_frames, const ldpc_decode_params *p, int32_t *best_layout,
                           float *best_ms, int32_t *n_tried);
+
+/*
+ * The packed shapes ldpc_autotune times on this code, the handle's current
+ * one first: (slots per lane, rows per thread, threads per workgroup)
+ * triples, the fields ldpc_code_info reports as pk_slots,
+ * pk_rows_per_thread and pk_threads (a shape with fewer slots than the
+ * longest row splits every row over a lane pair).  None (count 0) when the
+ * code has no packed shape.  Works on host-only handles.
+ *  shapes  out: [cap][3]; the first min(cap, count) triples are written.
+ *  count   out: triples in all.
+ */
+ldpc_status ldpc_code_packed_shapes(const ldpc_code *code, int32_t *shapes, int32_t cap, int32_t *count);
+
+/*
+ * Make one of ldpc_code_packed_shapes() the handle's packed shape (to install
+ * a shape ldpc_autotune chose earlier without timing again, say).  Rebuilds
+ * the per-edge records on the host and replaces the handle's device copies
+ * (allocates; synchronous).  Decoding results do not depend on the shape.  No
+ * other call may use the handle meanwhile, and work queued earlier with it
+ * must have finished.  LDPC_EUNSUPPORTED for a triple not in the list,
+ * LDPC_EINVAL for a host-only handle, LDPC_ENOMEM / LDPC_EDEVICE (the handle
+ * keeps its shape).
+ */
+ldpc_status ldpc_code_set_packed_shape(ldpc_code *code, int32_t slots, int32_t rows_per_thread, int32_t threads);
 
 #ifdef __cplusplus
 }

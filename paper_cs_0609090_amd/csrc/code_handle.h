@@ -2,6 +2,7 @@
 // shared by the decoder runtime and the channel-simulation entry points.
 #pragma once
 
+#include <array>
 #include <cstdint>
 #include <mutex>
 #include <string>
@@ -103,6 +104,16 @@ struct PersistJob;
 ldpc_status persist_job(const ldpc_code *c, int32_t n_frames, const void *llr_in, const ldpc_decode_params *p,
                         uint8_t *hard_out, float *llr_out, int32_t *iters_out, uint8_t *syndrome_ok,
                         PersistJob *out);
+
+// Packed shapes worth timing on this code (the handle's own first): per
+// threads-per-workgroup and lanes-per-row pair, the instantiated shape that
+// covers the code with the fewest slots and rows.  Empty without a packed shape.
+std::vector<std::array<int, 4>> pk_candidates(const ldpc_code *c);
+// Makes (D, R, T, S) the handle's packed shape: rebuilds its records and slot
+// placement and replaces the device copies.  On failure the handle keeps its
+// shape and arrays.  No call may use the handle meanwhile, and no kernel
+// launched with the old arrays may still be running.
+ldpc_status pk_install(ldpc_code *c, int D, int R, int T, int S);
 
 // error state of the calling thread (ldpc_last_error), set by every entry point
 ldpc_status set_error(ldpc_status st, const std::string &msg);

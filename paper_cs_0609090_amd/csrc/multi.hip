@@ -305,6 +305,12 @@ ldpc_status ldpc_autotune(ldpc_code *code, int32_t n_frames, const ldpc_decode_p
 
     ldpc::DeviceGuard g(code->device);
     if (!g.ok) return ldpc::set_error(LDPC_EDEVICE, "hipSetDevice failed");
+    // REG on a handle with a packed shape runs the packed kernel: its other
+    // shapes (threads per workgroup, hence frames per CU) are timed as well
+    const std::vector<std::array<int, 4>> shapes =
+        feasible[0] && code->pkD > 0 ? ldpc::pk_candidates(code) : std::vector<std::array<int, 4>>();
+    const std::array<int, 4> orig = {code->pkD, code->pkR, code->pkT, code->pkS};
+    std::array<int, 4> best_shape = orig;
     const bool fp32 = p->msg == LDPC_MSG_FP32;
     const size_t cnt = (size_t)n_frames * (size_t)code->N;
     void *llr = nullptr, *ws = nullptr;
@@ -313,7 +319,9 @@ ldpc_status ldpc_autotune(ldpc_code *code, int32_t n_frames, const ldpc_decode_p
     hipStream_t s = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     ldpc::reset_alloc_count();
-    hipError_t e = ldpc::dev_malloc(&llr, cnt * (fp32 ? 4 : 1));
+    // a shape change frees arrays that work queued earlier may still read
+    hipError_t e = shapes.size() > 1 ? hipDeviceSynchronize() : hipSuccess;
+    if (e == hipSuccess) e = ldpc::dev_malloc(&llr, cnt * (fp32 ? 4 : 1));
     if (e == hipSuccess) e = ldpc::dev_malloc(reinterpret_cast<void **>(&hard), cnt);
     if (e == hipSuccess) e = ldpc::dev_malloc(reinterpret_cast<void **>(&iters), 4 * (size_t)n_frames);
     if (e == hipSuccess) e = ldpc::dev_malloc(reinterpret_cast<void **>(&ok), (size_t)n_frames);
@@ -331,33 +339,61 @@ ldpc_status ldpc_autotune(ldpc_code *code, int32_t n_frames, const ldpc_decode_p
                            (int64_t)cnt, fp32 ? 1 : 0);
         e = hipGetLastError();
     }
+    // makes a packed shape the handle's (nothing to do when it already is)
+    auto install = [&](const std::array<int, 4> &sh) -> ldpc_status {
+        if (sh[0] == code->pkD && sh[1] == code->pkR && sh[2] == code->pkT && sh[3] == code->pkS) return LDPC_OK;
+        if (s && (e = hipStreamSynchronize(s)) != hipSuccess) return LDPC_EDEVICE;
+        return ldpc::pk_install(code, sh[0], sh[1], sh[2], sh[3]);
+    };
     for (int i = 0; i < 5 && e == hipSuccess && st == LDPC_OK; ++i) {
         if (!feasible[i]) continue;
-        float t_min = 0.0f;
-        for (int rep = 0; rep < 4 && st == LDPC_OK && e == hipSuccess; ++rep) {
-            e = hipEventRecord(e0, s);
-            if (e != hipSuccess) break;
-            st = ldpc::decode_job(code, n_frames, llr, &q[i], hard, nullptr, iters, ok, ws, ws_max, s, true);
-            if (st != LDPC_OK) {
-                msg = ldpc_last_error();
-                break;
+        const size_t nsh = kCand[i] == LDPC_LAYOUT_REG && !shapes.empty() ? shapes.size() : 1;
+        for (size_t k = 0; k < nsh && e == hipSuccess && st == LDPC_OK; ++k) {
+            if (nsh > 1) {
+                st = install(shapes[k]);
+                if (st != LDPC_OK) {
+                    msg = e != hipSuccess ? std::string("autotune: ") + hipGetErrorString(e) : ldpc_last_error();
+                    break;
+                }
             }
-            e = hipEventRecord(e1, s);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (rep > 0 && (rep == 1 || ms < t_min)) t_min = ms;  // rep 0 is the warm-up
-        }
-        if (st != LDPC_OK || e != hipSuccess) break;
-        ++tried;
-        if (best == 0 || t_min < best_t) {
-            best = kCand[i];
-            best_t = t_min;
+            float t_min = 0.0f;
+            for (int rep = 0; rep < 4 && st == LDPC_OK && e == hipSuccess; ++rep) {
+                e = hipEventRecord(e0, s);
+                if (e != hipSuccess) break;
+                st = ldpc::decode_job(code, n_frames, llr, &q[i], hard, nullptr, iters, ok, ws, ws_max, s, true);
+                if (st != LDPC_OK) {
+                    msg = ldpc_last_error();
+                    break;
+                }
+                e = hipEventRecord(e1, s);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (rep > 0 && (rep == 1 || ms < t_min)) t_min = ms;  // rep 0 is the warm-up
+            }
+            if (st != LDPC_OK || e != hipSuccess) break;
+            ++tried;
+            if (best == 0 || t_min < best_t) {
+                best = kCand[i];
+                best_t = t_min;
+                if (nsh > 1) best_shape = shapes[k];
+            }
         }
     }
     if (e != hipSuccess && st == LDPC_OK) {
         st = LDPC_EDEVICE;
         msg = std::string("autotune: ") + hipGetErrorString(e);
+    }
+    // the winning packed shape when REG won, else the handle's own
+    if (shapes.size() > 1) {
+        const hipError_t e_keep = e;
+        e = hipSuccess;
+        const ldpc_status sti = install(st == LDPC_OK && best == LDPC_LAYOUT_REG ? best_shape : orig);
+        if (sti != LDPC_OK && st == LDPC_OK) {
+            st = sti;
+            msg = e != hipSuccess ? std::string("autotune: ") + hipGetErrorString(e) : ldpc_last_error();
+        }
+        if (e == hipSuccess) e = e_keep;
     }
     if (s) (void)hipStreamSynchronize(s);
     if (e0) (void)hipEventDestroy(e0);
@@ -375,6 +411,33 @@ ldpc_status ldpc_autotune(ldpc_code *code, int32_t n_frames, const ldpc_decode_p
     if (n_tried) *n_tried = tried;
     ldpc::clear_error();
     return LDPC_OK;
+}
+
+ldpc_status ldpc_code_packed_shapes(const ldpc_code *code, int32_t *shapes, int32_t cap, int32_t *count) {
+    if (!code || !count || cap < 0 || (cap > 0 && !shapes)) return ldpc::set_error(LDPC_EINVAL, "NULL argument");
+    const std::vector<std::array<int, 4>> c = ldpc::pk_candidates(code);
+    for (size_t i = 0; i < c.size() && (int64_t)i < cap; ++i) {
+        shapes[3 * i] = c[i][0];
+        shapes[3 * i + 1] = c[i][1];
+        shapes[3 * i + 2] = c[i][2];
+    }
+    *count = (int32_t)c.size();
+    ldpc::clear_error();
+    return LDPC_OK;
+}
+
+ldpc_status ldpc_code_set_packed_shape(ldpc_code *code, int32_t slots, int32_t rows_per_thread, int32_t threads) {
+    if (!code) return ldpc::set_error(LDPC_EINVAL, "NULL argument");
+    if (code->device < 0) return ldpc::set_error(LDPC_EINVAL, "host-only handle (device < 0)");
+    for (const std::array<int, 4> &sh : ldpc::pk_candidates(code))
+        if (sh[0] == slots && sh[1] == rows_per_thread && sh[2] == threads) {
+            ldpc::reset_alloc_count();
+            const ldpc_status st = ldpc::pk_install(code, sh[0], sh[1], sh[2], sh[3]);
+            if (st != LDPC_OK) return ldpc::set_error(st, ldpc_last_error());
+            ldpc::clear_error();
+            return LDPC_OK;
+        }
+    return ldpc::set_error(LDPC_EUNSUPPORTED, "not one of ldpc_code_packed_shapes() for this code");
 }
 
 }  // extern "C"

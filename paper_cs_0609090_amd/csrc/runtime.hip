@@ -1,6 +1,7 @@
 // C ABI of the decoder library (declared in include/ldpc.h): code handles,
 // argument validation, the per-call layout plan and kernel dispatch.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -419,6 +420,161 @@ hipError_t launch_check_input(const void *llr, int64_t count, int msg, int qmax,
 }
 }  // namespace ldpc
 
+// Host arrays of the packed kernel for shape (Dk slots per lane, R rows per
+// thread, T threads, S lanes per row): the slot placement and the per-edge
+// records {zold_a, zold_b, acc_a, acc_b} of slot j of rows a = p*T/S + t/S,
+// b = (p + R/2)*T/S + t/S (lane t holds the row slots (t%S)*D + j): LDS byte
+// address of the saturated posterior and (LDS byte address of the
+// accumulator word << 5) | field shift; the set for int16 Z_old (7-8 bit
+// messages), and one set per LDS region of the persistent launch.
+struct PkHost {
+    std::vector<uint32_t> idx, idx16, grp, slot;
+    int groups = 0;
+    uint32_t region = 0;
+};
+
+static void pk_build_host(const ldpc_code *c, const int32_t *row_ptr, const int32_t *col_idx, int Dk, int R, int T,
+                          int S, int lds_dev, PkHost *out) {
+    const int M = c->M, N = c->N;
+    std::vector<uint32_t> &pk_idx = out->idx, &pk_idx16 = out->idx16, &pk_grp = out->grp, &pk_slot = out->slot;
+    const int RP = R / 2, Pk = c->regP;
+    const int fbits = Pk == 1 ? 32 : (Pk == 2 ? 16 : 10);
+    const uint32_t nwords = (uint32_t)c->dummy / (uint32_t)Pk + 1;
+    pk_slot = pk_slot_assignment(M, N, row_ptr, col_idx, Dk, R, T, S, Pk,
+                                 (uint32_t)align_up((size_t)c->dummy + 1, 16));
+    // zb: bytes per stored Z_old (1; 2 for the int16 Z_old of 8-bit messages,
+    // whose accumulator words then start after the wider Z_old array)
+    auto build = [&](std::vector<uint32_t> &rec, uint32_t zb) {
+        const uint32_t zacc_off = (uint32_t)align_up(((size_t)c->dummy + 1) * zb, 16);
+        auto acc_of_slot = [&](uint32_t sl) -> uint32_t {
+            const uint32_t w = sl / (uint32_t)Pk, fld = sl % (uint32_t)Pk;
+            return ((zacc_off + w * 4u) << 5) | (fld * (uint32_t)fbits);
+        };
+        rec.assign((size_t)RP * Dk * T * 4, 0u);
+        for (int pp = 0; pp < RP; ++pp)
+            for (int j = 0; j < Dk; ++j)
+                for (int t = 0; t < T; ++t)
+                    for (int h = 0; h < 2; ++h) {
+                        const int m = (pp + h * RP) * (T / S) + t / S, jr = (t % S) * Dk + j;
+                        uint32_t *r = &rec[(((size_t)pp * Dk + j) * T + t) * 4];
+                        if (m < M && jr < row_ptr[m + 1] - row_ptr[m]) {
+                            const uint32_t sl = pk_slot[col_idx[row_ptr[m] + jr]];
+                            r[h] = sl * zb;
+                            r[2 + h] = acc_of_slot(sl);
+                        } else {  // padding: shared Z_old, a private accumulator word per lane
+                            r[h] = (uint32_t)c->dummy * zb;
+                            r[2 + h] = (zacc_off + (nwords + (uint32_t)(t & 63)) * 4u) << 5;
+                        }
+                    }
+    };
+    build(pk_idx, 1);
+    // 7-8 bit messages need accumulator fields of 16 bits or more
+    if (Pk <= 2) build(pk_idx16, 2);
+    // the persistent launch: 1024 / T frames per workgroup, each in its
+    // own LDS region of the 6-bit plan's size; one record set per region
+    // (the records hold absolute LDS addresses)
+    const size_t region = align_up((size_t)c->dummy + 1, 16) +
+                          align_up(4 * ((size_t)c->dummy / Pk + 1 + 64), 16) + 16;
+    const int G = ldpc::kPersistThreads % T == 0 ? ldpc::kPersistThreads / T : 0;
+    if (G >= 1 && (size_t)G * region + 16 <= (size_t)lds_dev) {
+        out->groups = G;
+        out->region = (uint32_t)region;
+        if (G > 1) {
+            std::vector<uint32_t> one;
+            build(one, 1);
+            pk_grp.reserve(one.size() * G);
+            for (int g = 0; g < G; ++g) {
+                const uint32_t off = (uint32_t)(g * region);
+                for (size_t i = 0; i < one.size(); i += 4) {
+                    pk_grp.push_back(one[i] + off);
+                    pk_grp.push_back(one[i + 1] + off);
+                    pk_grp.push_back(one[i + 2] + (off << 5));
+                    pk_grp.push_back(one[i + 3] + (off << 5));
+                }
+            }
+        }
+    }
+}
+
+// Device copies of a packed shape's host arrays, replacing the handle's
+// previous ones (freed) on success; on failure the handle keeps its arrays
+// and whatever was allocated here is freed.  The device is current.
+static ldpc_status pk_upload(ldpc_code *c, const PkHost &h) {
+    uint32_t *di = nullptr, *di16 = nullptr, *dg = nullptr, *ds = nullptr;
+    hipError_t e = ldpc::dev_malloc((void **)&di, h.idx.size() * sizeof(uint32_t));
+    if (e == hipSuccess) e = ldpc::dev_malloc((void **)&ds, h.slot.size() * sizeof(uint32_t));
+    if (e == hipSuccess && !h.idx16.empty()) e = ldpc::dev_malloc((void **)&di16, h.idx16.size() * sizeof(uint32_t));
+    if (e == hipSuccess && !h.grp.empty()) e = ldpc::dev_malloc((void **)&dg, h.grp.size() * sizeof(uint32_t));
+    const bool allocated = e == hipSuccess;
+    if (allocated) e = hipMemcpy(di, h.idx.data(), h.idx.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ds, h.slot.data(), h.slot.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess && di16)
+        e = hipMemcpy(di16, h.idx16.data(), h.idx16.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess && dg) e = hipMemcpy(dg, h.grp.data(), h.grp.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        for (uint32_t *q : {di, di16, dg, ds})
+            if (q) (void)hipFree(q);
+        (void)hipGetLastError();
+        return allocated ? fail(LDPC_EDEVICE, "copy of the packed layout to the device failed")
+                         : fail(LDPC_ENOMEM, "device allocation failed");
+    }
+    for (uint32_t *q : {c->d_pk_idx, c->d_pk_idx16, c->d_pk_grp, c->d_pk_slot})
+        if (q) (void)hipFree(q);
+    c->d_pk_idx = di;
+    c->d_pk_idx16 = di16;
+    c->d_pk_grp = dg;
+    c->d_pk_slot = ds;
+    c->pkGroups = h.groups;
+    c->pkRegion = h.region;
+    return LDPC_OK;
+}
+
+namespace ldpc {
+
+std::vector<std::array<int, 4>> pk_candidates(const ldpc_code *c) {
+    std::vector<std::array<int, 4>> out;
+    if (c->pkD <= 0) return out;
+    out.push_back({c->pkD, c->pkR, c->pkT, c->pkS});
+    int pks[4 * 64], n = 0;
+    pk_shapes(pks, 64, &n);
+    n = std::min(n, 64);
+    // per (threads, lanes per row): the covering shape with the fewest slots,
+    // then the fewest rows per thread (more of either is padding only); rows
+    // padded to more than twice max(D, 8) slots are not tried, nor lane pairs
+    // for rows that fit one lane
+    for (int i = 0; i < n; ++i) {
+        const int d = pks[4 * i], r = pks[4 * i + 1], t = pks[4 * i + 2], l = pks[4 * i + 3];
+        if (d * l < c->D || (int64_t)r * (t / l) < c->M || d * l > 2 * std::max(c->D, 8)) continue;
+        if (l > 1 && d >= c->D) continue;
+        bool best = true;
+        for (int k = 0; k < n && best; ++k) {
+            const int d2 = pks[4 * k], r2 = pks[4 * k + 1], t2 = pks[4 * k + 2], l2 = pks[4 * k + 3];
+            if (k == i || t2 != t || l2 != l || d2 * l2 < c->D || (int64_t)r2 * (t2 / l2) < c->M) continue;
+            if (d2 < d || (d2 == d && r2 < r)) best = false;
+        }
+        if (!best || (d == c->pkD && r == c->pkR && t == c->pkT && l == c->pkS)) continue;
+        out.push_back({d, r, t, l});
+    }
+    return out;
+}
+
+ldpc_status pk_install(ldpc_code *c, int D, int R, int T, int S) {
+    if (c->device < 0) return fail(LDPC_EINVAL, "host-only handle");
+    PkHost h;
+    pk_build_host(c, c->h_row_ptr.data(), c->h_col_idx.data(), D, R, T, S, c->lds_limit, &h);
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(LDPC_EDEVICE, "hipSetDevice failed");
+    const ldpc_status st = pk_upload(c, h);
+    if (st != LDPC_OK) return st;
+    c->pkD = D;
+    c->pkR = R;
+    c->pkT = T;
+    c->pkS = S;
+    return LDPC_OK;
+}
+
+}  // namespace ldpc
+
 extern "C" {
 
 const char *ldpc_last_error(void) { return g_err.c_str(); }
@@ -578,69 +734,11 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
             for (int j = 0; j < row_ptr[m + 1] - row_ptr[m]; ++j)
                 ell_reg[(size_t)j * Mr + m] = (uint32_t)col_idx[row_ptr[m] + j];
     }
-    std::vector<uint32_t> pk_idx, pk_idx16, pk_grp, pk_slot;
+    PkHost pkh;
     if (c->pkD > 0) {
-        // record {zold_a, zold_b, acc_a, acc_b} of slot j of rows a = p*T/S + t/S,
-        // b = (p + R/2)*T/S + t/S (T threads, S lanes per row; lane t holds the
-        // row slots (t%S)*D + j): LDS byte address of the saturated posterior
-        // and (LDS byte address of the accumulator word << 5) | field shift
-        const int T = c->pkT, RP = c->pkR / 2, Dk = c->pkD, Pk = c->regP, S = c->pkS;
-        const int fbits = Pk == 1 ? 32 : (Pk == 2 ? 16 : 10);
-        const uint32_t nwords = (uint32_t)c->dummy / (uint32_t)Pk + 1;
-        pk_slot = pk_slot_assignment(M, N, row_ptr, col_idx, Dk, c->pkR, T, S, Pk,
-                                     (uint32_t)align_up((size_t)c->dummy + 1, 16));
-        // zb: bytes per stored Z_old (1; 2 for the int16 Z_old of 8-bit messages,
-        // whose accumulator words then start after the wider Z_old array)
-        auto build = [&](std::vector<uint32_t> &rec, uint32_t zb) {
-            const uint32_t zacc_off = (uint32_t)align_up(((size_t)c->dummy + 1) * zb, 16);
-            auto acc_of_slot = [&](uint32_t sl) -> uint32_t {
-                const uint32_t w = sl / (uint32_t)Pk, fld = sl % (uint32_t)Pk;
-                return ((zacc_off + w * 4u) << 5) | (fld * (uint32_t)fbits);
-            };
-            rec.assign((size_t)RP * Dk * T * 4, 0u);
-            for (int pp = 0; pp < RP; ++pp)
-                for (int j = 0; j < Dk; ++j)
-                    for (int t = 0; t < T; ++t)
-                        for (int h = 0; h < 2; ++h) {
-                            const int m = (pp + h * RP) * (T / S) + t / S, jr = (t % S) * Dk + j;
-                            uint32_t *r = &rec[(((size_t)pp * Dk + j) * T + t) * 4];
-                            if (m < M && jr < row_ptr[m + 1] - row_ptr[m]) {
-                                const uint32_t sl = pk_slot[col_idx[row_ptr[m] + jr]];
-                                r[h] = sl * zb;
-                                r[2 + h] = acc_of_slot(sl);
-                            } else {  // padding: shared Z_old, a private accumulator word per lane
-                                r[h] = (uint32_t)c->dummy * zb;
-                                r[2 + h] = (zacc_off + (nwords + (uint32_t)(t & 63)) * 4u) << 5;
-                            }
-                        }
-        };
-        build(pk_idx, 1);
-        // 7-8 bit messages need accumulator fields of 16 bits or more
-        if (Pk <= 2) build(pk_idx16, 2);
-        // the persistent launch: 1024 / T frames per workgroup, each in its
-        // own LDS region of the 6-bit plan's size; one record set per region
-        // (the records hold absolute LDS addresses)
-        const size_t region = align_up((size_t)c->dummy + 1, 16) +
-                              align_up(4 * ((size_t)c->dummy / Pk + 1 + 64), 16) + 16;
-        const int G = ldpc::kPersistThreads % T == 0 ? ldpc::kPersistThreads / T : 0;
-        if (G >= 1 && (size_t)G * region + 16 <= (size_t)lds_dev) {
-            c->pkGroups = G;
-            c->pkRegion = (uint32_t)region;
-            if (G > 1) {
-                std::vector<uint32_t> one;
-                build(one, 1);
-                pk_grp.reserve(one.size() * G);
-                for (int g = 0; g < G; ++g) {
-                    const uint32_t off = (uint32_t)(g * region);
-                    for (size_t i = 0; i < one.size(); i += 4) {
-                        pk_grp.push_back(one[i] + off);
-                        pk_grp.push_back(one[i + 1] + off);
-                        pk_grp.push_back(one[i + 2] + (off << 5));
-                        pk_grp.push_back(one[i + 3] + (off << 5));
-                    }
-                }
-            }
-        }
+        pk_build_host(c, row_ptr, col_idx, c->pkD, c->pkR, c->pkT, c->pkS, lds_dev, &pkh);
+        c->pkGroups = pkh.groups;
+        c->pkRegion = pkh.region;
     }
     if (device < 0) {  // host-only handle: planning and queries, no decoding
         c->lds_limit = kHostOnlyLds;
@@ -673,18 +771,10 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
     hipError_t e10 = ldpc::dev_malloc((void **)&c->d_row_cls, sizeof(int32_t) * std::max<size_t>(row_cls.size(), 1));
     hipError_t e2 = ldpc::dev_malloc((void **)&c->d_vc_ptr, vc_ptr.size() * sizeof(int32_t));
     hipError_t e3 = ldpc::dev_malloc((void **)&c->d_vc_slot, vc_slot.size() * sizeof(uint32_t));
-    hipError_t e4 = hipSuccess, e5 = hipSuccess, e6 = hipSuccess;
+    hipError_t e4 = hipSuccess;
     if (!ell_reg.empty()) e4 = ldpc::dev_malloc((void **)&c->d_ell_reg, ell_reg.size() * sizeof(uint32_t));
-    if (!pk_idx.empty()) {
-        e5 = ldpc::dev_malloc((void **)&c->d_pk_idx, pk_idx.size() * sizeof(uint32_t));
-        e6 = ldpc::dev_malloc((void **)&c->d_pk_slot, pk_slot.size() * sizeof(uint32_t));
-        if (e5 == hipSuccess && !pk_idx16.empty())
-            e5 = ldpc::dev_malloc((void **)&c->d_pk_idx16, pk_idx16.size() * sizeof(uint32_t));
-        if (e5 == hipSuccess && !pk_grp.empty())
-            e5 = ldpc::dev_malloc((void **)&c->d_pk_grp, pk_grp.size() * sizeof(uint32_t));
-    }
-    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || e5 != hipSuccess ||
-        e6 != hipSuccess || e7 != hipSuccess || e8 != hipSuccess || e9 != hipSuccess || e10 != hipSuccess) {
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || e7 != hipSuccess ||
+        e8 != hipSuccess || e9 != hipSuccess || e10 != hipSuccess) {
         ldpc_code_destroy(c);
         (void)hipGetLastError();
         return fail(LDPC_ENOMEM, "device allocation failed");
@@ -699,17 +789,17 @@ ldpc_status ldpc_code_create(int32_t M, int32_t N, int64_t nnz, const int32_t *r
         hipMemcpy(c->d_row_cls, row_cls.data(), sizeof(int32_t) * row_cls.size(), hipMemcpyHostToDevice) !=
             hipSuccess ||
         (c->d_ell_reg && hipMemcpy(c->d_ell_reg, ell_reg.data(), ell_reg.size() * sizeof(uint32_t),
-                                   hipMemcpyHostToDevice) != hipSuccess) ||
-        (c->d_pk_idx && hipMemcpy(c->d_pk_idx, pk_idx.data(), pk_idx.size() * sizeof(uint32_t),
-                                  hipMemcpyHostToDevice) != hipSuccess) ||
-        (c->d_pk_idx16 && hipMemcpy(c->d_pk_idx16, pk_idx16.data(), pk_idx16.size() * sizeof(uint32_t),
-                                    hipMemcpyHostToDevice) != hipSuccess) ||
-        (c->d_pk_grp && hipMemcpy(c->d_pk_grp, pk_grp.data(), pk_grp.size() * sizeof(uint32_t),
-                                  hipMemcpyHostToDevice) != hipSuccess) ||
-        (c->d_pk_slot && hipMemcpy(c->d_pk_slot, pk_slot.data(), pk_slot.size() * sizeof(uint32_t),
                                    hipMemcpyHostToDevice) != hipSuccess)) {
         ldpc_code_destroy(c);
         return fail(LDPC_EDEVICE, "copy of the code to the device failed");
+    }
+    if (c->pkD > 0) {
+        const ldpc_status st = pk_upload(c, pkh);
+        if (st != LDPC_OK) {
+            const std::string msg = g_err;
+            ldpc_code_destroy(c);
+            return fail(st, msg);
+        }
     }
     *out = c;
     g_err.clear();

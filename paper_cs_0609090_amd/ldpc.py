@@ -40,7 +40,8 @@ EXPORTS = ("ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query",
            "ldpc_learn_backward", "ldpc_learn_backward_weighted",
            # include/ldpc_multi.h
            "ldpc_multi_workspace_size", "ldpc_decode_multi", "ldpc_autotune",
-           "ldpc_multi_persistent_workspace_size", "ldpc_decode_multi_persistent")
+           "ldpc_multi_persistent_workspace_size", "ldpc_decode_multi_persistent",
+           "ldpc_code_packed_shapes", "ldpc_code_set_packed_shape")
 LAYOUT_NAME = {v: k for k, v in LAYOUT.items()}
 KERNEL_NAME = {0: "generic_int", 1: "generic_f32", 2: "two_scan", 3: "reg1", 4: "packed",
                5: "f32_frames", 6: "two_scan_frames"}  # ldpc_kernel
@@ -139,6 +140,8 @@ def lib():
         L.ldpc_decode_multi_persistent.argtypes = [ctypes.POINTER(Job), i32, vp, sz, vp]
         L.ldpc_autotune.argtypes = [vp, i32, ctypes.POINTER(DecodeParams), ctypes.POINTER(i32),
                                     ctypes.POINTER(ctypes.c_float), ctypes.POINTER(i32)]
+        L.ldpc_code_packed_shapes.argtypes = [vp, ctypes.POINTER(i32), i32, ctypes.POINTER(i32)]
+        L.ldpc_code_set_packed_shape.argtypes = [vp, i32, i32, i32]
         for f in ("ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query",
                   "ldpc_decode_workspace_size", "ldpc_decode_plan", "ldpc_decode_batch",
                   "ldpc_decode_batch_noalloc", "ldpc_encoder_info",
@@ -146,7 +149,7 @@ def lib():
                   "ldpc_learn_classes", "ldpc_learn_workspace_size", "ldpc_learn_forward",
                   "ldpc_learn_backward", "ldpc_learn_backward_weighted", "ldpc_multi_workspace_size",
                   "ldpc_decode_multi", "ldpc_multi_persistent_workspace_size", "ldpc_decode_multi_persistent",
-                  "ldpc_autotune"):
+                  "ldpc_autotune", "ldpc_code_packed_shapes", "ldpc_code_set_packed_shape"):
             getattr(L, f).restype = ctypes.c_int
         L.ldpc_last_error.restype = ctypes.c_char_p
         L.ldpc_version.restype = ctypes.c_char_p
@@ -399,12 +402,26 @@ class Code:
         self._check_weights(params)
 
     def autotune(self, n_frames: int, params: DecodeParams) -> dict:
-        """Time every layout that can run these parameters and make AUTO use
-        the fastest from now on (ldpc_autotune)."""
+        """Time every layout that can run these parameters (and, for the packed
+        kernel, each of packed_shapes()) and make AUTO use the fastest from now
+        on (ldpc_autotune)."""
         lay, ms, tried = ctypes.c_int32(), ctypes.c_float(), ctypes.c_int32()
         _check(lib().ldpc_autotune(self._h, int(n_frames), ctypes.byref(params), ctypes.byref(lay),
                                    ctypes.byref(ms), ctypes.byref(tried)))
         return {"layout": LAYOUT_NAME[int(lay.value)], "ms": float(ms.value), "tried": int(tried.value)}
+
+    def packed_shapes(self) -> list[tuple[int, int, int]]:
+        """(slots per lane, rows per thread, threads) of the packed shapes that
+        autotune times, the handle's current one first (ldpc_code_packed_shapes)."""
+        n = ctypes.c_int32()
+        _check(lib().ldpc_code_packed_shapes(self._h, None, 0, ctypes.byref(n)))
+        buf = (ctypes.c_int32 * max(3 * n.value, 1))()
+        _check(lib().ldpc_code_packed_shapes(self._h, buf, n.value, ctypes.byref(n)))
+        return [(buf[3 * i], buf[3 * i + 1], buf[3 * i + 2]) for i in range(n.value)]
+
+    def set_packed_shape(self, slots: int, rows_per_thread: int, threads: int) -> None:
+        """Make one of packed_shapes() the handle's (ldpc_code_set_packed_shape)."""
+        _check(lib().ldpc_code_set_packed_shape(self._h, int(slots), int(rows_per_thread), int(threads)))
 
     def alloc_outputs(self, n_frames: int, device, with_llr: bool = True) -> dict:
         return {

@@ -623,3 +623,39 @@ def test_persistent_multi_host_checks(L):
     assert L.lib().ldpc_decode_multi_persistent(jobs, 3, None, 0, None) == L.LDPC_EINVAL
     for h in hs:
         L.lib().ldpc_code_destroy(h)
+
+
+@pytest.mark.parametrize("name,expect", [
+    ("peg1008", [(6, 2, 256), (6, 2, 1024)]),      # 256 threads (several frames per CU) or 1024
+    ("qc7493", [(11, 12, 512), (21, 4, 768)]),     # rows over a lane pair (two frames per CU) or one lane
+    ("ira16200", [(7, 8, 1024)]),
+    ("ira64800", [(7, 32, 1024)]),
+])
+def test_packed_shape_candidates(L, name, expect):
+    """The packed shapes autotuning times: the handle's own first, one per
+    (threads, lanes per row), each covering every row and every slot of the
+    longest row; host-only handles list them but cannot install one."""
+    code = {"peg1008": W.code_c0_peg1008, "qc7493": W.code_c1_qc7493, "ira16200": W.code_ira16200,
+            "ira64800": W.code_c2_ira64800}[name]()
+    gc = L.Code.from_parity_check(code, device=-1)
+    info = gc.info()
+    shapes = gc.packed_shapes()
+    assert shapes == expect
+    assert shapes[0] == (info["pk_slots"], info["pk_rows_per_thread"], info["pk_threads"])
+    D, M = int(code.row_degrees().max()), code.M
+    pairs = set()
+    for d, r, t in shapes:
+        lanes = 2 if d < D else 1
+        assert d * lanes >= D and r * (t // lanes) >= M
+        pairs.add((t, lanes))
+    assert len(pairs) == len(shapes)
+    # a short buffer gets the first triples only; the count is the full one
+    lib = L.lib()
+    buf, n = (ctypes.c_int32 * 3)(), ctypes.c_int32()
+    assert lib.ldpc_code_packed_shapes(gc._h, buf, 1, ctypes.byref(n)) == L.LDPC_OK
+    assert n.value == len(shapes) and tuple(buf) == shapes[0]
+    assert lib.ldpc_code_packed_shapes(gc._h, None, 1, ctypes.byref(n)) == L.LDPC_EINVAL
+    assert lib.ldpc_code_packed_shapes(None, None, 0, ctypes.byref(n)) == L.LDPC_EINVAL
+    assert lib.ldpc_code_set_packed_shape(gc._h, *shapes[-1]) == L.LDPC_EINVAL
+    assert b"host-only" in lib.ldpc_last_error()
+    gc.close()

@@ -176,6 +176,88 @@ def test_autotune_picks_a_feasible_layout(torch_dev, L, name, msg, sched):
     gc.close()
 
 
+@pytest.mark.parametrize("name", ["peg1008", "qc7493"])
+def test_every_packed_shape_gives_the_same_results(torch_dev, L, orc, name):
+    """Each packed shape autotuning may install (PEG: 256 or 1024 threads;
+    QC: rows over a lane pair in 512 threads, or on one lane in 768) decodes
+    6-bit int8, 7-bit int8 and 1-bit state on the REG layout exactly as the
+    handle's first shape does, and sampled frames equal the oracle."""
+    torch = torch_dev
+    code = {"qc7493": W.code_c1_qc7493, "peg1008": W.code_c0_peg1008}[name]()
+    F, T = 300, 20
+    gc = L.Code.from_parity_check(code)
+    shapes = gc.packed_shapes()
+    assert len(shapes) == 2
+    cases = [("int8", 6), ("int8", 7), ("1bit", 6)]
+    hosts = {}
+    for msg, bits in cases:
+        Q = (1 << (bits - 1)) - 1
+        eb = np.random.default_rng(bits).uniform(1.0, 3.0, size=F)
+        hosts[(msg, bits)] = W.quantize_llr(W.awgn_llr(code.N, F, eb, code.design_rate, key=(0xC5, bits)),
+                                            step=0.5 if bits == 6 else 0.25, qmax=Q)
+    first = {}
+    for shape in shapes + [shapes[0]]:  # and back to the first
+        gc.set_packed_shape(*shape)
+        info = gc.info()
+        assert (info["pk_slots"], info["pk_rows_per_thread"], info["pk_threads"]) == shape
+        assert gc.packed_shapes()[0] == shape
+        for msg, bits in cases:
+            for early_stop in (True, False):
+                print(f"[shape] {name} {shape} {msg} {bits}-bit early_stop={early_stop}", flush=True)
+                x = _dev(torch, hosts[(msg, bits)])
+                g = _np(gc.decode(x, max_iter=T, early_stop=early_stop, msg=msg, layout="reg",
+                                  llr_step=0.5 if bits == 6 else 0.25, msg_bits=bits))
+                key = (msg, bits, early_stop)
+                if key not in first:
+                    first[key] = g
+                    sel = np.array([0, 1, 77, F - 1])
+                    algo = "one_bit" if msg == "1bit" else "single_scan"
+                    r = orc.decode(code, hosts[(msg, bits)][sel], algo=algo, arith="int", max_iter=T, alpha=0.8,
+                                   early_stop=early_stop, step=0.5 if bits == 6 else 0.25, qbits=bits)
+                    for k, rk in (("iters", "iters"), ("ok", "ok"), ("hard", "hard"), ("llr", "post")):
+                        np.testing.assert_array_equal(g[k][sel], r[rk].astype(g[k].dtype),
+                                                      err_msg=f"{k} {key} {shape}")
+                else:
+                    for k in g:
+                        np.testing.assert_array_equal(g[k], first[key][k], err_msg=f"{k} {key} {shape}")
+    gc.close()
+
+
+@pytest.mark.parametrize("name", ["peg1008", "qc7493"])
+def test_autotune_times_packed_shapes(torch_dev, L, name):
+    """Autotuning int8 single-scan also times the other packed shape; the
+    handle ends on one of the listed shapes (its own unless REG won) and
+    decodes as before."""
+    torch = torch_dev
+    code = {"qc7493": W.code_c1_qc7493, "peg1008": W.code_c0_peg1008}[name]()
+    F = 256
+    x = _dev(torch, _host_llr(code, F, "int8", 301))
+    gc = L.Code.from_parity_check(code)
+    shapes = gc.packed_shapes()
+    before = _np(gc.decode(x, max_iter=20, msg="int8"))
+    p = L.make_params(max_iter=20, msg="int8")
+    n_layouts = sum(1 for lay in ("reg", "reg1", "lds", "hbm", "frames")
+                    if _feasible(L, gc, F, L.make_params(max_iter=20, msg="int8", layout=lay)))
+    r = gc.autotune(F, p)
+    assert r["tried"] == n_layouts + len(shapes) - 1, r
+    now = gc.packed_shapes()
+    assert sorted(now) == sorted(shapes)
+    if r["layout"] != "reg":
+        assert now[0] == shapes[0]
+    after = _np(gc.decode(x, max_iter=20, msg="int8"))
+    for k in before:
+        np.testing.assert_array_equal(after[k], before[k], err_msg=f"{k} {name} tuned={r} shape={now[0]}")
+    gc.close()
+
+
+def _feasible(L, gc, F, p):
+    try:
+        gc.workspace_size(F, p)
+        return True
+    except L.LdpcError:
+        return False
+
+
 def test_single_and_empty_calls(torch_dev, L, orc):
     """One active job runs on the caller's stream; no active job is a no-op."""
     torch = torch_dev
