@@ -41,6 +41,7 @@ struct ldpc_code {
     uint32_t pkRegion = 0;
     uint32_t *d_pk_grp = nullptr;
     uint32_t *d_pk_slot = nullptr;  // [N] posterior slot of each variable
+    uint32_t *d_pk_shift = nullptr;  // accumulator field shift of every edge (bytes), one set for all regions
     // frames-across-lanes binary32 path: CSR rows and, per edge, {variable,
     // position of the edge in variable-major order}
     int32_t *d_row_ptr = nullptr;

@@ -30,6 +30,8 @@ struct DevCode {
     const uint32_t *pk_idx;  // [pkR/2][pkD][T] x {zold_a, zold_b, acc_a, acc_b} LDS byte addresses for the packed
                              // kernel (or null); the set for 16-bit Z_old with 8-bit messages
     const uint32_t *pk_slot; // [N] posterior slot of each variable (packed kernel)
+    const uint32_t *pk_shift; // [pkR/2][ceil(ceil(pkD/2)/4)][T] x 4 words: the field shift of each record's
+                              // accumulator word, bytes (a, b) of slot 2i and then 2i+1 in word i
 };
 
 // Everything a decode kernel needs; passed by value in the kernel arguments.

@@ -421,14 +421,17 @@ hipError_t launch_check_input(const void *llr, int64_t count, int msg, int qmax,
 }  // namespace ldpc
 
 // Host arrays of the packed kernel for shape (Dk slots per lane, R rows per
-// thread, T threads, S lanes per row): the slot placement and the per-edge
+// thread, T threads, S lanes per row): the slot placement; the per-edge
 // records {zold_a, zold_b, acc_a, acc_b} of slot j of rows a = p*T/S + t/S,
 // b = (p + R/2)*T/S + t/S (lane t holds the row slots (t%S)*D + j): LDS byte
-// address of the saturated posterior and (LDS byte address of the
-// accumulator word << 5) | field shift; the set for int16 Z_old (7-8 bit
-// messages), and one set per LDS region of the persistent launch.
+// addresses of the saturated posterior and of the accumulator word; the set
+// for int16 Z_old (7-8 bit messages), and one set per LDS region of the
+// persistent launch; and the field shifts of the accumulator words, one byte
+// per edge, shared by every set: word i of row pair p holds slots 2i and
+// 2i + 1 (bytes: row a, row b, row a, row b), four words per 16-byte entry
+// [p][i / 4][t].
 struct PkHost {
-    std::vector<uint32_t> idx, idx16, grp, slot;
+    std::vector<uint32_t> idx, idx16, grp, slot, shift;
     int groups = 0;
     uint32_t region = 0;
 };
@@ -447,8 +450,7 @@ static void pk_build_host(const ldpc_code *c, const int32_t *row_ptr, const int3
     auto build = [&](std::vector<uint32_t> &rec, uint32_t zb) {
         const uint32_t zacc_off = (uint32_t)align_up(((size_t)c->dummy + 1) * zb, 16);
         auto acc_of_slot = [&](uint32_t sl) -> uint32_t {
-            const uint32_t w = sl / (uint32_t)Pk, fld = sl % (uint32_t)Pk;
-            return ((zacc_off + w * 4u) << 5) | (fld * (uint32_t)fbits);
+            return zacc_off + sl / (uint32_t)Pk * 4u;
         };
         rec.assign((size_t)RP * Dk * T * 4, 0u);
         for (int pp = 0; pp < RP; ++pp)
@@ -463,11 +465,25 @@ static void pk_build_host(const ldpc_code *c, const int32_t *row_ptr, const int3
                             r[2 + h] = acc_of_slot(sl);
                         } else {  // padding: shared Z_old, a private accumulator word per lane
                             r[h] = (uint32_t)c->dummy * zb;
-                            r[2 + h] = (zacc_off + (nwords + (uint32_t)(t & 63)) * 4u) << 5;
+                            r[2 + h] = zacc_off + (nwords + (uint32_t)(t & 63)) * 4u;
                         }
                     }
     };
     build(pk_idx, 1);
+    // field shifts (padding slots: 0, their words are private)
+    const int NQ = ((Dk + 1) / 2 + 3) / 4;
+    out->shift.assign((size_t)RP * NQ * T * 4, 0u);
+    for (int pp = 0; pp < RP; ++pp)
+        for (int j = 0; j < Dk; ++j)
+            for (int t = 0; t < T; ++t)
+                for (int h = 0; h < 2; ++h) {
+                    const int m = (pp + h * RP) * (T / S) + t / S, jr = (t % S) * Dk + j;
+                    if (m >= M || jr >= row_ptr[m + 1] - row_ptr[m]) continue;
+                    const uint32_t sl = pk_slot[col_idx[row_ptr[m] + jr]];
+                    const uint32_t sh = sl % (uint32_t)Pk * (uint32_t)fbits;
+                    const int i = j / 2;
+                    out->shift[(((size_t)pp * NQ + i / 4) * T + t) * 4 + i % 4] |= sh << (8 * (2 * (j % 2) + h));
+                }
     // 7-8 bit messages need accumulator fields of 16 bits or more
     if (Pk <= 2) build(pk_idx16, 2);
     // the persistent launch: 1024 / T frames per workgroup, each in its
@@ -488,8 +504,8 @@ static void pk_build_host(const ldpc_code *c, const int32_t *row_ptr, const int3
                 for (size_t i = 0; i < one.size(); i += 4) {
                     pk_grp.push_back(one[i] + off);
                     pk_grp.push_back(one[i + 1] + off);
-                    pk_grp.push_back(one[i + 2] + (off << 5));
-                    pk_grp.push_back(one[i + 3] + (off << 5));
+                    pk_grp.push_back(one[i + 2] + off);
+                    pk_grp.push_back(one[i + 3] + off);
                 }
             }
         }
@@ -500,26 +516,29 @@ static void pk_build_host(const ldpc_code *c, const int32_t *row_ptr, const int3
 // previous ones (freed) on success; on failure the handle keeps its arrays
 // and whatever was allocated here is freed.  The device is current.
 static ldpc_status pk_upload(ldpc_code *c, const PkHost &h) {
-    uint32_t *di = nullptr, *di16 = nullptr, *dg = nullptr, *ds = nullptr;
+    uint32_t *di = nullptr, *di16 = nullptr, *dg = nullptr, *ds = nullptr, *dh = nullptr;
     hipError_t e = ldpc::dev_malloc((void **)&di, h.idx.size() * sizeof(uint32_t));
     if (e == hipSuccess) e = ldpc::dev_malloc((void **)&ds, h.slot.size() * sizeof(uint32_t));
+    if (e == hipSuccess) e = ldpc::dev_malloc((void **)&dh, h.shift.size() * sizeof(uint32_t));
     if (e == hipSuccess && !h.idx16.empty()) e = ldpc::dev_malloc((void **)&di16, h.idx16.size() * sizeof(uint32_t));
     if (e == hipSuccess && !h.grp.empty()) e = ldpc::dev_malloc((void **)&dg, h.grp.size() * sizeof(uint32_t));
     const bool allocated = e == hipSuccess;
     if (allocated) e = hipMemcpy(di, h.idx.data(), h.idx.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ds, h.slot.data(), h.slot.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dh, h.shift.data(), h.shift.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess && di16)
         e = hipMemcpy(di16, h.idx16.data(), h.idx16.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess && dg) e = hipMemcpy(dg, h.grp.data(), h.grp.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-        for (uint32_t *q : {di, di16, dg, ds})
+        for (uint32_t *q : {di, di16, dg, ds, dh})
             if (q) (void)hipFree(q);
         (void)hipGetLastError();
         return allocated ? fail(LDPC_EDEVICE, "copy of the packed layout to the device failed")
                          : fail(LDPC_ENOMEM, "device allocation failed");
     }
-    for (uint32_t *q : {c->d_pk_idx, c->d_pk_idx16, c->d_pk_grp, c->d_pk_slot})
+    for (uint32_t *q : {c->d_pk_idx, c->d_pk_idx16, c->d_pk_grp, c->d_pk_slot, c->d_pk_shift})
         if (q) (void)hipFree(q);
+    c->d_pk_shift = dh;
     c->d_pk_idx = di;
     c->d_pk_idx16 = di16;
     c->d_pk_grp = dg;
@@ -827,6 +846,7 @@ ldpc_status ldpc_code_destroy(ldpc_code *code) {
     if (code->d_pk_idx16) (void)hipFree(code->d_pk_idx16);
     if (code->d_pk_grp) (void)hipFree(code->d_pk_grp);
     if (code->d_pk_slot) (void)hipFree(code->d_pk_slot);
+    if (code->d_pk_shift) (void)hipFree(code->d_pk_shift);
     delete code;
     return LDPC_OK;
 }
@@ -971,6 +991,7 @@ void fill_args(const ldpc_code *c, int32_t n_frames, const void *llr_in, const l
     a.c.ell_reg = c->d_ell_reg;
     a.c.pk_idx = qmax_of(p) > 63 ? c->d_pk_idx16 : c->d_pk_idx;  // int16 Z_old for 8-bit messages
     a.c.pk_slot = c->d_pk_slot;
+    a.c.pk_shift = c->d_pk_shift;
     a.n_frames = n_frames;
     a.max_iter = p->max_iter;
     a.early_stop = p->early_stop ? 1 : 0;

@@ -25,13 +25,20 @@
 // slot table maps variables to slots only at load and store time.
 //
 // Per-slot index record (host-built, 16 bytes, coalesced per wavefront):
-//   { s_a, s_b, acc_a, acc_b },  acc = (LDS byte address of the accumulator
-//   word << 5) | field shift.
-// The byte address/shift pair encodes any accumulator packing, so the kernel
-// needs no division by the field count; padding entries of short rows read
-// the dummy slot (Z_old at its maximum, never the row minimum) and add into a
-// private word per lane.  Z_old is stored as Z + 63 (bytes), messages as
-// L + 63: a stored Z_old byte has bit 6 clear exactly when Z_old <= 0.
+//   { s_a, s_b, acc_a, acc_b },  acc = LDS byte address of the accumulator
+//   word; and per row pair the field shifts of its accumulator words, one
+//   byte per edge (16 bytes per eight slots: one more load per row pair).
+// The byte address and shift encode any accumulator packing, so the kernel
+// needs no division by the field count; bytes 0, 2 and 3 of a shift word feed
+// the shifts of the deltas as operands with no extraction (byte 1 after one
+// shift right).  Against a combined record word ((address << 5) | shift),
+// which needs a shift right per atomic address, this removes two VALU
+// instructions per slot and row pair for one texture-addresser load per row
+// pair (measured faster on every workload shape).  Padding entries of short
+// rows read the dummy slot (Z_old at its maximum, never the row minimum) and
+// add into a private word per lane.
+// Z_old is stored as Z + 63 (bytes), messages as L + 63: a stored Z_old byte
+// has bit 6 clear exactly when Z_old <= 0.
 //
 // Early stop (FUSED, for callers that want hard decisions only): the gather
 // of iteration k already reads every Z^(k-1) byte, so the syndrome of the
@@ -216,6 +223,9 @@ __device__ __forceinline__ void pk_frame(const DecodeArgs &a, int f, bool live, 
     const int8_t *__restrict__ z0 = static_cast<const int8_t *>(a.llr_in) + (size_t)(live ? f : 0) * N;
     const __amdgpu_buffer_rsrc_t rec =
         __builtin_amdgcn_make_buffer_rsrc((void *)rec_p, (short)0, RP * D * kT * 16, kRsrcWord3);
+    constexpr int NQ = (W + 3) / 4;  // 16-byte shift entries per row pair
+    const __amdgpu_buffer_rsrc_t shr =
+        __builtin_amdgcn_make_buffer_rsrc((void *)a.c.pk_shift, (short)0, RP * NQ * kT * 16, kRsrcWord3);
     bool done = LOCK && !live;  // LOCK: this group has finished (or never had a frame)
     const int bitsP = (P == 1) ? 32 : (P == 2 ? 16 : 10);
     const int biasP = a.zbias;
@@ -328,10 +338,13 @@ __device__ __forceinline__ void pk_frame(const DecodeArgs &a, int f, bool live, 
             // scheduler interleaves them, which keeps the dependent packed ops
             // of one slot apart (the 21-slot shape lost most of its hazard
             // wait states this way: int8 12%, 1-bit 21% faster)
-            rec_t rc[D];
+            rec_t rc[D], shq[NQ];
 #pragma unroll
             for (int j = 0; j < D; ++j)
                 rc[j] = __builtin_amdgcn_raw_buffer_load_b128(rec, tid16, it0 + (uint32_t)((p * D + j) * kT * 16), 0);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+                shq[q] = __builtin_amdgcn_raw_buffer_load_b128(shr, tid16, it0 + (uint32_t)((p * NQ + q) * kT * 16), 0);
 
             uint32_t acc_a[D], acc_b[D], t2[D], lo2[D], mg2[D], h2[D];
             u16x2 min1 = {0xFFFF, 0xFFFF}, min2 = {0xFFFF, 0xFFFF};
@@ -448,6 +461,9 @@ __device__ __forceinline__ void pk_frame(const DecodeArgs &a, int f, bool live, 
                     // own sign +-1, then L_new + 63 in one multiply-add
                     const i16x2 sg = (as_i(t2[j]) >> (i16x2){15, 15}) | (i16x2){1, 1};
                     lb = as_i(mag) * sg + (i16x2){kB, kB};
+                    // one multiply-add: kept apart from the delta below, which the
+                    // compiler would otherwise fold into a multiply and two adds
+                    asm volatile("" : "+v"(lb));
                     if (ONEBIT) {  // keep the own-extrinsic sign and the minimum flag
                         const uint32_t sneg = bits(as_i(t2[j]) >> (i16x2){15, 15});
                         uint32_t &S = Sn[j >> 3];
@@ -466,8 +482,11 @@ __device__ __forceinline__ void pk_frame(const DecodeArgs &a, int f, bool live, 
                 const uint32_t d = bits(lb - as_i(lo2[j]));
                 const int da = (int)(d << 16) >> 16;
                 const int db = (int)d >> 16;
-                lds_add(acc_a[j] >> 5, (uint32_t)da << (acc_a[j] & 31u));
-                lds_add(acc_b[j] >> 5, (uint32_t)db << (acc_b[j] & 31u));
+                // word j / 2 holds slots j & ~1 and j | 1, bytes (row a, row b)
+                const uint32_t shw = shq[j >> 3][(j >> 1) & 3];
+                const uint32_t sha = (shw >> (16 * (j & 1))) & 0xFFu, shb = (shw >> (16 * (j & 1) + 8)) & 0xFFu;
+                lds_add(acc_a[j], (uint32_t)da << sha);
+                lds_add(acc_b[j], (uint32_t)db << shb);
             }
             if (ONEBIT) {
 #pragma unroll

@@ -231,7 +231,7 @@ def test_injected_allocation_failures(torch_dev, L, orc, monkeypatch):
     code = W.code_c0_peg1008()
     free0 = torch.cuda.mem_get_info()[0]
     first_ok = None
-    for k in range(1, 16):
+    for k in range(1, 25):
         monkeypatch.setenv("LDPC_FAIL_ALLOC", str(k))
         try:
             gc = L.Code.from_parity_check(code)
