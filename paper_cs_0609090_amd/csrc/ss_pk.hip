@@ -168,6 +168,48 @@ __device__ __forceinline__ void refresh3(const uint32_t *zacc, uint8_t *zold, in
     }
 }
 
+// Z_old from the accumulator words with one or two fields per word (PF = 1:
+// the word is Z itself; PF = 2: 16-bit fields biased by 32768, i.e. offset
+// binary, so flipping each half's top bit gives Z as an int16): four
+// variables per step, one 16- or 8-byte LDS read, the clamp to +-ZMAX in
+// packed 16-bit halves, and one 4-byte write (8 bytes for the 16-bit Z_old
+// of 8-bit messages).  Words past the last one are private padding words
+// (read, never used); slots >= N (unused, the dummy) are left untouched.
+template <int QB, int PF, int T>
+__device__ __forceinline__ void refresh12(const uint32_t *zacc, uint8_t *zold, int N, int nwords, int tid) {
+    using Wd = Width<QB>;
+    const int ngroups = (nwords * PF + 3) / 4;
+    const i16x2 lo = {(short)-Wd::ZMAX, (short)-Wd::ZMAX}, hi = {(short)Wd::ZMAX, (short)Wd::ZMAX};
+    const i16x2 zb = {(short)Wd::ZB, (short)Wd::ZB};
+    for (int g = tid; g < ngroups; g += T) {
+        const int n0 = g * 4;
+        uint32_t h[2];  // variables n0, n0+1 and n0+2, n0+3 as Z_old + ZB in 16-bit halves
+        if (PF == 1) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(zacc + n0);
+            // |Z| stays far below 2^15 (the sums are bounded by the field
+            // design), so the low halves of the words are Z exactly
+            h[0] = __builtin_amdgcn_perm(v.y, v.x, 0x05040100u);
+            h[1] = __builtin_amdgcn_perm(v.w, v.z, 0x05040100u);
+        } else {
+            const uint2 v = *reinterpret_cast<const uint2 *>(zacc + n0 / 2);
+            h[0] = v.x ^ 0x80008000u;
+            h[1] = v.y ^ 0x80008000u;
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+            h[k] = bits(__builtin_elementwise_min(__builtin_elementwise_max(as_i(h[k]), lo), hi) + zb);
+        if (n0 + 4 <= N) {
+            if (Wd::Z16)
+                *reinterpret_cast<uint2 *>(zold + 2 * (size_t)n0) = make_uint2(h[0], h[1]);
+            else
+                *reinterpret_cast<uint32_t *>(zold + n0) = __builtin_amdgcn_perm(h[1], h[0], 0x06040200u);
+        } else {
+            for (int k = 0; k < 4 && n0 + k < N; ++k)
+                zold_put<QB>(zold, n0 + k, (int)(short)(h[k >> 1] >> (16 * (k & 1))));
+        }
+    }
+}
+
 // Shapes of 1024 threads with at most 8 rows per thread and 7 slots ask for
 // 8 waves per SIMD (at most 64 VGPRs): with the small LDS of such codes two
 // frames then share a CU, and one frame's barriers hide behind the other's
@@ -535,6 +577,10 @@ __device__ __forceinline__ void pk_frame(const DecodeArgs &a, int f, bool live, 
                 refresh3<319, kT>(zacc, zold, N, nwords, tid);
             else
                 refresh3<575, kT>(zacc, zold, N, nwords, tid);
+        } else if (P == 1) {
+            refresh12<QB, 1, kT>(zacc, zold, N, nwords, tid);
+        } else if (P == 2) {
+            refresh12<QB, 2, kT>(zacc, zold, N, nwords, tid);
         } else {
             for (int w = tid; w < nwords; w += kT) {
                 const uint32_t v = zacc[w];
