@@ -352,6 +352,16 @@ __device__ __forceinline__ void pk_frame(const DecodeArgs &a, int f, bool live, 
     uint32_t kSelBase = 0x0c040c00u;
     asm volatile("" : "+v"(kSelBase));
     using rec_t = decltype(__builtin_amdgcn_raw_buffer_load_b128(rec, 0u, 0u, 0));
+    // one row pair per thread: its records are the same every iteration, so
+    // they are loaded once and stay in registers
+    constexpr bool KEEP = RP == 1 && !LOCK;
+    rec_t rk[KEEP ? D : 1], sk[KEEP ? NQ : 1];
+    if constexpr (KEEP) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) rk[j] = __builtin_amdgcn_raw_buffer_load_b128(rec, tid16, (uint32_t)(j * kT * 16), 0);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) sk[q] = __builtin_amdgcn_raw_buffer_load_b128(shr, tid16, (uint32_t)(q * kT * 16), 0);
+    }
     int iters = 0;
     bool converged = false;  // the decision of the last completed iteration is a codeword
     bool conv_prev = false;  // FUSED: that of the iteration before the last one is
@@ -383,10 +393,14 @@ __device__ __forceinline__ void pk_frame(const DecodeArgs &a, int f, bool live, 
             rec_t rc[D], shq[NQ];
 #pragma unroll
             for (int j = 0; j < D; ++j)
-                rc[j] = __builtin_amdgcn_raw_buffer_load_b128(rec, tid16, it0 + (uint32_t)((p * D + j) * kT * 16), 0);
+                rc[j] = KEEP ? rk[j]
+                             : __builtin_amdgcn_raw_buffer_load_b128(rec, tid16,
+                                                                     it0 + (uint32_t)((p * D + j) * kT * 16), 0);
 #pragma unroll
             for (int q = 0; q < NQ; ++q)
-                shq[q] = __builtin_amdgcn_raw_buffer_load_b128(shr, tid16, it0 + (uint32_t)((p * NQ + q) * kT * 16), 0);
+                shq[q] = KEEP ? sk[q]
+                              : __builtin_amdgcn_raw_buffer_load_b128(shr, tid16,
+                                                                      it0 + (uint32_t)((p * NQ + q) * kT * 16), 0);
 
             uint32_t acc_a[D], acc_b[D], t2[D], lo2[D], mg2[D], h2[D];
             u16x2 min1 = {0xFFFF, 0xFFFF}, min2 = {0xFFFF, 0xFFFF};
