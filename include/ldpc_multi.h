@@ -37,10 +37,13 @@ ldpc_status ldpc_multi_workspace_size(const ldpc_job *jobs, int32_t n_jobs, size
 
 /*
  * Decode every job (all codes on one device).  Results equal n_jobs separate
- * ldpc_decode_batch calls.  Jobs are spread over up to 4 library streams,
- * the longest (frames x edges x max_iter) first; with one job, the caller's
- * stream is used directly.  Errors as ldpc_decode_batch, checked for every
- * job before anything is launched.
+ * ldpc_decode_batch calls.  The job whose workgroups each take the most LDS,
+ * if that is more than half of a CU's (one frame per CU: its workgroups can
+ * only start on empty CUs), is launched first on the caller's stream; the
+ * others are spread over up to 4 library streams, the longest (frames x
+ * edges x max_iter) first; with one job, the caller's stream is used
+ * directly.  Errors as ldpc_decode_batch, checked for every job before
+ * anything is launched.
  */
 ldpc_status ldpc_decode_multi(const ldpc_job *jobs, int32_t n_jobs, void *workspace, size_t workspace_bytes,
                               void *stream);
