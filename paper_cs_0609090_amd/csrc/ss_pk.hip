@@ -12,8 +12,8 @@
 //     parity ^= t2                          (sign bits 15 and 31)
 //   per pair of rows: A2, B2 = normalised min1/min2;
 //     mag2 = max(A2, B2 + 64 min1 - 64 |t2|)   (one multiply-add, one max;
-//            rows of up to 8 slots), or a bit-select of A2 / B2 on the mask
-//            (min1 - |t2|) >> 15 (wider rows and the 1-bit state)
+//            int8 messages of 6-7 bits), or a bit-select of A2 / B2 on the
+//            mask (min1 - |t2|) >> 15 (the 1-bit state, 8-bit messages)
 //   i.e. B where |t_j| equals the row minimum and A elsewhere: no argmin is
 //   needed, since a tie at the minimum forces min2 = min1 and so A = B.
 //     L2   = mag2 * (+-1: own sign XOR row parity) + 63, delta2 = L2 - Lold2
@@ -250,11 +250,12 @@ __device__ __forceinline__ void pk_frame(const DecodeArgs &a, int f, bool live, 
     constexpr int RP = R / 2;        // row pairs per thread
     constexpr int W = (D + 1) / 2;   // registers per row pair: two slots (4 bytes) each
     constexpr int NS = (D + 7) / 8;  // 1-bit state registers per row pair: eight slots each
-    // B-or-A choice per slot: a mask and a bit-select (the 1-bit state keeps
-    // the mask; measured faster for rows wider than 8 slots; 8-bit messages,
-    // where B can reach 127), else one multiply-add and a max (fewer
-    // instructions, faster for short rows)
-    constexpr bool kMaskSelect = ONEBIT || D > 8 || QB == 8;
+    // B-or-A choice per slot: a mask and a bit-select (the 1-bit state, which
+    // keeps the mask as its minimum flag; 8-bit messages, where B can reach
+    // 127), else one multiply-add and a max, one instruction fewer per slot
+    // pair with the sign (measured 2% faster on the QC code's 11-slot lane
+    // pairs as well as on short rows)
+    constexpr bool kMaskSelect = ONEBIT || QB == 8;
     const int N = a.c.N;
     const int P = a.zpack;
     const uint32_t dummy = (uint32_t)a.c.dummy;
@@ -496,7 +497,8 @@ __device__ __forceinline__ void pk_frame(const DecodeArgs &a, int f, bool live, 
                 // |t_j| equals min1 at the minimum (and at a tie, where A = B)
                 // and is at least min1 + 1 elsewhere, where B - 64 (|t_j| - min1)
                 // < 0 <= A: so max(A, Cs - 64 |t_j|) with Cs = B + 64 min1 is B
-                // at the minimum and A elsewhere (|t_j| <= 93: no overflow)
+                // at the minimum and A elsewhere (|t_j| <= 93, 189 with 7-bit
+                // messages: within 16 bits)
                 A2 = bits(Am);
                 Cs = bits(min1 * as_u(k64) + as_u(bits(Bm)));
                 mn1 = bits(ps);  // the row parity as a mask per half
