@@ -105,6 +105,19 @@ def test_mixed_codes_and_paths(torch_dev, L, orc, early_stop):
         assert len(set(got[0]["iters"].tolist())) > 3
 
 
+def test_mixed_whole_cu_jobs_lead(torch_dev, L, orc):
+    """Two jobs whose workgroups each take a whole CU's LDS (N=64800, int8
+    and 1-bit): the larger-LDS one is launched first on the caller's stream,
+    the other forked with the rest; every job equals its separate call and
+    sampled frames the oracle."""
+    ira = W.code_c2_ira64800()
+    spec = [(W.code_c0_peg1008(), 200, "int8", "single_scan", "auto"),
+            (ira, 24, "int8", "single_scan", "auto"),
+            (ira, 16, "1bit", "single_scan", "auto"),
+            (W.code_ira16200(), 40, "int8", "single_scan", "auto")]
+    _check_jobs(torch_dev, L, orc, spec, max_iter=12, early_stop=True, samples=3)
+
+
 def test_mixed_full_workload_sampled(torch_dev, L, orc):
     """The full mixed workload (8192 x PEG1008, 2048 x QC7493, 256 x IRA16200,
     128 x IRA64800; int8; 50 iterations; early stop), in the launch
@@ -196,6 +209,10 @@ def test_every_packed_shape_gives_the_same_results(torch_dev, L, orc, name):
         hosts[(msg, bits)] = W.quantize_llr(W.awgn_llr(code.N, F, eb, code.design_rate, key=(0xC5, bits)),
                                             step=0.5 if bits == 6 else 0.25, qmax=Q)
     first = {}
+    with pytest.raises(L.LdpcError) as ei:  # not one of the listed shapes
+        gc.set_packed_shape(99, 2, 256)
+    assert ei.value.status == L.LDPC_EUNSUPPORTED
+    assert gc.packed_shapes() == shapes
     for shape in shapes + [shapes[0]]:  # and back to the first
         gc.set_packed_shape(*shape)
         info = gc.info()
