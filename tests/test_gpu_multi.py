@@ -193,7 +193,7 @@ def test_autotune_picks_a_feasible_layout(torch_dev, L, name, msg, sched):
 def test_every_packed_shape_gives_the_same_results(torch_dev, L, orc, name):
     """Each packed shape autotuning may install (PEG: 256 or 1024 threads;
     QC: rows over a lane pair in 512 threads, or on one lane in 768) decodes
-    6-bit int8, 7-bit int8 and 1-bit state on the REG layout exactly as the
+    6-, 7- and 8-bit int8 and the 1-bit state on the REG layout exactly as the
     handle's first shape does, and sampled frames equal the oracle."""
     torch = torch_dev
     code = {"qc7493": W.code_c1_qc7493, "peg1008": W.code_c0_peg1008}[name]()
@@ -201,7 +201,7 @@ def test_every_packed_shape_gives_the_same_results(torch_dev, L, orc, name):
     gc = L.Code.from_parity_check(code)
     shapes = gc.packed_shapes()
     assert len(shapes) == 2
-    cases = [("int8", 6), ("int8", 7), ("1bit", 6)]
+    cases = [("int8", 6), ("int8", 7), ("int8", 8), ("1bit", 6)]
     hosts = {}
     for msg, bits in cases:
         Q = (1 << (bits - 1)) - 1

@@ -342,6 +342,34 @@ def test_edge_cases(torch_dev, L, orc):
     gc.close()
 
 
+@pytest.mark.parametrize("variant", VARIANTS, ids=lambda v: f"{v[0]}-{v[1]}")
+def test_maximum_row_degree(torch_dev, L, orc, variant):
+    """Rows of the largest accepted degree (64) beside short ones, through
+    the layout AUTO picks and against the oracle, with and without early
+    stop."""
+    code = W.random_small_code(24, 150, (58, 64), seed=64)
+    if int(code.row_degrees().max()) < 64:  # make one row exactly 64 long
+        rows = [code.col_idx[code.row_ptr[m]:code.row_ptr[m + 1]] for m in range(code.M)]
+        rest = np.setdiff1d(np.arange(code.N), rows[0])
+        rows[0] = np.concatenate([rows[0], rest[:64 - len(rows[0])]])
+        code = W.ParityCheck.from_rows(code.M, code.N, rows, "rowdeg64")
+    assert int(code.row_degrees().max()) == 64
+    rng = np.random.default_rng(64)
+    F = 5
+    if variant[0] == "fp32":
+        x = rng.normal(1.5, 2.0, size=(F, code.N)).astype(np.float32)
+    else:
+        x = rng.integers(-31, 32, size=(F, code.N)).astype(np.int8)
+    layouts = ["auto"]
+    if variant[:2] in (("fp32", "single_scan"), ("int8", "two_scan"), ("fp32", "two_scan")):
+        layouts.append("frames")  # the 64-slot instantiation of the frames-across-lanes kernels
+    if variant[1] == "single_scan" and variant[0] != "fp32":
+        layouts.append("hbm")
+    for lay in layouts:
+        for es in (True, False):
+            _run_pair(torch_dev, L, orc, code, x, variant, max_iter=8, alpha=0.8, early_stop=es, layout=lay)
+
+
 def test_workspace_too_small_rejected(torch_dev, L):
     torch = torch_dev
     code = W.code_c2_ira64800()
