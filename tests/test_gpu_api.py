@@ -268,3 +268,43 @@ def test_injected_allocation_failures(torch_dev, L, orc, monkeypatch):
     monkeypatch.delenv("LDPC_FAIL_ALLOC")
     assert gc.autotune(16, L.make_params(msg="int8", max_iter=5))["tried"] >= 2
     gc.close()
+
+
+@pytest.mark.parametrize("msg,layout", [("int8", "auto"), ("1bit", "auto"), ("fp32", "frames")])
+def test_noalloc_call_captured_in_a_graph(torch_dev, L, msg, layout):
+    """The allocation-free call is meant for code under graph capture: one
+    ldpc_decode_batch_noalloc captured into a HIP graph, replayed three times
+    with new inputs copied in and eager work on the same stream between the
+    replays, equals the eager call on the same inputs every time (the
+    binary32 frames-across-lanes plan uses the library's static scratch)."""
+    torch = torch_dev
+    code = W.code_ira16200()
+    F = 96
+    gc = L.Code.from_parity_check(code)
+    p = L.make_params(max_iter=15, msg=msg, layout=layout, early_stop=True)
+    def inputs(seed):
+        x = W.awgn_llr(code.N, F, 2.0 + 0.2 * seed, code.design_rate, key=(0x6A, seed))
+        return torch.from_numpy(x if msg == "fp32" else W.quantize_llr(x)).cuda()
+    xin = inputs(0)
+    out = gc.alloc_outputs(F, xin.device)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):  # a first eager call before the capture
+        gc.decode_noalloc_into(xin, p, out["hard"], out["llr"], out["iters"], out["ok"])
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        gc.decode_noalloc_into(xin, p, out["hard"], out["llr"], out["iters"], out["ok"])
+    for rep in range(3):
+        x = inputs(rep + 1)
+        xin.copy_(x)
+        _ = (x.float() * 2).sum()  # eager work between the replays
+        g.replay()
+        torch.cuda.synchronize()
+        got = {k: v.clone() for k, v in out.items() if v is not None}
+        ref = gc.decode(x, max_iter=15, msg=msg, layout=layout, early_stop=True)
+        torch.cuda.synchronize()
+        for k in got:
+            assert torch.equal(got[k], ref[k]), f"replay {rep} {k}"
+    gc.close()
