@@ -363,6 +363,16 @@ __device__ __forceinline__ void pk_frame(const DecodeArgs &a, int f, bool live, 
 #pragma unroll
         for (int q = 0; q < NQ; ++q) sk[q] = __builtin_amdgcn_raw_buffer_load_b128(shr, tid16, (uint32_t)(q * kT * 16), 0);
     }
+    // several row pairs per thread: the first pair's records of the next
+    // iteration are loaded before the barriers and the refresh, which then
+    // hide their latency (not in the 64-register shapes, where the registers
+    // would spill)
+    constexpr bool PRE = !KEEP && !LOCK && pk_waves_per_eu<D, R, T>() < 8;
+    rec_t r0[PRE ? D : 1];
+    if constexpr (PRE) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) r0[j] = __builtin_amdgcn_raw_buffer_load_b128(rec, tid16, (uint32_t)(j * kT * 16), 0);
+    }
     int iters = 0;
     bool converged = false;  // the decision of the last completed iteration is a codeword
     bool conv_prev = false;  // FUSED: that of the iteration before the last one is
@@ -394,9 +404,10 @@ __device__ __forceinline__ void pk_frame(const DecodeArgs &a, int f, bool live, 
             rec_t rc[D], shq[NQ];
 #pragma unroll
             for (int j = 0; j < D; ++j)
-                rc[j] = KEEP ? rk[j]
-                             : __builtin_amdgcn_raw_buffer_load_b128(rec, tid16,
-                                                                     it0 + (uint32_t)((p * D + j) * kT * 16), 0);
+                rc[j] = KEEP                ? rk[j]
+                        : (PRE && p == 0) ? r0[j]
+                                          : __builtin_amdgcn_raw_buffer_load_b128(
+                                                rec, tid16, it0 + (uint32_t)((p * D + j) * kT * 16), 0);
 #pragma unroll
             for (int q = 0; q < NQ; ++q)
                 shq[q] = KEEP ? sk[q]
@@ -565,6 +576,11 @@ __device__ __forceinline__ void pk_frame(const DecodeArgs &a, int f, bool live, 
                     asm volatile("" : "+v"(Lw[p][i]));
                 }
             }
+        }
+        if constexpr (PRE) {
+#pragma unroll
+            for (int j = 0; j < D; ++j)
+                r0[j] = __builtin_amdgcn_raw_buffer_load_b128(rec, tid16, it0 + (uint32_t)(j * kT * 16), 0);
         }
         if (FUSED && it >= 2 && (zodd & Wd::HMASK)) flag[1 + (it & 1)] = 1;
         __syncthreads();
