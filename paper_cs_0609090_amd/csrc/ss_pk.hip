@@ -6,8 +6,11 @@
 //
 //   thread t of T owns the rows a = p*T + t and b = (p + R/2)*T + t for
 //   p < R/2; for every slot j the pair (row a, row b) is one 16-bit lane pair:
-//     t2   = Zold2 - Lold2                  (v_pk_sub_i16; both stored +63)
-//     m2   = |t2|
+//     t2   = Zold2 - Lold2                  (both stored +63: v_pk_add_f16
+//            on the stored integers read as binary16 subnormals, which is
+//            exact and gives sign and magnitude; v_pk_sub_i16 for the
+//            16-bit Z_old of 8-bit messages)
+//     m2   = |t2|                           (one mask of the sign bits)
 //     min2 = min(min2, max(min1, m2)), min1 = min(min1, m2)   (v_pk_*_u16)
 //     parity ^= t2                          (sign bits 15 and 31)
 //   per pair of rows: A2, B2 = normalised min1/min2;
@@ -78,6 +81,7 @@ struct Width {
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 typedef short i16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 
 // LDS accessed by absolute byte address (the kernel declares only dynamic LDS,
 // which starts at address 0): per-edge addresses need no base add.
@@ -454,10 +458,24 @@ __device__ __forceinline__ void pk_frame(const DecodeArgs &a, int f, bool live, 
                     l2 = pair_of(Lw[p][j >> 1], j & 1);
                 }
                 lo2[j] = l2;
-                const i16x2 t = as_i(z2) - as_i(l2);  // Z_old - L_old per row
-                t2[j] = bits(t);
-                const u16x2 mag = as_u(bits(__builtin_elementwise_max(t, -t)));
-                mg2[j] = bits(mag);
+                // Z_old - L_old per row, and its magnitude
+                uint32_t tb, mb;
+                if constexpr (!Wd::Z16) {
+                    // both stored values are non-negative integers below 1024,
+                    // which are binary16 subnormals with the same bits: their
+                    // binary16 difference is exact and in sign-magnitude form,
+                    // so the magnitude is one mask (the sign bits 15 and 31 are
+                    // those of the integer difference, +0 for a zero one)
+                    tb = __builtin_bit_cast(uint32_t, __builtin_bit_cast(f16x2, z2) - __builtin_bit_cast(f16x2, l2));
+                    mb = tb & 0x7FFF7FFFu;
+                } else {
+                    const i16x2 t = as_i(z2) - as_i(l2);
+                    tb = bits(t);
+                    mb = bits(__builtin_elementwise_max(t, -t));
+                }
+                t2[j] = tb;
+                const u16x2 mag = as_u(mb);
+                mg2[j] = mb;
                 min2 = __builtin_elementwise_min(min2, __builtin_elementwise_max(min1, mag));
                 min1 = __builtin_elementwise_min(min1, mag);
             }
