@@ -530,7 +530,8 @@ __device__ __forceinline__ void pk_frame(const DecodeArgs &a, int f, bool live, 
                 // messages: within 16 bits)
                 A2 = bits(Am);
                 Cs = bits(min1 * as_u(k64) + as_u(bits(Bm)));
-                mn1 = bits(ps);  // the row parity as a mask per half
+                // +-1.0 in binary16 per half, negative for an odd row parity
+                mn1 = (par & 0x80008000u) | 0x3C003C00u;
                 asm volatile("" : "+v"(A2), "+v"(Cs), "+v"(mn1));
             }
             uint32_t nl[D];
@@ -560,10 +561,15 @@ __device__ __forceinline__ void pk_frame(const DecodeArgs &a, int f, bool live, 
                 } else {
                     const i16x2 mag =
                         __builtin_elementwise_max(as_i(mg2[j]) * as_i(kn64) + as_i(Cs), as_i(A2));
-                    // sign +-1 per half: own extrinsic's sign XOR the row parity
-                    const uint32_t sg = __builtin_amdgcn_bitop3_b32(
-                        bits(as_i(t2[j]) >> (i16x2){15, 15}), mn1, 0x00010001u, 0xBE);  // (a ^ b) | c
-                    lb = mag * as_i(sg) + (i16x2){kB, kB};
+                    // sign +-1.0 per half: own extrinsic's sign (bit 15 of the
+                    // sign-magnitude t) XOR the row parity; then L + ZB as one
+                    // binary16 multiply-add on subnormals (|L| <= Q < ZB:
+                    // exact, and the bits of the result are the integer)
+                    const uint32_t sg = (t2[j] & 0x80008000u) ^ mn1;
+                    lb = as_i(__builtin_bit_cast(
+                        uint32_t, __builtin_elementwise_fma(__builtin_bit_cast(f16x2, bits(mag)),
+                                                            __builtin_bit_cast(f16x2, sg),
+                                                            __builtin_bit_cast(f16x2, Wd::ZB2))));
                 }
                 nl[j] = bits(lb);
                 const uint32_t d = bits(lb - as_i(lo2[j]));
