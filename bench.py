@@ -64,10 +64,10 @@ KERNELS = {
 # path's kernels), keyed by the hash of the kernel sources the counters were
 # taken on; any other source reports traffic as null.
 MEASURED_TRAFFIC = [
-    {"kernel": "packed", "hash": "e6a50da1e9a2ffce", "workload": ("int8", "single_scan", 512, 50),
-     "bytes": 240.8e6, "profile": "profiles/ss_pk_int8_ira64800_512f.md"},
-    {"kernel": "packed", "hash": "e6a50da1e9a2ffce", "workload": ("1bit", "single_scan", 512, 50),
-     "bytes": 240.7e6, "profile": "profiles/ss_pk_1bit_ira64800_512f.md"},
+    {"kernel": "packed", "hash": "b02a9fc1700f7c6d", "workload": ("int8", "single_scan", 512, 50),
+     "bytes": 240.7e6, "profile": "profiles/ss_pk_int8_ira64800_512f.md"},
+    {"kernel": "packed", "hash": "b02a9fc1700f7c6d", "workload": ("1bit", "single_scan", 512, 50),
+     "bytes": 240.6e6, "profile": "profiles/ss_pk_1bit_ira64800_512f.md"},
     {"kernel": "f32_frames", "hash": "1c5cdaa9c2275be3", "workload": ("fp32", "single_scan", 512, 50),
      "bytes": 105147.1e6, "profile": "profiles/fl_f32_ira64800_512f.md"},
     {"kernel": "reg1", "hash": "e7d86239f37f995e", "workload": ("int8", "single_scan", 512, 50),

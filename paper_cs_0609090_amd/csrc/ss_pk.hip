@@ -20,7 +20,11 @@
 //   i.e. B where |t_j| equals the row minimum and A elsewhere: no argmin is
 //   needed, since a tie at the minimum forces min2 = min1 and so A = B.
 //     L2   = mag2 * (+-1: own sign XOR row parity) + 63, delta2 = L2 - Lold2
+//            (6-7 bit int8 messages: a binary16 multiply-add on subnormals)
 //   and one LDS atomic per edge adds the delta into the posterior field.
+// The binary16 forms rely on subnormals being kept, the default binary16
+// denormal mode of a kernel (the build passes no fast-math flag); the
+// bit-exact parity tests would fail at once if they were flushed.
 //
 // Variables live in LDS "slots" chosen at code creation: slot s holds Z_old
 // in byte s and the accumulator in field s%P of word s/P, and the placement
